@@ -1,0 +1,305 @@
+"""Plain FP64 CPU oracle of the compact fourth-order doubly conservative AF
+method with monolithic convex limiting (arXiv 2510.11527).
+
+TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` use it.  The GPU library never imports it
+and shares no code with it.
+
+The arithmetic lives in ``af_oracle.c`` (plain C, FP64, no fast-math, no
+FMA contraction); this module only marshals numpy arrays through ctypes.
+
+A problem is described by a plain dict (see
+``paper_2510_11527_amd.workloads``)::
+
+    {"dim": 2, "n": [nx, ny], "lo": [..], "hi": [..],
+     "flux": [("quad", 0.5), ("quad", 0.5)],      # per axis: kind, params
+     "diff": ("deadzone", eps, u0),                  # kind, params
+     "umin": 0.0, "umax": 1.0, "limiter": True,
+     "si": False, "si_gamma": 1.0, "cfl": 0.075}
+
+DoFs are a list of 2^d numpy float64 arrays in the zeta order of Sec. 4
+(average first), each of prod(n) values with x fastest.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "af_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+FLUX_KINDS = {"linear": 0, "quad": 1, "bl": 2, "bl_grav": 3}
+DIFF_KINDS = {"linear": 0, "power": 1, "deadzone": 2, "bl": 3, "ramp2": 4}
+THETA_MODES = {"computed": 0, "one": 1, "zero": 2}
+
+
+class OrcProblem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("n", ctypes.c_int * 3),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("fkind", ctypes.c_int * 3),
+        ("fpar", (ctypes.c_double * 2) * 3),
+        ("akind", ctypes.c_int),
+        ("apar", ctypes.c_double * 3),
+        ("umin", ctypes.c_double),
+        ("umax", ctypes.c_double),
+        ("limiter", ctypes.c_int),
+        ("si", ctypes.c_int),
+        ("si_gamma", ctypes.c_double),
+        ("theta_mode", ctypes.c_int),
+        ("dx", ctypes.c_double * 3),
+        ("kappa_max", ctypes.c_double),
+        ("ncrit", ctypes.c_int * 3),
+        ("crit", (ctypes.c_double * 16) * 3),
+    ]
+
+
+class OrcDiag(ctypes.Structure):
+    _fields_ = [
+        ("uL_out_of_bounds", ctypes.c_longlong),
+        ("n_theta", ctypes.c_longlong),
+        ("n_theta_lt1", ctypes.c_longlong),
+        ("max_avg_clamp", ctypes.c_double),
+        ("max_pv_clamp", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def build(force=False):
+    """Compile af_oracle.c into liborc.so (gcc, FP64, no contraction)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
+           "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        pp = ctypes.POINTER(dp)
+        PP = ctypes.POINTER(OrcProblem)
+        DG = ctypes.POINTER(OrcDiag)
+        L.orc_setup.argtypes = [PP]
+        L.orc_setup.restype = ctypes.c_int
+        L.orc_rhs.argtypes = [PP, pp, pp]
+        L.orc_rhs_cells.argtypes = [PP, pp, ctypes.POINTER(ctypes.c_long), ctypes.c_long, dp]
+        L.orc_fe.argtypes = [PP, pp, ctypes.c_double, pp, DG]
+        L.orc_fe_cells.argtypes = [PP, pp, ctypes.c_double, ctypes.POINTER(ctypes.c_long), ctypes.c_long, dp, DG]
+        L.orc_ssprk3_step.argtypes = [PP, pp, ctypes.c_double, pp, pp, DG]
+        L.orc_dt.argtypes = [PP, pp, ctypes.c_double]
+        L.orc_dt.restype = ctypes.c_double
+        L.orc_limiter_probe.argtypes = [PP, pp, ctypes.c_double, ctypes.c_int, ctypes.c_long, dp]
+        L.orc_eval.argtypes = [PP, ctypes.c_int, dp, ctypes.c_long, dp, dp, dp, dp]
+        L.orc_alpha_L.argtypes = [PP, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.orc_alpha_L.restype = ctypes.c_double
+        L.orc_halfgrid.argtypes = [PP, pp, dp]
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_sizeof_problem.restype = ctypes.c_int
+        L.orc_sizeof_diag.restype = ctypes.c_int
+        assert L.orc_sizeof_problem() == ctypes.sizeof(OrcProblem)
+        assert L.orc_sizeof_diag() == ctypes.sizeof(OrcDiag)
+        _lib = L
+    return _lib
+
+
+def num_threads():
+    return lib().orc_num_threads()
+
+
+def problem(spec, theta_mode="computed"):
+    """Build and set up an orc_problem from a problem dict."""
+    d = int(spec["dim"])
+    P = OrcProblem()
+    P.dim = d
+    n = list(spec["n"]) + [1] * (3 - len(spec["n"]))
+    lo = list(spec.get("lo", [0.0] * d)) + [0.0] * (3 - d)
+    hi = list(spec.get("hi", [1.0] * d)) + [1.0] * (3 - d)
+    for l in range(3):
+        P.n[l] = int(n[l]) if l < d else 1
+        P.lo[l] = float(lo[l])
+        P.hi[l] = float(hi[l])
+    for l in range(d):
+        kind, *par = spec["flux"][l]
+        P.fkind[l] = FLUX_KINDS[kind]
+        for k, v in enumerate(par[:2]):
+            P.fpar[l][k] = float(v)
+    kind, *par = spec["diff"]
+    P.akind = DIFF_KINDS[kind]
+    for k, v in enumerate(par[:3]):
+        P.apar[k] = float(v)
+    P.umin = float(spec["umin"])
+    P.umax = float(spec["umax"])
+    P.limiter = int(bool(spec.get("limiter", False)))
+    P.si = int(bool(spec.get("si", False)))
+    P.si_gamma = float(spec.get("si_gamma", 1.0))
+    P.theta_mode = THETA_MODES[theta_mode]
+    if lib().orc_setup(ctypes.byref(P)) != 0:
+        raise ValueError("oracle: invalid problem")
+    return P
+
+
+def ncells(P):
+    return P.n[0] * P.n[1] * P.n[2]
+
+
+def ndofs(P):
+    return 1 << P.dim
+
+
+def _ptrs(arrs):
+    dp = ctypes.POINTER(ctypes.c_double)
+    arr = (dp * len(arrs))()
+    for i, a in enumerate(arrs):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+        arr[i] = a.ctypes.data_as(dp)
+    return arr
+
+
+def _as_state(P, U):
+    N = ncells(P)
+    out = [np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(-1)) for u in U]
+    assert len(out) == ndofs(P) and all(u.size == N for u in out)
+    return out
+
+
+def rhs(P, U):
+    """Semi-discrete right-hand side (no limiting, no blending) of every DoF."""
+    U = _as_state(P, U)
+    R = [np.empty(ncells(P)) for _ in range(ndofs(P))]
+    lib().orc_rhs(ctypes.byref(P), _ptrs(U), _ptrs(R))
+    return R
+
+
+def rhs_cells(P, U, cells):
+    U = _as_state(P, U)
+    cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64))
+    out = np.empty((cells.size, ndofs(P)))
+    lib().orc_rhs_cells(ctypes.byref(P), _ptrs(U), cells.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+                        cells.size, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def fe(P, U, dt):
+    """One forward-Euler stage; returns (new DoFs, diagnostics dict)."""
+    U = _as_state(P, U)
+    V = [np.empty(ncells(P)) for _ in range(ndofs(P))]
+    dg = OrcDiag()
+    lib().orc_fe(ctypes.byref(P), _ptrs(U), float(dt), _ptrs(V), ctypes.byref(dg))
+    return V, dg.as_dict()
+
+
+def fe_cells(P, U, dt, cells):
+    U = _as_state(P, U)
+    cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64))
+    out = np.empty((cells.size, ndofs(P)))
+    dg = OrcDiag()
+    lib().orc_fe_cells(ctypes.byref(P), _ptrs(U), float(dt), cells.ctypes.data_as(ctypes.POINTER(ctypes.c_long)),
+                       cells.size, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(dg))
+    return out, dg.as_dict()
+
+
+def dt_cfl(P, U, cfl):
+    U = _as_state(P, U)
+    return lib().orc_dt(ctypes.byref(P), _ptrs(U), float(cfl))
+
+
+def ssprk3_step(P, U, dt, diag=None):
+    """One SSP-RK3 step; U (list of float64 arrays) is updated in place."""
+    assert all(u.dtype == np.float64 and u.flags.c_contiguous for u in U)
+    W1 = [np.empty(ncells(P)) for _ in range(ndofs(P))]
+    W2 = [np.empty(ncells(P)) for _ in range(ndofs(P))]
+    dg = OrcDiag()
+    lib().orc_ssprk3_step(ctypes.byref(P), _ptrs([u.reshape(-1) for u in U]), float(dt), _ptrs(W1), _ptrs(W2),
+                          ctypes.byref(dg))
+    if diag is not None:
+        d = dg.as_dict()
+        diag["uL_out_of_bounds"] = diag.get("uL_out_of_bounds", 0) + d["uL_out_of_bounds"]
+        diag["n_theta"] = diag.get("n_theta", 0) + d["n_theta"]
+        diag["n_theta_lt1"] = diag.get("n_theta_lt1", 0) + d["n_theta_lt1"]
+        diag["max_avg_clamp"] = max(diag.get("max_avg_clamp", 0.0), d["max_avg_clamp"])
+        diag["max_pv_clamp"] = max(diag.get("max_pv_clamp", 0.0), d["max_pv_clamp"])
+    return U
+
+
+def run(P, U, nsteps=None, cfl=None, t0=0.0, t_end=None, dts=None, integrator="ssprk3", diag=None):
+    """Advance U.  Either a list of prescribed time steps ``dts`` or a CFL
+    number (dt from the MPP CFL condition, the last step clipped to t_end).
+    Returns (U, t, list of dt used)."""
+    U = [np.array(u, dtype=np.float64).reshape(-1) for u in U]
+    t = t0
+    used = []
+    k = 0
+    while True:
+        if dts is not None:
+            if k >= len(dts):
+                break
+            dt = float(dts[k])
+        else:
+            if nsteps is not None and k >= nsteps:
+                break
+            if t_end is not None and t_end - t <= 1e-12 * abs(t_end):
+                break  # a remainder below 1e-12 T is rounding, not a step
+            dt = dt_cfl(P, U, cfl)
+            if t_end is not None:
+                dt = min(dt, t_end - t)
+        if integrator == "ssprk3":
+            ssprk3_step(P, U, dt, diag)
+        else:
+            V, d = fe(P, U, dt)
+            U = V
+        t += dt
+        used.append(dt)
+        k += 1
+    return U, t, used
+
+
+def limiter_probe(P, U, dt, l, cell):
+    """uL+, uL-, fhat_H, fhat_L, ahat_H, a(avg), theta_c, theta_d of one cell."""
+    U = _as_state(P, U)
+    out = np.empty(8)
+    lib().orc_limiter_probe(ctypes.byref(P), _ptrs(U), float(dt), int(l), int(cell),
+                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def evaluate(P, l, u):
+    """f_l, f_l', a, kappa at the values u."""
+    u = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(-1))
+    outs = [np.empty(u.size) for _ in range(4)]
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib().orc_eval(ctypes.byref(P), int(l), u.ctypes.data_as(dp), u.size, *[o.ctypes.data_as(dp) for o in outs])
+    return outs
+
+
+def alpha_L(P, l, ua, ub):
+    return lib().orc_alpha_L(ctypes.byref(P), int(l), float(ua), float(ub))
+
+
+def halfgrid(P, U):
+    """All half-grid values (centres reconstructed), shape (2n_{d-1}, ..., 2n_0)."""
+    U = _as_state(P, U)
+    shape = [2 * P.n[l] for l in range(P.dim)][::-1]
+    out = np.empty(int(np.prod(shape)))
+    lib().orc_halfgrid(ctypes.byref(P), _ptrs(U), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out.reshape(shape)
+
+
+def crit_points(P, l):
+    return [P.crit[l][i] for i in range(P.ncrit[l])]
