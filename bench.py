@@ -1,0 +1,185 @@
+"""Benchmark of the per-stage residual-and-update sweep on one MI355X.
+
+Default workload: the batched case -- 256 independent 2D instances of uneven
+size (64^2..512^2), f = (u^2/2, u^2/2), a = c u^m, limiter and point-value
+projection on, FP32, SSP-RK3, all K steps in one HIP graph launch.  Prints one
+JSON line.  ``value`` is cell-DoF updates per second per RK stage (all
+instances, inputs resident in HBM before the timed region).
+
+    python bench.py [--steps K] [--warmup W] [--workload c4|c2|c3|c3f32|c5]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-DOF updates/s per RK stage + %HBM roofline, FP32 batched vs FP64 plain"
+UNIT = "cell-DoF updates/s per RK stage"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_2510_11527_amd import workloads as W
+    if name == "c4":
+        items = W.config4()
+        return "c4_batched_256x2d_pme_burgers_fp32", items
+    if name == "c2":
+        return "c2_burgers_deadzone_512x512_fp64", [W.config2()]
+    if name == "c3":
+        return "c3_buckley_leverett_gravity_1024x1024_fp64", [W.config3(precision=64)]
+    if name == "c3f32":
+        return "c3_buckley_leverett_gravity_1024x1024_fp32", [W.config3(precision=32)]
+    if name == "c5":
+        return "c5_degenerate_3d_256cubed_fp32_si", [W.config5()]
+    raise SystemExit("unknown workload " + name)
+
+
+def make_ctx(items, precision=None, variant=None):
+    from paper_2510_11527_amd import af
+    ctx = af.Context([s for s, _ in items], precision=precision)
+    if variant is not None:
+        ctx.set_variant(variant)
+    for i, (_, U) in enumerate(items):
+        ctx.set_state(i, U)
+    return ctx
+
+
+def cpu_baseline(items, target_cells):
+    """The FP64 oracle on a bounded sample: the first instances of the same
+    workload up to target_cells cells, one SSP-RK3 step with CFL steps."""
+    import oracle
+    oracle.build()
+    sample, cells = [], 0
+    for s, U in items:
+        sample.append((s, U))
+        cells += int(np.prod(s["n"][:s["dim"]]))
+        if cells >= target_cells:
+            break
+    dofs_per_cell = 2 ** items[0][0]["dim"]
+    t0 = time.perf_counter()
+    for s, U in sample:
+        P = oracle.problem(s)
+        oracle.run(P, U, nsteps=1, cfl=s["cfl"])
+    el = time.perf_counter() - t0
+    return {"value": cells * dofs_per_cell * 3 / el, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "first %d instances of the workload (%d cells), 1 SSP-RK3 step (3 stages), %.1f s"
+                      % (len(sample), cells, el)}
+
+
+def fp64_plain(items, steps, max_cells):
+    """Same instances in FP64, one context per instance, stepped one after
+    the other (no batching): the 'plain' form."""
+    from paper_2510_11527_amd import af
+    sample, cells = [], 0
+    for s, U in items:
+        sample.append((s, U))
+        cells += int(np.prod(s["n"][:s["dim"]]))
+        if cells >= max_cells:
+            break
+    ctxs = []
+    for s, U in sample:
+        c = af.Context(dict(s, precision=64))
+        c.set_state(0, U)
+        c.step(2)  # warm up (graph build)
+        ctxs.append(c)
+    t0 = time.perf_counter()
+    for c in ctxs:
+        c.step(steps)
+    el = time.perf_counter() - t0
+    for c in ctxs:
+        c.close()
+    dpc = 2 ** items[0][0]["dim"]
+    return {"value": cells * dpc * 3 * steps / el, "unit": UNIT, "dtype": "f64", "instances": len(sample),
+            "cells": cells, "steps": steps, "seconds": el}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c4")
+    ap.add_argument("--variant", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-plain", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2510_11527_amd import af
+    if not os.path.exists(af.LIB_PATH):
+        from paper_2510_11527_amd import build as B
+        B.build(verbose=False)
+
+    t0 = time.perf_counter()
+    wname, items = workload(args.workload)
+    log("workload %s: %d instances generated in %.1f s" % (wname, len(items), time.perf_counter() - t0))
+    prec = items[0][0]["precision"]
+    ctx = make_ctx(items, variant=args.variant)
+    work = ctx.work()
+    variant_name = ctx.variant_name(args.variant if args.variant is not None else 0)
+    if args.warmup > 0:
+        ctx.step(args.warmup)
+    log("warmup done")
+    # timed region: K steps in one graph launch; inputs already in HBM
+    ctx.step(1)
+    ctx.step(args.steps)  # builds the graph for K steps (and runs them)
+    t1 = time.perf_counter()
+    ctx.step(args.steps)
+    t2 = time.perf_counter()
+    el = t2 - t1
+    stages = 3 * args.steps
+    value = work["dofs"] * stages / el
+    log("timed %d steps in %.4f s" % (args.steps, el))
+
+    roof = None
+    if not args.no_kernel_timing:
+        # stage-kernel durations from HIP events around every stage launch on
+        # the context stream, over K more steps of the same workload
+        ms, nl = ctx.step_timed(args.steps)
+        achieved = work["bytes_per_stage"] / (ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "af4::stage_kernel (%s, tile %s)" % ("fp32" if prec == 32 else "fp64", variant_name),
+                "mean_launch_ms": ms, "launches": nl,
+                "algorithmic_bytes_per_launch": work["bytes_per_stage"]}
+        log("stage kernel mean %.4f ms over %d launches -> %.1f GB/s" % (ms, nl, achieved))
+    ctx.close()
+
+    line = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == 32 else "f64", "data": "synthetic",
+            "config": {"workload": wname, "instances": len(items), "cells": work["cells"], "dofs": work["dofs"],
+                       "integrator": "ssprk3", "limiter": bool(items[0][0]["limiter"]),
+                       "si": bool(items[0][0]["si"]), "cfl": items[0][0]["cfl"], "tile": variant_name,
+                       "graph": "one hipGraph launch of %d steps" % args.steps},
+            "cell_updates_per_s": work["cells"] * stages / el,
+            "step_hbm_frac": work["bytes_per_stage"] * stages / el / 1e9 / HBM_PEAK_GBS}
+    if roof:
+        line["roofline"] = roof
+    if not args.no_fp64_plain and prec == 32:
+        try:
+            line["fp64_plain"] = fp64_plain(items, max(10, args.steps // 10), 4_000_000)
+            line["fp32_batched_over_fp64_plain"] = value / line["fp64_plain"]["value"]
+        except Exception as e:  # reported, not fatal
+            line["fp64_plain"] = {"error": str(e)}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(items, 1_500_000 if items[0][0]["dim"] == 2 else 300_000)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * af.h -- C ABI of the MI355X (gfx950) implementation of the compact
+ * fourth-order doubly conservative active flux (AF) method with monolithic
+ * convex limiting for degenerate convection-diffusion equations
+ *
+ *     u_t + div f(u) = Lap a(u),   a(u) = int kappa,  kappa >= 0,
+ *
+ * on periodic uniform Cartesian meshes in 1, 2 or 3 dimensions
+ * (J. Duan, arXiv 2510.11527; the PDE is Eq. (cde_conservative), the
+ * periodic maximum principle [u_min, u_max] is stated in Sec. 1).
+ *
+ * Every call returns an af_status; no C++ exception crosses this boundary.
+ * All host buffers are owned by the caller and copied by the library; the
+ * context owns all device memory until af_destroy.  A context is not
+ * thread-safe; distinct contexts are independent.
+ *
+ * DoF layout (Sec. 4 of the paper, "zeta order"): a state of a d-dimensional
+ * instance is 2^d arrays of n0*n1*n2 values each, x fastest:
+ *   1D: average, x-face point value
+ *   2D: average, x-face, y-face, corner
+ *   3D: average, x-face, y-face, z-face, (i+1/2,j+1/2,k), (i+1/2,j,k+1/2),
+ *       (i,j+1/2,k+1/2), corner
+ * The point value at a half index i+1/2 is stored at index i.
+ */
+#ifndef AF4_AF_H
+#define AF4_AF_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct af_ctx af_ctx;
+
+typedef enum {
+    AF_OK = 0,
+    AF_ERR_ARG = -1,         /* invalid argument or problem description */
+    AF_ERR_ALLOC = -2,       /* device or host allocation failed */
+    AF_ERR_DEVICE = -3,      /* a HIP call failed; see af_last_error */
+    AF_ERR_BOUNDS = -4,      /* state outside [umin, umax] with the limiter on */
+    AF_ERR_NONFINITE = -5,   /* non-finite or divergent state */
+    AF_ERR_CFL = -6,         /* CFL number outside the admissible range */
+    AF_ERR_STATE = -7,       /* call out of order (e.g. step before set_state) */
+    AF_ERR_UNSUPPORTED = -8  /* valid but not supported combination */
+} af_status;
+
+/* Convection flux f_l(u) per axis (Sec. 6 examples). */
+typedef enum {
+    AF_F_LINEAR = 0,  /* p0 * u                                  */
+    AF_F_QUAD = 1,    /* p0 * u^2   (p0 = 1/2: Burgers)          */
+    AF_F_BL = 2,      /* u^2 / (u^2 + (1-u)^2)  (Example 6.6)    */
+    AF_F_BL_GRAV = 3  /* BL(u) * (1 - p1 (1-u)^2)  (Example 6.6) */
+} af_flux_kind;
+
+/* Diffusion potential a(u) = int kappa (Sec. 1). */
+typedef enum {
+    AF_A_LINEAR = 0,   /* p0 * u                                            */
+    AF_A_POWER = 1,    /* p0 * u^p1  (porous medium, Eq. (pme))             */
+    AF_A_DEADZONE = 2, /* p0 * sign(u) * max(0, |u| - p1)  (Examples 6.8/9) */
+    AF_A_BL = 3,       /* p0 (2u^2 - 4u^3/3) on [0,1], constant outside     */
+    AF_A_RAMP2 = 4     /* (p0/2) max(0, u - p1)^2, i.e. kappa = p0 max(0,u-p1) */
+} af_diff_kind;
+
+typedef enum {
+    AF_RK_SSP3 = 0,   /* SSP-RK3, Shu-Osher form; R(z) of Sec. 3.2 */
+    AF_RK_EULER = 1   /* one forward-Euler stage per step (Sec. 5)  */
+} af_integrator;
+
+typedef struct {
+    int dim;                 /* 1, 2 or 3 */
+    int n[3];                /* cells per axis (>= 4 on used axes) */
+    double lo[3], hi[3];     /* periodic box */
+    int flux[3];             /* af_flux_kind per axis */
+    double flux_par[3][2];   /* p0, p1 per axis */
+    int diff;                /* af_diff_kind */
+    double diff_par[2];      /* p0, p1 */
+    double umin, umax;       /* bounds; NaN: min/max over the DoFs of the first af_set_state */
+    double cfl;              /* C in dt = C / max_{l,faces}(alpha_l/dx_l + kappa_max/dx_l^2),
+                                Eqs. (1d_av_pp_dt, multid_av_pp_dt); with the limiter C <= 1/(2d) */
+    int limiter;             /* 1: monolithic convex limiting of the averages (Sec. 5.1.1, 5.2.1)
+                                and projection of the point values (Sec. 5.1.2) */
+    int si_blend;            /* 1: smoothness-indicator blending (Sec. 5.1.3) */
+    double si_gamma;         /* gamma of the blending */
+    int precision;           /* 32 or 64: storage and stencil arithmetic */
+    int integrator;          /* af_integrator */
+} af_problem;
+
+typedef struct {
+    double t;                /* time of the state */
+    double dt_last;          /* last step size used */
+    double mass;             /* FP64 sum of averages times the cell volume */
+    double min_avg, max_avg; /* over the averages */
+    double min_pv, max_pv;   /* over the point values */
+    double l1_avg, l2_avg, linf_avg;  /* volume-weighted norms of the averages */
+    double max_clamp;        /* largest safeguard clamp applied to an average so far */
+    long long steps;         /* steps taken */
+    int nonfinite;           /* 1 if a non-finite value was produced */
+    int reserved;
+} af_norms_t;
+
+/* Creates a context holding n_inst independent instances (batched when
+ * n_inst > 1: one launch per Runge-Kutta stage advances all of them, each
+ * with its own time step).  All instances must share dim, precision,
+ * limiter, si_blend and integrator (else AF_ERR_UNSUPPORTED); grids, fluxes,
+ * potentials, bounds and CFL numbers may differ.  Validation: n >= 4 on used
+ * axes, hi > lo, 0 < cfl, cfl <= 1/(2 dim) with the limiter (AF_ERR_CFL).
+ * Allocates three state buffers per instance on the current HIP device. */
+af_status af_create(int n_inst, const af_problem *probs, af_ctx **out);
+
+/* Frees all device memory and graphs of the context.  NULL is accepted. */
+af_status af_destroy(af_ctx *ctx);
+
+/* Copies the state of instance inst from the host: dofs[0..2^d-1] point to
+ * n0*n1*n2 doubles each, in zeta order.  FP32 contexts round to nearest.
+ * Validates before mutating: non-finite -> AF_ERR_NONFINITE; with the
+ * limiter, a value outside [umin, umax] -> AF_ERR_BOUNDS.  If umin/umax were
+ * NaN at creation they are set here, once, from the (rounded) DoFs. */
+af_status af_set_state(af_ctx *ctx, int inst, const double *const *dofs, double t);
+
+/* Copies the state of instance inst to the host (widened to double). */
+af_status af_get_state(af_ctx *ctx, int inst, double *const *dofs, double *t);
+
+/* Advances every instance by nsteps steps.  Per step and instance, dt is
+ * the CFL value computed on the device from the averages (FP64 reduction of
+ * the interval maximum of |f_l'|, Eq. (1d_local_wave_speed)), or
+ * dt_prescribed[inst] when dt_prescribed is not NULL; with t_end > 0 it is
+ * clipped to t_end - t and an instance that has reached t_end stays put.
+ * On return dt_used[inst] (if not NULL) holds the last step of each
+ * instance.  Runs as one HIP graph launch when nsteps > 1.  Returns
+ * AF_ERR_NONFINITE if any stage produced a non-finite value or the
+ * averages diverged; the state is then readable but unspecified. */
+af_status af_step(af_ctx *ctx, int nsteps, double t_end, const double *dt_prescribed, double *dt_used);
+
+/* Semi-discrete right-hand side R(U) of instance inst, without limiting or
+ * blending (Eq. (2d_af_dc); Eq. (1d_af_dc) in 1D), to rhs[0..2^d-1]. */
+af_status af_residual(af_ctx *ctx, int inst, double *const *rhs);
+
+/* Norms and diagnostics of instance inst, reduced on the device in FP64. */
+af_status af_norms(af_ctx *ctx, int inst, af_norms_t *out);
+
+/* Message of the last error of the context (or of af_create if ctx is NULL). */
+const char *af_last_error(const af_ctx *ctx);
+
+/* Uses the given hipStream_t (passed as void*) for all further work of the
+ * context; NULL restores the context's own stream.  Cached graphs are
+ * dropped. */
+af_status af_set_stream(af_ctx *ctx, void *stream);
+
+/* Selects the stage-kernel tile variant (0 = default; see af_num_variants)
+ * and returns AF_ERR_ARG for an out-of-range index.  Used by the tile
+ * autotuner; cached graphs are dropped. */
+af_status af_set_variant(af_ctx *ctx, int variant);
+int af_num_variants(const af_ctx *ctx);
+const char *af_variant_name(const af_ctx *ctx, int variant);
+
+/* Times the stage kernels: runs nsteps steps like af_step, launching
+ * eagerly with HIP events around every stage-kernel launch on the context
+ * stream, and returns the mean stage-kernel duration in milliseconds and the
+ * number of timed launches.  The state advances as with af_step. */
+af_status af_step_timed(af_ctx *ctx, int nsteps, double t_end, const double *dt_prescribed, double *mean_stage_ms,
+                        int *launches);
+
+/* Algorithmic HBM bytes of one stage launch over all instances, averaged over
+ * the stages of one step: (2 + 1 for stages that read U^n) * 2^d * cells *
+ * value size.  Grid cells and DoFs of the context in *cells, *dofs. */
+af_status af_work(const af_ctx *ctx, double *bytes_per_stage, double *cells, double *dofs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AF4_AF_H */

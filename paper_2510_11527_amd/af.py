@@ -1,0 +1,233 @@
+"""ctypes binding of the AF library (include/af.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of libaf4.so; this module
+never computes any part of it.  Importing it loads the library and fails
+loudly if it has not been built (``python -m paper_2510_11527_amd.build``).
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libaf4.so")
+
+AF_OK, AF_ERR_ARG, AF_ERR_ALLOC, AF_ERR_DEVICE, AF_ERR_BOUNDS = 0, -1, -2, -3, -4
+AF_ERR_NONFINITE, AF_ERR_CFL, AF_ERR_STATE, AF_ERR_UNSUPPORTED = -5, -6, -7, -8
+STATUS_NAMES = {0: "AF_OK", -1: "AF_ERR_ARG", -2: "AF_ERR_ALLOC", -3: "AF_ERR_DEVICE", -4: "AF_ERR_BOUNDS",
+                -5: "AF_ERR_NONFINITE", -6: "AF_ERR_CFL", -7: "AF_ERR_STATE", -8: "AF_ERR_UNSUPPORTED"}
+FLUX = {"linear": 0, "quad": 1, "bl": 2, "bl_grav": 3}
+DIFF = {"linear": 0, "power": 1, "deadzone": 2, "bl": 3, "ramp2": 4}
+INTEGRATORS = {"ssprk3": 0, "euler": 1}
+
+EXPORTS = ["af_create", "af_destroy", "af_set_state", "af_get_state", "af_step", "af_residual", "af_norms",
+           "af_last_error", "af_set_stream", "af_set_variant", "af_num_variants", "af_variant_name",
+           "af_step_timed", "af_work"]
+
+
+class AfProblem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("n", ctypes.c_int * 3),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("flux", ctypes.c_int * 3),
+        ("flux_par", (ctypes.c_double * 2) * 3),
+        ("diff", ctypes.c_int),
+        ("diff_par", ctypes.c_double * 2),
+        ("umin", ctypes.c_double),
+        ("umax", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("limiter", ctypes.c_int),
+        ("si_blend", ctypes.c_int),
+        ("si_gamma", ctypes.c_double),
+        ("precision", ctypes.c_int),
+        ("integrator", ctypes.c_int),
+    ]
+
+
+class AfNorms(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("dt_last", ctypes.c_double), ("mass", ctypes.c_double),
+                ("min_avg", ctypes.c_double), ("max_avg", ctypes.c_double), ("min_pv", ctypes.c_double),
+                ("max_pv", ctypes.c_double), ("l1_avg", ctypes.c_double), ("l2_avg", ctypes.c_double),
+                ("linf_avg", ctypes.c_double), ("max_clamp", ctypes.c_double), ("steps", ctypes.c_longlong),
+                ("nonfinite", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def lib():
+    """Load libaf4.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libaf4.so is not built; run python -m paper_2510_11527_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        pp = ctypes.POINTER(dp)
+        vp = ctypes.c_void_p
+        L.af_create.argtypes = [ctypes.c_int, ctypes.POINTER(AfProblem), ctypes.POINTER(vp)]
+        L.af_destroy.argtypes = [vp]
+        L.af_set_state.argtypes = [vp, ctypes.c_int, pp, ctypes.c_double]
+        L.af_get_state.argtypes = [vp, ctypes.c_int, pp, dp]
+        L.af_step.argtypes = [vp, ctypes.c_int, ctypes.c_double, dp, dp]
+        L.af_step_timed.argtypes = [vp, ctypes.c_int, ctypes.c_double, dp, dp, ctypes.POINTER(ctypes.c_int)]
+        L.af_residual.argtypes = [vp, ctypes.c_int, pp]
+        L.af_norms.argtypes = [vp, ctypes.c_int, ctypes.POINTER(AfNorms)]
+        L.af_last_error.argtypes = [vp]
+        L.af_last_error.restype = ctypes.c_char_p
+        L.af_set_stream.argtypes = [vp, vp]
+        L.af_set_variant.argtypes = [vp, ctypes.c_int]
+        L.af_num_variants.argtypes = [vp]
+        L.af_variant_name.argtypes = [vp, ctypes.c_int]
+        L.af_variant_name.restype = ctypes.c_char_p
+        L.af_work.argtypes = [vp, dp, dp, dp]
+        for name in EXPORTS:
+            if name not in ("af_last_error", "af_num_variants", "af_variant_name"):
+                getattr(L, name).restype = ctypes.c_int
+        L.af_num_variants.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class AFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def make_problem(spec, precision=None, integrator="ssprk3"):
+    """af_problem from a problem dict (see workloads.py)."""
+    P = AfProblem()
+    d = int(spec["dim"])
+    P.dim = d
+    for l in range(3):
+        P.n[l] = int(spec["n"][l]) if l < d else 1
+        P.lo[l] = float(spec["lo"][l]) if l < d else 0.0
+        P.hi[l] = float(spec["hi"][l]) if l < d else 1.0
+    for l in range(d):
+        kind, *par = spec["flux"][l]
+        P.flux[l] = FLUX[kind]
+        for k, v in enumerate(par[:2]):
+            P.flux_par[l][k] = float(v)
+    kind, *par = spec["diff"]
+    P.diff = DIFF[kind]
+    for k, v in enumerate(par[:2]):
+        P.diff_par[k] = float(v)
+    P.umin = float(spec.get("umin", math.nan))
+    P.umax = float(spec.get("umax", math.nan))
+    P.cfl = float(spec.get("cfl", 0.1))
+    P.limiter = int(bool(spec.get("limiter", False)))
+    P.si_blend = int(bool(spec.get("si", False)))
+    P.si_gamma = float(spec.get("si_gamma", 1.0))
+    P.precision = int(precision or spec.get("precision", 64))
+    P.integrator = INTEGRATORS[integrator]
+    return P
+
+
+def _pp(arrs):
+    dp = ctypes.POINTER(ctypes.c_double)
+    a = (dp * len(arrs))()
+    for i, x in enumerate(arrs):
+        a[i] = x.ctypes.data_as(dp)
+    return a
+
+
+class Context:
+    """Owns one af_ctx.  Methods mirror the C entry points."""
+
+    def __init__(self, specs, precision=None, integrator="ssprk3"):
+        if isinstance(specs, dict):
+            specs = [specs]
+        self.specs = list(specs)
+        self.dim = int(self.specs[0]["dim"])
+        arr = (AfProblem * len(self.specs))(*[make_problem(s, precision, integrator) for s in self.specs])
+        self.precision = arr[0].precision
+        h = ctypes.c_void_p()
+        st = lib().af_create(len(self.specs), arr, ctypes.byref(h))
+        if st != AF_OK:
+            raise AFError(st, lib().af_last_error(None).decode())
+        self.h = h
+        self.ncells = [int(np.prod([s["n"][l] for l in range(self.dim)])) for s in self.specs]
+
+    def _check(self, st):
+        if st != AF_OK:
+            raise AFError(st, lib().af_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().af_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, inst, dofs, t=0.0):
+        a = [np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1)) for x in dofs]
+        self._check(lib().af_set_state(self.h, int(inst), _pp(a), float(t)))
+
+    def get_state(self, inst):
+        out = [np.empty(self.ncells[inst]) for _ in range(1 << self.dim)]
+        t = ctypes.c_double()
+        self._check(lib().af_get_state(self.h, int(inst), _pp(out), ctypes.byref(t)))
+        return out, t.value
+
+    def step(self, nsteps=1, t_end=0.0, dt=None):
+        n = len(self.specs)
+        dp = ctypes.POINTER(ctypes.c_double)
+        used = np.empty(n)
+        presc = None
+        if dt is not None:
+            presc = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (n,)).copy())
+        st = lib().af_step(self.h, int(nsteps), float(t_end or 0.0),
+                           presc.ctypes.data_as(dp) if presc is not None else None, used.ctypes.data_as(dp))
+        self._check(st)
+        return used
+
+    def step_timed(self, nsteps=1, t_end=0.0, dt=None):
+        n = len(self.specs)
+        dp = ctypes.POINTER(ctypes.c_double)
+        presc = None
+        if dt is not None:
+            presc = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64), (n,)).copy())
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int()
+        self._check(lib().af_step_timed(self.h, int(nsteps), float(t_end or 0.0),
+                                        presc.ctypes.data_as(dp) if presc is not None else None,
+                                        ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
+
+    def residual(self, inst):
+        out = [np.empty(self.ncells[inst]) for _ in range(1 << self.dim)]
+        self._check(lib().af_residual(self.h, int(inst), _pp(out)))
+        return out
+
+    def norms(self, inst):
+        n = AfNorms()
+        self._check(lib().af_norms(self.h, int(inst), ctypes.byref(n)))
+        return n.as_dict()
+
+    def set_stream(self, stream_ptr):
+        self._check(lib().af_set_stream(self.h, ctypes.c_void_p(stream_ptr)))
+
+    def num_variants(self):
+        return lib().af_num_variants(self.h)
+
+    def variant_name(self, v):
+        return lib().af_variant_name(self.h, int(v)).decode()
+
+    def set_variant(self, v):
+        self._check(lib().af_set_variant(self.h, int(v)))
+
+    def work(self):
+        b, c, d = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(lib().af_work(self.h, ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+        return {"bytes_per_stage": b.value, "cells": c.value, "dofs": d.value}

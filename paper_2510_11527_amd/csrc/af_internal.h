@@ -1,0 +1,63 @@
+// af_internal.h -- device-side data structures shared by the host runtime and
+// the HIP kernels of the AF library.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace af4 {
+
+constexpr int kMaxCrit = 6;   // local maxima of |f_l'| kept per axis
+
+// Per-instance parameters, device resident (one array entry per instance).
+struct InstDev {
+    int n[3];            // cells per axis (1 on unused axes)
+    int tiles[3];        // tiles per axis for the selected stage variant
+    long long ncell;     // n0*n1*n2
+    long long off;       // element offset of the instance's DoF block
+    long long kstride;   // elements between consecutive DoF kinds of the block
+    double dx[3];
+    int fk[3];           // af_flux_kind per axis
+    double fp0[3], fp1[3];
+    int ak;              // af_diff_kind
+    int am;              // integer exponent of a power potential (0: use pow)
+    double ap0, ap1;
+    double umin, umax;
+    double kmax;         // sup of kappa over [umin, umax]
+    double cfl;
+    int ncrit[3];
+    double crit[3][kMaxCrit];  // interior local maxima of |f_l'|
+    double vol;          // cell volume
+    double si_gamma;     // smoothness-indicator blending strength
+};
+
+// Control block read by the time-step kernels (uploaded before each af_step).
+struct StepCtl {
+    double t_end;        // <= 0: no end time
+    int prescribed;      // 1: dt from the prescribed array, 0: CFL
+    int pad;
+};
+
+// Per-instance device scalars.
+struct InstState {
+    double dt;           // step of the current step
+    double t;            // time at the end of the current step
+    unsigned long long wmax;      // bits of the FP64 max wave speed (non-negative)
+    unsigned long long clampmax;  // bits of the largest average clamp (non-negative)
+    unsigned int flags;  // bit 0: non-finite / divergent value produced
+    unsigned int pad;
+    long long steps;     // steps with dt > 0
+};
+
+template <class T>
+struct StageParams {
+    const InstDev *inst;
+    const int2 *work;    // (instance, tile) per block
+    int nwork;
+    const T *in;         // stage input U^(s-1)
+    const T *un;         // U^n for the RK combination
+    T *out;              // stage output (or right-hand side)
+    InstState *st;
+    int stage;           // 0: forward Euler, 1..3: SSP-RK3 stage, 4: residual
+};
+
+}  // namespace af4

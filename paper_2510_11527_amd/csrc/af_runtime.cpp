@@ -1,0 +1,693 @@
+// af_runtime.cpp -- host runtime behind the C ABI of include/af.h: contexts,
+// instance table, device buffers, work lists, time stepping (eager and as one
+// HIP graph per af_step), residuals and norms.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "af.h"
+#include "af_internal.h"
+#include "launch.h"
+
+using af4::InstDev;
+using af4::InstState;
+using af4::StageParams;
+using af4::StepCtl;
+
+struct af_ctx {
+    int n_inst = 0, dim = 0, prec = 64, lim = 0, si = 0, integ = 0;
+    std::vector<af_problem> prob;
+    std::vector<InstDev> ih;
+    std::vector<int> have_state;
+    InstDev *d_inst = nullptr;
+    InstState *d_st = nullptr;
+    StepCtl *d_ctl = nullptr;
+    double *d_dtp = nullptr;
+    int2 *d_work = nullptr;
+    int nwork = 0;
+    std::vector<int> work_start, work_count;
+    int2 *d_chunks = nullptr;
+    int nchunks = 0;
+    void *buf[3] = {nullptr, nullptr, nullptr};
+    long long total = 0;     // elements per state buffer
+    double *d_npart = nullptr, *d_nout = nullptr;
+    hipStream_t own_stream = nullptr, stream = nullptr;
+    int variant = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_steps = 0;
+    std::string err;
+};
+
+static thread_local std::string g_create_err;
+
+namespace {
+
+size_t vbytes(const af_ctx *c) { return c->prec == 32 ? 4 : 8; }
+
+af_status fail(af_ctx *c, af_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    else g_create_err = msg;
+    return s;
+}
+
+#define HIPOK(ctx, call)                                                                         \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((ctx), AF_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------- physics (host)
+
+// |f_l'(u)| for the local-maximum search of the LLF wave speed
+double host_adf(int kind, double c, double g, double u)
+{
+    switch (kind) {
+    case AF_F_LINEAR: return std::fabs(c);
+    case AF_F_QUAD: return std::fabs(2 * c * u);
+    default: {
+        double v = 1 - u, den = u * u + v * v;
+        double d1 = 2 * u * v / (den * den);
+        if (kind == AF_F_BL) return std::fabs(d1);
+        double q = u * u / den;
+        return std::fabs(d1 * (1 - g * v * v) + q * 2 * g * v);
+    }
+    }
+}
+
+// Interior local maxima of |f_l'| over [a, b]: dense sampling, then golden
+// section refinement of every sampled local maximum.
+int host_local_maxima(int kind, double c, double g, double a, double b, double *out, int maxout)
+{
+    if (kind == AF_F_LINEAR || kind == AF_F_QUAD) return 0;  // |f'| convex or constant
+    const int M = 8192;
+    std::vector<double> x(M + 1), y(M + 1);
+    for (int i = 0; i <= M; i++) {
+        x[i] = a + (b - a) * i / M;
+        y[i] = host_adf(kind, c, g, x[i]);
+    }
+    int n = 0;
+    const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+    for (int i = 1; i < M && n < maxout; i++) {
+        if (!(y[i] > y[i - 1] && y[i] >= y[i + 1])) continue;
+        double lo = x[i - 1], hi = x[i + 1];
+        double p = hi - gr * (hi - lo), q = lo + gr * (hi - lo);
+        double fp = host_adf(kind, c, g, p), fq = host_adf(kind, c, g, q);
+        for (int it = 0; it < 200 && hi - lo > 1e-15 * (1 + std::fabs(lo)); it++) {
+            if (fp < fq) {
+                lo = p; p = q; fp = fq;
+                q = lo + gr * (hi - lo); fq = host_adf(kind, c, g, q);
+            } else {
+                hi = q; q = p; fq = fp;
+                p = hi - gr * (hi - lo); fp = host_adf(kind, c, g, p);
+            }
+        }
+        out[n++] = 0.5 * (lo + hi);
+    }
+    return n;
+}
+
+// sup of kappa = a' over [lo, hi], closed forms per potential
+double host_kappa_max(int kind, double p0, double p1, double lo, double hi)
+{
+    switch (kind) {
+    case AF_A_LINEAR: return std::max(p0, 0.0);
+    case AF_A_POWER: {
+        auto k = [&](double u) { return p0 * p1 * std::pow(u, p1 - 1); };
+        return std::max(0.0, std::max(k(lo), k(hi)));
+    }
+    case AF_A_DEADZONE: return (hi > p1 || lo < -p1) ? std::max(p0, 0.0) : 0.0;
+    case AF_A_BL: {
+        double a = std::max(lo, 0.0), b = std::min(hi, 1.0);
+        if (a > b) return 0.0;
+        double u = std::min(std::max(0.5, a), b);
+        return std::max(0.0, 4 * p0 * u * (1 - u));
+    }
+    case AF_A_RAMP2: return std::max(0.0, p0 * std::max(0.0, hi - p1));
+    }
+    return 0.0;
+}
+
+void derive_bounds_params(InstDev &I, const af_problem &P, int dim)
+{
+    I.kmax = host_kappa_max(P.diff, P.diff_par[0], P.diff_par[1], I.umin, I.umax);
+    const double w = I.umax - I.umin;
+    for (int l = 0; l < 3; l++) {
+        I.ncrit[l] = 0;
+        for (int k = 0; k < af4::kMaxCrit; k++) I.crit[l][k] = 0;
+        if (l < dim)
+            I.ncrit[l] = host_local_maxima(P.flux[l], P.flux_par[l][0], P.flux_par[l][1], I.umin - w - 1,
+                                           I.umax + w + 1, I.crit[l], af4::kMaxCrit);
+    }
+}
+
+bool is_int_exponent(double p, int *m)
+{
+    double r = std::round(p);
+    if (r >= 1 && r <= 16 && r == p) {
+        *m = (int)r;
+        return true;
+    }
+    return false;
+}
+
+af_status validate(const af_problem &P, int idx)
+{
+    char buf[256];
+    auto bad = [&](af_status s, const char *what) {
+        std::snprintf(buf, sizeof buf, "instance %d: %s", idx, what);
+        return fail(nullptr, s, buf);
+    };
+    if (P.dim < 1 || P.dim > 3) return bad(AF_ERR_ARG, "dim must be 1, 2 or 3");
+    for (int l = 0; l < P.dim; l++) {
+        if (P.n[l] < 4) return bad(AF_ERR_ARG, "need at least 4 cells per axis");
+        if (!(P.hi[l] > P.lo[l])) return bad(AF_ERR_ARG, "hi must exceed lo");
+        if (P.flux[l] < AF_F_LINEAR || P.flux[l] > AF_F_BL_GRAV) return bad(AF_ERR_ARG, "unknown flux kind");
+    }
+    if (P.diff < AF_A_LINEAR || P.diff > AF_A_RAMP2) return bad(AF_ERR_ARG, "unknown potential kind");
+    if (P.precision != 32 && P.precision != 64) return bad(AF_ERR_ARG, "precision must be 32 or 64");
+    if (P.integrator != AF_RK_SSP3 && P.integrator != AF_RK_EULER) return bad(AF_ERR_ARG, "unknown integrator");
+    if (!(P.cfl > 0)) return bad(AF_ERR_CFL, "cfl must be positive");
+    if (P.limiter && P.cfl > 1.0 / (2 * P.dim) * (1 + 1e-12))
+        return bad(AF_ERR_CFL, "with the limiter cfl must not exceed 1/(2 dim)");
+    if (!std::isnan(P.umin) && !std::isnan(P.umax) && !(P.umax >= P.umin)) return bad(AF_ERR_ARG, "umax < umin");
+    if (P.si_blend && !(P.si_gamma >= 0)) return bad(AF_ERR_ARG, "si_gamma must be >= 0");
+    return AF_OK;
+}
+
+int nkinds(const af_ctx *c) { return 1 << c->dim; }
+
+void drop_graph(af_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->graph_steps = 0;
+}
+
+// Work list (instance, tile) for the current variant; instances are kept
+// contiguous so that one instance can be launched alone.
+af_status build_work(af_ctx *c)
+{
+    af4::VariantInfo vi = af4::stage_variant(c->dim, c->variant);
+    std::vector<int2> work;
+    c->work_start.assign(c->n_inst, 0);
+    c->work_count.assign(c->n_inst, 0);
+    for (int i = 0; i < c->n_inst; i++) {
+        InstDev &I = c->ih[i];
+        long long nt = 1;
+        for (int l = 0; l < 3; l++) {
+            I.tiles[l] = (I.n[l] + vi.tile[l] - 1) / vi.tile[l];
+            nt *= I.tiles[l];
+        }
+        c->work_start[i] = (int)work.size();
+        c->work_count[i] = (int)nt;
+        for (long long t = 0; t < nt; t++) work.push_back(make_int2(i, (int)t));
+    }
+    if (c->d_work) (void)hipFree(c->d_work);
+    c->d_work = nullptr;
+    c->nwork = (int)work.size();
+    HIPOK(c, hipMalloc(&c->d_work, sizeof(int2) * work.size()));
+    HIPOK(c, hipMemcpy(c->d_work, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice));
+    HIPOK(c, hipMemcpy(c->d_inst, c->ih.data(), sizeof(InstDev) * c->n_inst, hipMemcpyHostToDevice));
+    return AF_OK;
+}
+
+template <class T>
+StageParams<T> stage_params(af_ctx *c, int in, int out, int stage)
+{
+    StageParams<T> p;
+    p.inst = c->d_inst;
+    p.work = c->d_work;
+    p.nwork = c->nwork;
+    p.in = (const T *)c->buf[in];
+    p.un = (const T *)c->buf[0];
+    p.out = (T *)c->buf[out];
+    p.st = c->d_st;
+    p.stage = stage;
+    return p;
+}
+
+hipError_t launch_stage(af_ctx *c, int in, int out, int stage, bool lim, bool si, int wstart, int wcount)
+{
+    if (c->prec == 32) {
+        StageParams<float> p = stage_params<float>(c, in, out, stage);
+        p.work += wstart;
+        p.nwork = wcount;
+        return af4::stage_launch(c->dim, 32, lim, si, c->variant, wcount, &p, c->stream);
+    }
+    StageParams<double> p = stage_params<double>(c, in, out, stage);
+    p.work += wstart;
+    p.nwork = wcount;
+    return af4::stage_launch(c->dim, 64, lim, si, c->variant, wcount, &p, c->stream);
+}
+
+// One time step over all instances, enqueued on the context stream.  With
+// events != nullptr, records an event pair around every stage launch.
+hipError_t enqueue_step(af_ctx *c, std::vector<hipEvent_t> *events, size_t *ev_next)
+{
+    hipError_t e;
+    e = af4::wavespeed_launch(c->dim, c->prec, c->d_inst, c->d_chunks, c->nchunks, c->buf[0], c->d_st, c->stream);
+    if (e != hipSuccess) return e;
+    e = af4::finalize_launch(c->n_inst, c->d_inst, c->d_ctl, c->d_dtp, c->d_st, c->stream);
+    if (e != hipSuccess) return e;
+    auto stage = [&](int in, int out, int st) -> hipError_t {
+        if (events) (void)hipEventRecord((*events)[(*ev_next)++], c->stream);
+        hipError_t r = launch_stage(c, in, out, st, c->lim, c->si, 0, c->nwork);
+        if (events) (void)hipEventRecord((*events)[(*ev_next)++], c->stream);
+        return r;
+    };
+    if (c->integ == AF_RK_SSP3) {
+        if ((e = stage(0, 1, 1)) != hipSuccess) return e;
+        if ((e = stage(1, 2, 2)) != hipSuccess) return e;
+        if ((e = stage(2, 0, 3)) != hipSuccess) return e;
+    } else {
+        if ((e = stage(0, 1, 0)) != hipSuccess) return e;
+        e = af4::copy_launch(c->prec, c->buf[1], c->buf[0], c->total, c->stream);
+    }
+    return e;
+}
+
+af_status upload_ctl(af_ctx *c, double t_end, const double *dtp)
+{
+    StepCtl ctl;
+    ctl.t_end = t_end > 0 ? t_end : 0.0;
+    ctl.prescribed = dtp ? 1 : 0;
+    ctl.pad = 0;
+    HIPOK(c, hipMemcpyAsync(c->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, c->stream));
+    if (dtp) HIPOK(c, hipMemcpyAsync(c->d_dtp, dtp, sizeof(double) * c->n_inst, hipMemcpyHostToDevice, c->stream));
+    // the host buffers may go away after return: finish the copies now
+    HIPOK(c, hipStreamSynchronize(c->stream));
+    return AF_OK;
+}
+
+af_status check_ready(af_ctx *c)
+{
+    for (int i = 0; i < c->n_inst; i++)
+        if (!c->have_state[i]) return fail(c, AF_ERR_STATE, "af_set_state has not been called for every instance");
+    return AF_OK;
+}
+
+af_status finish_step(af_ctx *c, double *dt_used)
+{
+    std::vector<InstState> st(c->n_inst);
+    HIPOK(c, hipMemcpyAsync(st.data(), c->d_st, sizeof(InstState) * c->n_inst, hipMemcpyDeviceToHost, c->stream));
+    HIPOK(c, hipStreamSynchronize(c->stream));
+    bool bad = false;
+    for (int i = 0; i < c->n_inst; i++) {
+        if (dt_used) dt_used[i] = st[i].dt;
+        if (st[i].flags & 1u) bad = true;
+    }
+    if (bad) return fail(c, AF_ERR_NONFINITE, "non-finite or divergent state produced");
+    return AF_OK;
+}
+
+template <class T>
+void to_device_layout(const double *src, void *dst, long long n)
+{
+    T *d = (T *)dst;
+    for (long long i = 0; i < n; i++) d[i] = (T)src[i];
+}
+
+template <class T>
+void from_device_layout(const void *src, double *dst, long long n)
+{
+    const T *s = (const T *)src;
+    for (long long i = 0; i < n; i++) dst[i] = (double)s[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
+{
+    if (!out || !probs || n_inst < 1) return fail(nullptr, AF_ERR_ARG, "af_create: bad arguments");
+    *out = nullptr;
+    for (int i = 0; i < n_inst; i++) {
+        af_status s = validate(probs[i], i);
+        if (s != AF_OK) return s;
+        const af_problem &a = probs[0], &b = probs[i];
+        if (b.dim != a.dim || b.precision != a.precision || !!b.limiter != !!a.limiter ||
+            !!b.si_blend != !!a.si_blend || b.integrator != a.integrator)
+            return fail(nullptr, AF_ERR_UNSUPPORTED,
+                        "instances of one context must share dim, precision, limiter, si_blend and integrator");
+    }
+    af_ctx *c = new af_ctx();
+    c->n_inst = n_inst;
+    c->dim = probs[0].dim;
+    c->prec = probs[0].precision;
+    c->lim = !!probs[0].limiter;
+    c->si = !!probs[0].si_blend;
+    c->integ = probs[0].integrator;
+    c->prob.assign(probs, probs + n_inst);
+    c->ih.resize(n_inst);
+    c->have_state.assign(n_inst, 0);
+    long long off = 0;
+    for (int i = 0; i < n_inst; i++) {
+        const af_problem &P = probs[i];
+        InstDev &I = c->ih[i];
+        std::memset(&I, 0, sizeof I);
+        I.vol = 1.0;
+        for (int l = 0; l < 3; l++) {
+            I.n[l] = l < P.dim ? P.n[l] : 1;
+            I.dx[l] = l < P.dim ? (P.hi[l] - P.lo[l]) / P.n[l] : 1.0;
+            I.fk[l] = l < P.dim ? P.flux[l] : AF_F_LINEAR;
+            I.fp0[l] = l < P.dim ? P.flux_par[l][0] : 0.0;
+            I.fp1[l] = l < P.dim ? P.flux_par[l][1] : 0.0;
+            if (l < P.dim) I.vol *= I.dx[l];
+        }
+        I.ncell = (long long)I.n[0] * I.n[1] * I.n[2];
+        I.kstride = (I.ncell + 63) / 64 * 64;
+        I.off = off;
+        off += I.kstride * (1 << P.dim);
+        I.ak = P.diff;
+        I.ap0 = P.diff_par[0];
+        I.ap1 = P.diff_par[1];
+        int m = 0;
+        I.am = (P.diff == AF_A_POWER && is_int_exponent(P.diff_par[1], &m)) ? m : 0;
+        I.umin = P.umin;
+        I.umax = P.umax;
+        I.cfl = P.cfl;
+        I.si_gamma = P.si_blend ? P.si_gamma : 0.0;
+        if (!std::isnan(P.umin) && !std::isnan(P.umax)) derive_bounds_params(I, P, P.dim);
+    }
+    c->total = off;
+    // default tile variant: the first one built for this combination (the
+    // residual kernel, unlimited and unblended, fits wherever the stage does)
+    c->variant = -1;
+    for (int v = 0; v < af4::stage_num_variants(c->dim); v++)
+        if (af4::stage_supported(c->dim, c->prec, c->lim, c->si, v)) {
+            c->variant = v;
+            break;
+        }
+    if (c->variant < 0) {
+        delete c;
+        return fail(nullptr, AF_ERR_UNSUPPORTED, "no stage kernel fits this dimension/precision/flag combination");
+    }
+    hipError_t e = hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        fail(nullptr, AF_ERR_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        delete c;
+        return AF_ERR_DEVICE;
+    }
+    c->stream = c->own_stream;
+    auto alloc = [&](void **p, size_t bytes) -> bool {
+        hipError_t r = hipMalloc(p, bytes);
+        if (r != hipSuccess) {
+            fail(nullptr, AF_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(r));
+            return false;
+        }
+        return true;
+    };
+    bool ok = true;
+    for (int b = 0; b < 3 && ok; b++) ok = alloc(&c->buf[b], (size_t)c->total * vbytes(c));
+    ok = ok && alloc((void **)&c->d_inst, sizeof(InstDev) * n_inst);
+    ok = ok && alloc((void **)&c->d_st, sizeof(InstState) * n_inst);
+    ok = ok && alloc((void **)&c->d_ctl, sizeof(StepCtl));
+    ok = ok && alloc((void **)&c->d_dtp, sizeof(double) * n_inst);
+    ok = ok && alloc((void **)&c->d_npart, sizeof(double) * 9 * af4::kNormBlocks);
+    ok = ok && alloc((void **)&c->d_nout, sizeof(double) * 16);
+    if (!ok) {
+        af_destroy(c);
+        return AF_ERR_ALLOC;
+    }
+    if (hipMemset(c->d_st, 0, sizeof(InstState) * n_inst) != hipSuccess ||
+        hipMemset(c->d_dtp, 0, sizeof(double) * n_inst) != hipSuccess) {
+        af_destroy(c);
+        return fail(nullptr, AF_ERR_DEVICE, "hipMemset failed");
+    }
+    // wave-speed chunks
+    std::vector<int2> chunks;
+    for (int i = 0; i < n_inst; i++) {
+        long long nch = (c->ih[i].ncell + af4::kWaveChunk - 1) / af4::kWaveChunk;
+        for (long long k = 0; k < nch; k++) chunks.push_back(make_int2(i, (int)k));
+    }
+    c->nchunks = (int)chunks.size();
+    if (!alloc((void **)&c->d_chunks, sizeof(int2) * chunks.size()) ||
+        hipMemcpy(c->d_chunks, chunks.data(), sizeof(int2) * chunks.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        af_destroy(c);
+        return AF_ERR_DEVICE;
+    }
+    af_status s = build_work(c);
+    if (s != AF_OK) {
+        g_create_err = c->err;
+        af_destroy(c);
+        return s;
+    }
+    *out = c;
+    return AF_OK;
+}
+
+af_status af_destroy(af_ctx *c)
+{
+    if (!c) return AF_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    for (int b = 0; b < 3; b++)
+        if (c->buf[b]) (void)hipFree(c->buf[b]);
+    void *ptrs[] = {c->d_inst, c->d_st, c->d_ctl, c->d_dtp, c->d_work, c->d_chunks, c->d_npart, c->d_nout};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    delete c;
+    return AF_OK;
+}
+
+const char *af_last_error(const af_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+af_status af_set_stream(af_ctx *c, void *stream)
+{
+    if (!c) return AF_ERR_ARG;
+    HIPOK(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    c->stream = stream ? (hipStream_t)stream : c->own_stream;
+    return AF_OK;
+}
+
+int af_num_variants(const af_ctx *c) { return c ? af4::stage_num_variants(c->dim) : 0; }
+
+const char *af_variant_name(const af_ctx *c, int v)
+{
+    if (!c || v < 0 || v >= af4::stage_num_variants(c->dim)) return "";
+    return af4::stage_variant(c->dim, v).name;
+}
+
+af_status af_set_variant(af_ctx *c, int v)
+{
+    if (!c) return AF_ERR_ARG;
+    if (v < 0 || v >= af4::stage_num_variants(c->dim)) return fail(c, AF_ERR_ARG, "variant out of range");
+    if (!af4::stage_supported(c->dim, c->prec, c->lim, c->si, v))
+        return fail(c, AF_ERR_UNSUPPORTED, "tile variant not built for this combination");
+    HIPOK(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    c->variant = v;
+    return build_work(c);
+}
+
+af_status af_set_state(af_ctx *c, int inst, const double *const *dofs, double t)
+{
+    if (!c || inst < 0 || inst >= c->n_inst || !dofs) return fail(c, AF_ERR_ARG, "af_set_state: bad arguments");
+    InstDev &I = c->ih[inst];
+    const af_problem &P = c->prob[inst];
+    const int nk = nkinds(c);
+    const long long n = I.ncell;
+    // round to the storage precision first: bounds and checks see what is stored
+    std::vector<double> r((size_t)n * nk);
+    for (int z = 0; z < nk; z++) {
+        if (!dofs[z]) return fail(c, AF_ERR_ARG, "af_set_state: null DoF array");
+        for (long long k = 0; k < n; k++) {
+            double v = dofs[z][k];
+            if (!std::isfinite(v)) return fail(c, AF_ERR_NONFINITE, "af_set_state: non-finite DoF");
+            r[(size_t)z * n + k] = c->prec == 32 ? (double)(float)v : v;
+        }
+    }
+    double umin = I.umin, umax = I.umax;
+    const bool derive = std::isnan(P.umin) || std::isnan(P.umax);
+    if (derive && !c->have_state[inst]) {
+        umin = *std::min_element(r.begin(), r.end());
+        umax = *std::max_element(r.begin(), r.end());
+    }
+    if (c->lim)
+        for (double v : r)
+            if (v < umin || v > umax) return fail(c, AF_ERR_BOUNDS, "af_set_state: DoF outside [umin, umax]");
+    if (derive && !c->have_state[inst]) {
+        I.umin = umin;
+        I.umax = umax;
+        derive_bounds_params(I, P, c->dim);
+        HIPOK(c, hipMemcpy(c->d_inst + inst, &I, sizeof I, hipMemcpyHostToDevice));
+    }
+    std::vector<char> stage((size_t)n * vbytes(c));
+    char *base = (char *)c->buf[0] + (size_t)I.off * vbytes(c);
+    for (int z = 0; z < nk; z++) {
+        if (c->prec == 32) to_device_layout<float>(&r[(size_t)z * n], stage.data(), n);
+        else to_device_layout<double>(&r[(size_t)z * n], stage.data(), n);
+        HIPOK(c, hipMemcpyAsync(base + (size_t)z * I.kstride * vbytes(c), stage.data(), stage.size(),
+                                hipMemcpyHostToDevice, c->stream));
+        HIPOK(c, hipStreamSynchronize(c->stream));
+    }
+    InstState st;
+    std::memset(&st, 0, sizeof st);
+    st.t = t;
+    HIPOK(c, hipMemcpyAsync(c->d_st + inst, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
+    HIPOK(c, hipStreamSynchronize(c->stream));
+    c->have_state[inst] = 1;
+    return AF_OK;
+}
+
+af_status af_get_state(af_ctx *c, int inst, double *const *dofs, double *t)
+{
+    if (!c || inst < 0 || inst >= c->n_inst || !dofs) return fail(c, AF_ERR_ARG, "af_get_state: bad arguments");
+    const InstDev &I = c->ih[inst];
+    const long long n = I.ncell;
+    std::vector<char> stage((size_t)n * vbytes(c));
+    const char *base = (const char *)c->buf[0] + (size_t)I.off * vbytes(c);
+    for (int z = 0; z < nkinds(c); z++) {
+        if (!dofs[z]) return fail(c, AF_ERR_ARG, "af_get_state: null DoF array");
+        HIPOK(c, hipMemcpyAsync(stage.data(), base + (size_t)z * I.kstride * vbytes(c), stage.size(),
+                                hipMemcpyDeviceToHost, c->stream));
+        HIPOK(c, hipStreamSynchronize(c->stream));
+        if (c->prec == 32) from_device_layout<float>(stage.data(), dofs[z], n);
+        else from_device_layout<double>(stage.data(), dofs[z], n);
+    }
+    if (t) {
+        InstState st;
+        HIPOK(c, hipMemcpyAsync(&st, c->d_st + inst, sizeof st, hipMemcpyDeviceToHost, c->stream));
+        HIPOK(c, hipStreamSynchronize(c->stream));
+        *t = st.t;
+    }
+    return AF_OK;
+}
+
+af_status af_step(af_ctx *c, int nsteps, double t_end, const double *dt_prescribed, double *dt_used)
+{
+    if (!c || nsteps < 0) return fail(c, AF_ERR_ARG, "af_step: bad arguments");
+    af_status s = check_ready(c);
+    if (s != AF_OK) return s;
+    if (dt_prescribed)
+        for (int i = 0; i < c->n_inst; i++)
+            if (!(dt_prescribed[i] >= 0) || !std::isfinite(dt_prescribed[i]))
+                return fail(c, AF_ERR_ARG, "af_step: prescribed dt must be finite and >= 0");
+    if ((s = upload_ctl(c, t_end, dt_prescribed)) != AF_OK) return s;
+    if (nsteps == 0) return finish_step(c, dt_used);
+    if (nsteps == 1) {
+        HIPOK(c, enqueue_step(c, nullptr, nullptr));
+    } else {
+        if (!c->gexec || c->graph_steps != nsteps) {
+            drop_graph(c);
+            HIPOK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = hipSuccess;
+            for (int k = 0; k < nsteps && e == hipSuccess; k++) e = enqueue_step(c, nullptr, nullptr);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return fail(c, AF_ERR_DEVICE, std::string("graph capture: ") +
+                                                  hipGetErrorString(e != hipSuccess ? e : e2));
+            }
+            c->graph = g;
+            HIPOK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+            c->graph_steps = nsteps;
+        }
+        HIPOK(c, hipGraphLaunch(c->gexec, c->stream));
+    }
+    return finish_step(c, dt_used);
+}
+
+af_status af_step_timed(af_ctx *c, int nsteps, double t_end, const double *dt_prescribed, double *mean_stage_ms,
+                        int *launches)
+{
+    if (!c || nsteps < 1) return fail(c, AF_ERR_ARG, "af_step_timed: bad arguments");
+    af_status s = check_ready(c);
+    if (s != AF_OK) return s;
+    if ((s = upload_ctl(c, t_end, dt_prescribed)) != AF_OK) return s;
+    const int per = c->integ == AF_RK_SSP3 ? 3 : 1;
+    std::vector<hipEvent_t> ev((size_t)2 * per * nsteps);
+    for (auto &e : ev) HIPOK(c, hipEventCreate(&e));
+    size_t next = 0;
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < nsteps && err == hipSuccess; k++) err = enqueue_step(c, &ev, &next);
+    hipError_t se = hipStreamSynchronize(c->stream);
+    double total = 0;
+    for (size_t k = 0; k + 1 < next; k += 2) {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+        total += ms;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (err != hipSuccess || se != hipSuccess)
+        return fail(c, AF_ERR_DEVICE, std::string("af_step_timed: ") + hipGetErrorString(err != hipSuccess ? err : se));
+    if (mean_stage_ms) *mean_stage_ms = next ? total / (next / 2) : 0.0;
+    if (launches) *launches = (int)(next / 2);
+    return finish_step(c, nullptr);
+}
+
+af_status af_residual(af_ctx *c, int inst, double *const *rhs)
+{
+    if (!c || inst < 0 || inst >= c->n_inst || !rhs) return fail(c, AF_ERR_ARG, "af_residual: bad arguments");
+    if (!c->have_state[inst]) return fail(c, AF_ERR_STATE, "af_residual before af_set_state");
+    HIPOK(c, launch_stage(c, 0, 1, 4, false, false, c->work_start[inst], c->work_count[inst]));
+    const InstDev &I = c->ih[inst];
+    std::vector<char> stage((size_t)I.ncell * vbytes(c));
+    const char *base = (const char *)c->buf[1] + (size_t)I.off * vbytes(c);
+    for (int z = 0; z < nkinds(c); z++) {
+        HIPOK(c, hipMemcpyAsync(stage.data(), base + (size_t)z * I.kstride * vbytes(c), stage.size(),
+                                hipMemcpyDeviceToHost, c->stream));
+        HIPOK(c, hipStreamSynchronize(c->stream));
+        if (c->prec == 32) from_device_layout<float>(stage.data(), rhs[z], I.ncell);
+        else from_device_layout<double>(stage.data(), rhs[z], I.ncell);
+    }
+    return AF_OK;
+}
+
+af_status af_norms(af_ctx *c, int inst, af_norms_t *out)
+{
+    if (!c || inst < 0 || inst >= c->n_inst || !out) return fail(c, AF_ERR_ARG, "af_norms: bad arguments");
+    const InstDev &I = c->ih[inst];
+    const char *base = (const char *)c->buf[0] + (size_t)I.off * vbytes(c);
+    HIPOK(c, af4::norms_launch(c->prec, base, I.ncell, I.kstride, nkinds(c), c->d_npart, c->d_nout, c->stream));
+    double r[9];
+    InstState st;
+    HIPOK(c, hipMemcpyAsync(r, c->d_nout, sizeof r, hipMemcpyDeviceToHost, c->stream));
+    HIPOK(c, hipMemcpyAsync(&st, c->d_st + inst, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    HIPOK(c, hipStreamSynchronize(c->stream));
+    std::memset(out, 0, sizeof *out);
+    out->t = st.t;
+    out->dt_last = st.dt;
+    out->mass = r[0] * I.vol;
+    out->l1_avg = r[1] * I.vol;
+    out->l2_avg = std::sqrt(r[2] * I.vol);
+    out->linf_avg = r[3];
+    out->min_avg = r[4];
+    out->max_avg = r[5];
+    out->min_pv = r[6];
+    out->max_pv = r[7];
+    out->nonfinite = (r[8] > 0 || (st.flags & 1u)) ? 1 : 0;
+    out->max_clamp = __builtin_bit_cast(double, st.clampmax);
+    out->steps = st.steps;
+    return AF_OK;
+}
+
+af_status af_work(const af_ctx *c, double *bytes_per_stage, double *cells, double *dofs)
+{
+    if (!c) return AF_ERR_ARG;
+    double nc = 0;
+    for (const InstDev &I : c->ih) nc += (double)I.ncell;
+    const double per_cell_stage =
+        (c->integ == AF_RK_SSP3 ? (2.0 + 3.0 + 3.0) / 3.0 : 2.0) * (1 << c->dim) * (double)vbytes(c);
+    if (bytes_per_stage) *bytes_per_stage = per_cell_stage * nc;
+    if (cells) *cells = nc;
+    if (dofs) *dofs = nc * (1 << c->dim);
+    return AF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,236 @@
+// aux_kernels.hip -- time-step, norm and copy kernels of the AF library.
+#include <cfloat>
+#include "launch.h"
+#include "stage_kernel.hpp"
+
+namespace af4 {
+
+// Max over the faces owned by each cell (c, c + e_l) of the MPP CFL quantity
+// alpha_l / dx_l + kappa_max / dx_l^2 (Eqs. 1d_av_pp_dt, multid_av_pp_dt), in
+// FP64 from the stored averages, reduced per wave and merged per instance by
+// an integer atomic max on the bit pattern (valid for non-negative doubles).
+template <class T>
+__global__ void __launch_bounds__(256) wavespeed_kernel(const InstDev *inst, const int2 *chunks, const T *U,
+                                                        InstState *st, int dim)
+{
+    const int2 ch = chunks[blockIdx.x];
+    const InstDev &I = inst[ch.x];
+    Phys<double> P;
+    P.load(I, dim);
+    const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2];
+    const T *u = U + I.off;
+    const long long c0 = (long long)ch.y * kWaveChunk;
+    const double big = 1e6 * fmax(fmax(fabs(I.umin), fabs(I.umax)), 1.0);
+    double w = 0.0;
+    bool bad = false;
+    for (int t = threadIdx.x; t < kWaveChunk; t += blockDim.x) {
+        const long long c = c0 + t;
+        if (c >= I.ncell) break;
+        const int i = (int)(c % n0);
+        const long long r = c / n0;
+        const int j = (int)(r % n1), k = (int)(r / n1);
+        const double uc = (double)u[c];
+        if (!(fabs(uc) <= big)) bad = true;  // also catches NaN
+        for (int l = 0; l < dim; l++) {
+            long long cn;
+            if (l == 0) cn = (i + 1 == n0 ? c - i : c + 1);
+            else if (l == 1) cn = (j + 1 == n1 ? c - (long long)j * n0 : c + n0);
+            else cn = (k + 1 == n2 ? c - (long long)k * n0 * n1 : c + (long long)n0 * n1);
+            const double un = (double)u[cn];
+            const double v = P.alpha_int(l, uc, un) / I.dx[l] + I.kmax / (I.dx[l] * I.dx[l]);
+            w = fmax(w, v);
+        }
+    }
+    atomic_max_wave(&st[ch.x].wmax, w);
+    if (bad) atomicOr(&st[ch.x].flags, 1u);
+}
+
+__global__ void finalize_kernel(int n_inst, const InstDev *inst, const StepCtl *ctl, const double *dtp, InstState *st)
+{
+    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n_inst; i += blockDim.x * gridDim.x) {
+        const double te = ctl->t_end;
+        double dt;
+        if (ctl->prescribed) {
+            dt = dtp[i];
+        } else {
+            const double w = __longlong_as_double((long long)st[i].wmax);
+            dt = w > 0.0 ? inst[i].cfl / w : (te > 0.0 ? te - st[i].t : 0.0);
+        }
+        st[i].wmax = 0ull;
+        if (te > 0.0) {
+            const double rem = te - st[i].t;
+            if (rem <= 1e-12 * te) dt = 0.0;  // remainder is rounding, not a step
+            else if (dt > rem) dt = rem;
+        }
+        st[i].dt = dt;
+        st[i].t += dt;
+        if (dt > 0.0) st[i].steps++;
+    }
+}
+
+template <class T>
+__global__ void copy_kernel(const T *__restrict__ src, T *__restrict__ dst, long long n)
+{
+    for (long long i = threadIdx.x + (long long)blockIdx.x * blockDim.x; i < n; i += (long long)blockDim.x * gridDim.x)
+        dst[i] = src[i];
+}
+
+// Block partials in fixed order, then one block reduces them in fixed order:
+// the result is bitwise reproducible.
+template <class T>
+__global__ void __launch_bounds__(256) norms_kernel(const T *block, long long ncell, long long kstride, int nkinds,
+                                                    double *partials)
+{
+    __shared__ double sh[9][256];
+    double s1 = 0, sa = 0, s2 = 0, mx = 0, amin = DBL_MAX, amax = -DBL_MAX, pmin = DBL_MAX, pmax = -DBL_MAX, nbad = 0;
+    for (long long c = threadIdx.x + (long long)blockIdx.x * 256; c < ncell; c += (long long)gridDim.x * 256) {
+        const double u = (double)block[c];
+        if (!isfinite(u)) nbad += 1;
+        s1 += u;
+        sa += fabs(u);
+        s2 += u * u;
+        mx = fmax(mx, fabs(u));
+        amin = fmin(amin, u);
+        amax = fmax(amax, u);
+        for (int z = 1; z < nkinds; z++) {
+            const double v = (double)block[z * kstride + c];
+            if (!isfinite(v)) nbad += 1;
+            pmin = fmin(pmin, v);
+            pmax = fmax(pmax, v);
+        }
+    }
+    double vals[9] = {s1, sa, s2, mx, amin, amax, pmin, pmax, nbad};
+    for (int q = 0; q < 9; q++) sh[q][threadIdx.x] = vals[q];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const int t = threadIdx.x;
+            sh[0][t] += sh[0][t + w];
+            sh[1][t] += sh[1][t + w];
+            sh[2][t] += sh[2][t + w];
+            sh[3][t] = fmax(sh[3][t], sh[3][t + w]);
+            sh[4][t] = fmin(sh[4][t], sh[4][t + w]);
+            sh[5][t] = fmax(sh[5][t], sh[5][t + w]);
+            sh[6][t] = fmin(sh[6][t], sh[6][t + w]);
+            sh[7][t] = fmax(sh[7][t], sh[7][t + w]);
+            sh[8][t] += sh[8][t + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 9) partials[blockIdx.x * 9 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void norms_final_kernel(const double *partials, int nblocks, double *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double r[9] = {0, 0, 0, 0, DBL_MAX, -DBL_MAX, DBL_MAX, -DBL_MAX, 0};
+    for (int b = 0; b < nblocks; b++) {
+        const double *p = partials + 9 * b;
+        r[0] += p[0];
+        r[1] += p[1];
+        r[2] += p[2];
+        r[3] = fmax(r[3], p[3]);
+        r[4] = fmin(r[4], p[4]);
+        r[5] = fmax(r[5], p[5]);
+        r[6] = fmin(r[6], p[6]);
+        r[7] = fmax(r[7], p[7]);
+        r[8] += p[8];
+    }
+    for (int q = 0; q < 9; q++) out[q] = r[q];
+}
+
+hipError_t wavespeed_launch(int dim, int prec, const InstDev *inst, const int2 *chunks, int nchunks, const void *U,
+                            InstState *st, hipStream_t s)
+{
+    if (nchunks <= 0) return hipSuccess;
+    if (prec == 32)
+        hipLaunchKernelGGL(wavespeed_kernel<float>, dim3(nchunks), dim3(256), 0, s, inst, chunks, (const float *)U, st,
+                           dim);
+    else
+        hipLaunchKernelGGL(wavespeed_kernel<double>, dim3(nchunks), dim3(256), 0, s, inst, chunks, (const double *)U,
+                           st, dim);
+    return hipGetLastError();
+}
+
+hipError_t finalize_launch(int n_inst, const InstDev *inst, const StepCtl *ctl, const double *dtp, InstState *st,
+                           hipStream_t s)
+{
+    int nb = (n_inst + 255) / 256;
+    hipLaunchKernelGGL(finalize_kernel, dim3(nb), dim3(256), 0, s, n_inst, inst, ctl, dtp, st);
+    return hipGetLastError();
+}
+
+hipError_t copy_launch(int prec, const void *src, void *dst, long long n, hipStream_t s)
+{
+    long long nb = (n + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    if (nb < 1) nb = 1;
+    if (prec == 32)
+        hipLaunchKernelGGL(copy_kernel<float>, dim3((unsigned)nb), dim3(256), 0, s, (const float *)src, (float *)dst, n);
+    else
+        hipLaunchKernelGGL(copy_kernel<double>, dim3((unsigned)nb), dim3(256), 0, s, (const double *)src,
+                           (double *)dst, n);
+    return hipGetLastError();
+}
+
+hipError_t norms_launch(int prec, const void *block, long long ncell, long long kstride, int nkinds, double *partials,
+                        double *out, hipStream_t s)
+{
+    if (prec == 32)
+        hipLaunchKernelGGL(norms_kernel<float>, dim3(kNormBlocks), dim3(256), 0, s, (const float *)block, ncell,
+                           kstride, nkinds, partials);
+    else
+        hipLaunchKernelGGL(norms_kernel<double>, dim3(kNormBlocks), dim3(256), 0, s, (const double *)block, ncell,
+                           kstride, nkinds, partials);
+    hipLaunchKernelGGL(norms_final_kernel, dim3(1), dim3(64), 0, s, partials, kNormBlocks, out);
+    return hipGetLastError();
+}
+
+}  // namespace af4
+
+#include "variants.h"
+
+namespace af4 {
+
+int stage_num_variants(int dim)
+{
+    int n = 0;
+#define AF4_COUNT(V, TX, TY, TZ, NT, NAME) n++;
+    if (dim == 1) { AF4_VARIANTS_D1(AF4_COUNT) }
+    if (dim == 2) { AF4_VARIANTS_D2(AF4_COUNT) }
+    if (dim == 3) { AF4_VARIANTS_D3(AF4_COUNT) }
+#undef AF4_COUNT
+    return n;
+}
+
+VariantInfo stage_variant(int dim, int v)
+{
+    VariantInfo r = {{1, 1, 1}, 0, ""};
+#define AF4_INFO(V, TX, TY, TZ, NT, NAME) \
+    if (v == V) r = VariantInfo{{TX, TY, TZ}, NT, NAME};
+    if (dim == 1) { AF4_VARIANTS_D1(AF4_INFO) }
+    if (dim == 2) { AF4_VARIANTS_D2(AF4_INFO) }
+    if (dim == 3) { AF4_VARIANTS_D3(AF4_INFO) }
+#undef AF4_INFO
+    for (int l = dim; l < 3; l++) r.tile[l] = 1;
+    return r;
+}
+
+bool stage_supported(int dim, int prec, bool lim, bool si, int variant)
+{
+    if (dim == 1) return stage_supported_d1(prec, lim, si, variant);
+    if (dim == 2) return stage_supported_d2(prec, lim, si, variant);
+    if (dim == 3) return stage_supported_d3(prec, lim, si, variant);
+    return false;
+}
+
+hipError_t stage_launch(int dim, int prec, bool lim, bool si, int variant, int nblocks, const void *params,
+                        hipStream_t s)
+{
+    if (dim == 1) return stage_launch_d1(prec, lim, si, variant, nblocks, params, s);
+    if (dim == 2) return stage_launch_d2(prec, lim, si, variant, nblocks, params, s);
+    if (dim == 3) return stage_launch_d3(prec, lim, si, variant, nblocks, params, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace af4

@@ -1,0 +1,49 @@
+// launch.h -- kernel launch entry points used by the host runtime.
+#pragma once
+#include "af_internal.h"
+
+namespace af4 {
+
+struct VariantInfo {
+    int tile[3];
+    int nt;
+    const char *name;
+};
+
+int stage_num_variants(int dim);
+VariantInfo stage_variant(int dim, int v);
+
+// One stage launch over nblocks (instance, tile) work items.
+// params points to a StageParams<float> or StageParams<double>.
+// Returns hipErrorInvalidValue for a combination that is not built.
+hipError_t stage_launch(int dim, int prec, bool lim, bool si, int variant, int nblocks, const void *params,
+                        hipStream_t s);
+// true if the (dim, prec, lim, si, variant) kernel is built (LDS fits)
+bool stage_supported(int dim, int prec, bool lim, bool si, int variant);
+bool stage_supported_d1(int prec, bool lim, bool si, int variant);
+bool stage_supported_d2(int prec, bool lim, bool si, int variant);
+bool stage_supported_d3(int prec, bool lim, bool si, int variant);
+hipError_t stage_launch_d1(int prec, bool lim, bool si, int variant, int nblocks, const void *params, hipStream_t s);
+hipError_t stage_launch_d2(int prec, bool lim, bool si, int variant, int nblocks, const void *params, hipStream_t s);
+hipError_t stage_launch_d3(int prec, bool lim, bool si, int variant, int nblocks, const void *params, hipStream_t s);
+
+// FP64 max over faces of alpha_l/dx_l + kappa_max/dx_l^2 of the averages of
+// U (per instance, into InstState::wmax), plus the divergence check.
+constexpr int kWaveChunk = 2048;  // cells per wave-speed block
+hipError_t wavespeed_launch(int dim, int prec, const InstDev *inst, const int2 *chunks, int nchunks, const void *U,
+                            InstState *st, hipStream_t s);
+
+// dt and t of every instance from the wave speeds (or the prescribed steps).
+hipError_t finalize_launch(int n_inst, const InstDev *inst, const StepCtl *ctl, const double *dtp, InstState *st,
+                           hipStream_t s);
+
+// dst = src over n values.
+hipError_t copy_launch(int prec, const void *src, void *dst, long long n, hipStream_t s);
+
+// FP64 norms of one instance: out[0..9] = sum u, sum |u|, sum u^2, max |u|,
+// min avg, max avg, min pv, max pv, nonfinite count, (unused).
+constexpr int kNormBlocks = 240;
+hipError_t norms_launch(int prec, const void *block, long long ncell, long long kstride, int nkinds, double *partials,
+                        double *out, hipStream_t s);
+
+}  // namespace af4

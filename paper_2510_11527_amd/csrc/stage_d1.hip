@@ -1,0 +1,77 @@
+// stage_d1.hip -- instantiations and dispatch of the 1D stage kernels.
+#include "stage_kernel.hpp"
+#include "variants.h"
+
+namespace af4 {
+
+namespace {
+
+template <class T, bool LIM, bool SI, int TX, int TY, int TZ, int NT>
+hipError_t launch_one(int nblocks, const void *params, hipStream_t s)
+{
+    if constexpr (stage_lds_bytes<1, T, LIM, SI, TX, TY, TZ>() > 160L * 1024L) {
+        return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((stage_kernel<1, T, LIM, SI, TX, TY, TZ, NT>), dim3(nblocks), dim3(NT), 0, s,
+                           *(const StageParams<T> *)params);
+        return hipGetLastError();
+    }
+}
+
+template <int TX, int TY, int TZ, int NT>
+hipError_t launch_tile(int prec, bool lim, bool si, int nblocks, const void *params, hipStream_t s)
+{
+    if (prec == 32) {
+        if (lim) return si ? launch_one<float, true, true, TX, TY, TZ, NT>(nblocks, params, s)
+                           : launch_one<float, true, false, TX, TY, TZ, NT>(nblocks, params, s);
+        return si ? launch_one<float, false, true, TX, TY, TZ, NT>(nblocks, params, s)
+                  : launch_one<float, false, false, TX, TY, TZ, NT>(nblocks, params, s);
+    }
+    if (lim) return si ? launch_one<double, true, true, TX, TY, TZ, NT>(nblocks, params, s)
+                       : launch_one<double, true, false, TX, TY, TZ, NT>(nblocks, params, s);
+    return si ? launch_one<double, false, true, TX, TY, TZ, NT>(nblocks, params, s)
+              : launch_one<double, false, false, TX, TY, TZ, NT>(nblocks, params, s);
+}
+
+template <int TX, int TY, int TZ>
+bool fits(int prec, bool lim, bool si)
+{
+    constexpr long cap = 160L * 1024L;
+    if (prec == 32) {
+        if (lim) return si ? stage_lds_bytes<1, float, true, true, TX, TY, TZ>() <= cap
+                           : stage_lds_bytes<1, float, true, false, TX, TY, TZ>() <= cap;
+        return si ? stage_lds_bytes<1, float, false, true, TX, TY, TZ>() <= cap
+                  : stage_lds_bytes<1, float, false, false, TX, TY, TZ>() <= cap;
+    }
+    if (lim) return si ? stage_lds_bytes<1, double, true, true, TX, TY, TZ>() <= cap
+                       : stage_lds_bytes<1, double, true, false, TX, TY, TZ>() <= cap;
+    return si ? stage_lds_bytes<1, double, false, true, TX, TY, TZ>() <= cap
+              : stage_lds_bytes<1, double, false, false, TX, TY, TZ>() <= cap;
+}
+
+}  // namespace
+
+bool stage_supported_d1(int prec, bool lim, bool si, int variant)
+{
+    switch (variant) {
+#define AF4_FITS(V, TX, TY, TZ, NT, NAME) \
+    case V: return fits<TX, TY, TZ>(prec, lim, si);
+        AF4_VARIANTS_D1(AF4_FITS)
+#undef AF4_FITS
+    }
+    return false;
+}
+
+hipError_t stage_launch_d1(int prec, bool lim, bool si, int variant, int nblocks, const void *params, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    switch (variant) {
+#define AF4_CASE(V, TX, TY, TZ, NT, NAME) \
+    case V: return launch_tile<TX, TY, TZ, NT>(prec, lim, si, nblocks, params, s);
+        AF4_VARIANTS_D1(AF4_CASE)
+#undef AF4_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace af4

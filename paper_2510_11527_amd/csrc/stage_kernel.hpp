@@ -1,0 +1,604 @@
+// stage_kernel.hpp -- fused forward-Euler / SSP-RK3 stage kernel of the compact
+// fourth-order doubly conservative active flux method with monolithic convex
+// limiting (J. Duan, arXiv 2510.11527), for gfx950.
+//
+// One workgroup owns a tile of cells of one instance.  It stages the tile and
+// a halo of the input state in LDS as a "half grid": along every axis the
+// points x_{i-1/2}, x_i, x_{i+1/2}, ... are spaced dx/2 apart, so that all
+// operators of Sec. 2 and their multi-D half-index shifts (Sec. 4) become
+// 5-point stencils along one axis.  Cell centres (not DoFs) are reconstructed
+// in LDS by inverting the tensor Simpson rule.  The kernel then computes, in
+// LDS phases separated by barriers:
+//   * point values: the biased 4th-order FVS convection operator with the
+//     downwind point, in the exact equivalent form
+//       D+ f^+ + D- f^- = [ (f_{-2} - 8 f_{-1} + 8 f_1 - f_2)
+//                            + alpha (z_{-2} - 4 z_{-1} + 6 z_0 - 4 z_1 + z_2) ] / (6 dx),
+//     plus the compact D^{2,4th} on a(u), then projection onto [umin, umax];
+//   * averages: the doubly conservative update with Simpson face fluxes and
+//     cell-centred potentials, limited by the monolithic convex limiter
+//     against the LLF low-order scheme (Sec. 5.1.1 and 5.2.1);
+//   * the SSP-RK3 convex combination with U^n and the bound safeguard;
+// and writes the new DoFs of its tile.  Halo values are recomputed, never
+// exchanged, so one launch is one stage over all instances.
+#pragma once
+#include "af_internal.h"
+
+namespace af4 {
+
+// AF kind codes (same numbering as the public header)
+enum : int { kFLinear = 0, kFQuad = 1, kFBL = 2, kFBLGrav = 3 };
+enum : int { kALinear = 0, kAPower = 1, kADeadzone = 2, kABL = 3, kARamp2 = 4 };
+
+template <class T>
+struct Phys {
+    int fk[3];
+    T fc[3], fg[3];
+    int ak, am;
+    T a0, a1;
+    T umin, umax;
+    int nc[3];
+    const InstDev *ip;   // critical points are read from here (uniform loads)
+
+    __device__ void load(const InstDev &I, int D)
+    {
+        ip = &I;
+        for (int l = 0; l < 3; l++) {
+            fk[l] = I.fk[l];
+            fc[l] = (T)I.fp0[l];
+            fg[l] = (T)I.fp1[l];
+            nc[l] = l < D ? I.ncrit[l] : 0;
+        }
+        ak = I.ak;
+        am = I.am;
+        a0 = (T)I.ap0;
+        a1 = (T)I.ap1;
+        umin = (T)I.umin;
+        umax = (T)I.umax;
+    }
+
+    // f_l(u)
+    __device__ __forceinline__ T f(int l, T u) const
+    {
+        const int k = fk[l];
+        if (k == kFQuad) return fc[l] * u * u;
+        if (k == kFLinear) return fc[l] * u;
+        T v = T(1) - u;
+        T q = u * u / (u * u + v * v);
+        if (k == kFBL) return q;
+        return q * (T(1) - fg[l] * v * v);
+    }
+
+    // |f_l'(u)|
+    __device__ __forceinline__ T adf(int l, T u) const
+    {
+        const int k = fk[l];
+        if (k == kFQuad) return fabs(T(2) * fc[l] * u);
+        if (k == kFLinear) return fabs(fc[l]);
+        T v = T(1) - u;
+        T den = u * u + v * v;
+        T d1 = T(2) * u * v / (den * den);
+        if (k == kFBL) return fabs(d1);
+        T q = u * u / den;
+        return fabs(d1 * (T(1) - fg[l] * v * v) + q * T(2) * fg[l] * v);
+    }
+
+    // a(u)
+    __device__ __forceinline__ T a(T u) const
+    {
+        switch (ak) {
+        case kALinear: return a0 * u;
+        case kAPower: {
+            if (am > 0) {
+                T r = u;
+                for (int i = 1; i < am; i++) r *= u;
+                return a0 * r;
+            }
+            return a0 * pow(u, a1);
+        }
+        case kADeadzone: {
+            T m = fabs(u) - a1;
+            if (!(m > T(0))) return T(0);
+            return u > T(0) ? a0 * m : -a0 * m;
+        }
+        case kABL:
+            if (u < T(0)) return T(0);
+            if (u > T(1)) return a0 * T(2.0 / 3.0);
+            return a0 * (T(2) * u * u - T(4.0 / 3.0) * u * u * u);
+        default: {
+            T m = u - a1;
+            return m > T(0) ? T(0.5) * a0 * m * m : T(0);
+        }
+        }
+    }
+
+    // max of |f_l'| over [min(x,y), max(x,y)]: end points and interior local
+    // maxima of |f_l'|
+    __device__ __forceinline__ T alpha_int(int l, T x, T y) const
+    {
+        T lo = fmin(x, y), hi = fmax(x, y);
+        T r = fmax(adf(l, lo), adf(l, hi));
+        const int n = nc[l];
+        for (int c = 0; c < n; c++) {
+            const T cv = (T)ip->crit[l][c];
+            if (cv >= lo && cv <= hi) r = fmax(r, adf(l, cv));
+        }
+        return r;
+    }
+};
+
+// Theta(zL, zH) of Sec. 5.1.1: largest t in [0,1] with (1-t) zL + t zH in bounds
+template <class T>
+__device__ __forceinline__ T Theta(T zL, T zH, T umin, T umax)
+{
+    T t;
+    if (zH < umin) t = (zL - umin) / (zL - zH);
+    else if (zH > umax) t = (zL - umax) / (zL - zH);
+    else return T(1);
+    return t > T(0) ? fmin(t, T(1)) : T(0);
+}
+
+template <class T>
+__device__ __forceinline__ T clampb(T v, T lo, T hi) { return fmin(fmax(v, lo), hi); }
+
+// Tile geometry.  Axes beyond D have extent 1 and no halo.
+template <int D, int TX, int TY, int TZ, int HL>
+struct Geo {
+    static constexpr int T0 = TX, T1 = D >= 2 ? TY : 1, T2 = D >= 3 ? TZ : 1;
+    static constexpr int H0 = HL, H1 = D >= 2 ? HL : 0, H2 = D >= 3 ? HL : 0;
+    static constexpr int R0 = T0 + 2 * H0, R1 = T1 + 2 * H1, R2 = T2 + 2 * H2;
+    static constexpr int G0 = 2 * R0, G1 = D >= 2 ? 2 * R1 : 1, G2 = D >= 3 ? 2 * R2 : 1;
+    static constexpr int NCELL = R0 * R1 * R2;
+    static constexpr int NHG = G0 * G1 * G2;
+    static constexpr int NTILE = T0 * T1 * T2;
+    static constexpr int t(int l) { return l == 0 ? T0 : (l == 1 ? T1 : T2); }
+    static constexpr int h(int l) { return l == 0 ? H0 : (l == 1 ? H1 : H2); }
+    // per-direction line arrays: faces (extent t+3 along l), cells (t+2)
+    static constexpr int nface(int l) { return l < D ? (t(l) + 3) * (NTILE / t(l)) : 0; }
+    static constexpr int ncl(int l) { return l < D ? (t(l) + 2) * (NTILE / t(l)) : 0; }
+    static constexpr int face_off(int l) { return l == 0 ? 0 : (l == 1 ? nface(0) : nface(0) + nface(1)); }
+    static constexpr int cell_off(int l) { return l == 0 ? 0 : (l == 1 ? ncl(0) : ncl(0) + ncl(1)); }
+    static constexpr int NFACE = nface(0) + nface(1) + nface(2);
+    static constexpr int NCL = ncl(0) + ncl(1) + ncl(2);
+    // SI boxes: s on [h-1, h+t+1)^D, s~ of direction l on [h-2,h+t+2) along l
+    static constexpr int sb(int l) { return l < D ? t(l) + 2 : 1; }
+    static constexpr int NSB = sb(0) * sb(1) * sb(2);
+    static constexpr int NST = (sb(0) + 2) * sb(1) * sb(2) + (D >= 2 ? sb(0) * (sb(1) + 2) * sb(2) : 0) +
+                               (D >= 3 ? sb(0) * sb(1) * (sb(2) + 2) : 0);
+    static constexpr int st_off(int l)
+    {
+        return l == 0 ? 0 : (l == 1 ? (sb(0) + 2) * sb(1) * sb(2) : (sb(0) + 2) * sb(1) * sb(2) + sb(0) * (sb(1) + 2) * sb(2));
+    }
+    __device__ static __forceinline__ int cidx(int x, int y, int z) { return x + R0 * (y + R1 * z); }
+    __device__ static __forceinline__ int hidx(int x, int y, int z) { return x + G0 * (y + G1 * z); }
+};
+
+// Loop over a box of extents E0 x E1 x E2, x fastest, spread over NT threads.
+template <int E0, int E1, int E2, int NT, class F>
+__device__ __forceinline__ void box_loop(F &&fn)
+{
+    constexpr int N = E0 * E1 * E2;
+    for (int idx = (int)threadIdx.x; idx < N; idx += NT) {
+        int x = idx % E0;
+        int r = idx / E0;
+        int y = r % E1;
+        int z = r / E1;
+        fn(x, y, z);
+    }
+}
+
+__device__ __forceinline__ int wrap_index(int v, int n)
+{
+    while (v < 0) v += n;
+    while (v >= n) v -= n;
+    return v;
+}
+
+// half-shift mask of the DoF kind z (zeta order of Sec. 4)
+template <int D>
+__device__ __forceinline__ constexpr int zeta_mask(int z)
+{
+    return D == 3 ? (z == 3 ? 4 : (z == 4 ? 3 : z)) : z;
+}
+
+template <class T>
+__device__ __forceinline__ T rk_combine(int stage, T fe, T un)
+{
+    // U2 = 3/4 U^n + 1/4 FE(U1), U^{n+1} = 1/3 U^n + 2/3 FE(U2), written so
+    // that the weights sum to one exactly
+    if (stage == 2) return un + T(0.25) * (fe - un);
+    if (stage == 3) return un + T(2.0 / 3.0) * (fe - un);
+    return fe;
+}
+
+// Wave-wide max of a non-negative double, then one atomic per wave.
+__device__ __forceinline__ void atomic_max_wave(unsigned long long *dst, double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0 && v > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(v));
+}
+
+template <int D, class T, bool LIM, bool SI, int TX, int TY, int TZ, int NT>
+__global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
+{
+    constexpr int HL = SI ? 3 : 2;
+    using G = Geo<D, TX, TY, TZ, HL>;
+    constexpr int NB = 1 << D;
+
+    __shared__ T ub[G::NCELL];
+    __shared__ T hg[G::NHG];
+    __shared__ T fl[G::NFACE];                 // flux used in the update, per face
+    __shared__ T ulp[LIM ? G::NFACE : 1];      // u^{L,+} of the left cell of a face
+    __shared__ T ulm[LIM ? G::NFACE : 1];      // u^{L,-} of the right cell of a face
+    __shared__ T pc[G::NCL];                   // potential used in the update, per cell
+    __shared__ T ssm[SI ? D * G::NSB : 1];     // smoothed indicator s_l
+    __shared__ T stl[SI ? G::NST : 1];         // raw indicator s~_l
+
+    // block -> (instance, tile); consecutive logical tiles on the same XCD
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
+    const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3);
+    const int2 wk = p.work[logical];
+    const InstDev &I = p.inst[wk.x];
+    const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2];
+    const int tx = wk.y % I.tiles[0];
+    const int ty = (wk.y / I.tiles[0]) % I.tiles[1];
+    const int tz = wk.y / (I.tiles[0] * I.tiles[1]);
+    const int ox = tx * G::T0, oy = ty * G::T1, oz = tz * G::T2;
+    const long long kst = I.kstride;
+    const T *__restrict__ in = p.in + I.off;
+    const T *__restrict__ un = p.un + I.off;
+    T *__restrict__ out = p.out + I.off;
+    const bool residual = p.stage == 4;
+    const double dtd = p.st[wk.x].dt;
+
+    if (!residual && dtd == 0.0) {
+        // the instance has reached its end time: the stage leaves it unchanged
+        box_loop<G::T0, G::T1, G::T2, NT>([&](int i, int j, int k) {
+            if (ox + i >= n0 || oy + j >= n1 || oz + k >= n2) return;
+            long long gi = (ox + i) + (long long)n0 * ((oy + j) + (long long)n1 * (oz + k));
+            for (int z = 0; z < NB; z++) out[z * kst + gi] = in[z * kst + gi];
+        });
+        return;
+    }
+
+    Phys<T> P;
+    P.load(I, D);
+    const T dt = (T)dtd;
+    const T K = T(2 * D);
+    T idx1[3], idx2[3], i6dx[3], mu[3], nu[3];
+#pragma unroll
+    for (int l = 0; l < 3; l++) {
+        idx1[l] = (T)(1.0 / I.dx[l]);
+        idx2[l] = (T)(1.0 / (I.dx[l] * I.dx[l]));
+        i6dx[l] = (T)(1.0 / (6.0 * I.dx[l]));
+        mu[l] = (T)(dtd / I.dx[l]);
+        nu[l] = (T)(dtd / (I.dx[l] * I.dx[l]));
+    }
+
+    // ---- A: stage tile + halo (averages -> ub, point values -> half grid)
+    box_loop<G::R0, G::R1, G::R2, NT>([&](int x, int y, int z) {
+        int gx = wrap_index(ox + x - G::H0, n0);
+        int gy = D >= 2 ? wrap_index(oy + y - G::H1, n1) : 0;
+        int gz = D >= 3 ? wrap_index(oz + z - G::H2, n2) : 0;
+        long long gi = gx + (long long)n0 * (gy + (long long)n1 * gz);
+        ub[G::cidx(x, y, z)] = in[gi];
+#pragma unroll
+        for (int zk = 1; zk < NB; zk++) {
+            const int m = zeta_mask<D>(zk);
+            hg[G::hidx(2 * x + (m & 1), 2 * y + ((m >> 1) & 1), 2 * z + ((m >> 2) & 1))] = in[zk * kst + gi];
+        }
+    });
+    __syncthreads();
+
+    // ---- B: cell centres on [h-1, h+t+1)^D (inverse tensor Simpson)
+    {
+        constexpr int E0 = G::T0 + 2, E1 = D >= 2 ? G::T1 + 2 : 1, E2 = D >= 3 ? G::T2 + 2 : 1;
+        constexpr int L0 = G::H0 - 1, L1 = D >= 2 ? G::H1 - 1 : 0, L2 = D >= 3 ? G::H2 - 1 : 0;
+        constexpr T S = D == 1 ? T(6) : (D == 2 ? T(36) : T(216));
+        constexpr T iW = D == 1 ? T(0.25) : (D == 2 ? T(0.0625) : T(0.015625));
+        box_loop<E0, E1, E2, NT>([&](int i, int j, int k) {
+            const int x = i + L0, y = j + L1, z = k + L2;
+            T acc = S * ub[G::cidx(x, y, z)];
+#pragma unroll
+            for (int oz = (D >= 3 ? -1 : 0); oz <= (D >= 3 ? 1 : 0); oz++)
+#pragma unroll
+                for (int oy = (D >= 2 ? -1 : 0); oy <= (D >= 2 ? 1 : 0); oy++)
+#pragma unroll
+                    for (int oxx = -1; oxx <= 1; oxx++) {
+                        if (oxx == 0 && oy == 0 && oz == 0) continue;
+                        const T w = T((oxx == 0 ? 4 : 1) * (D >= 2 && oy == 0 ? 4 : 1) * (D >= 3 && oz == 0 ? 4 : 1));
+                        acc -= w * hg[G::hidx(2 * x + oxx, 2 * y + oy, 2 * z + oz)];
+                    }
+            hg[G::hidx(2 * x, 2 * y, 2 * z)] = acc * iW;
+        });
+    }
+
+    // ---- B': smoothness indicators (Sec. 5.1.3, direction by direction)
+    if constexpr (SI) {
+#pragma unroll
+        for (int l = 0; l < D; l++) {
+            // s~_l on the box extended by one more cell along l
+            const int e0 = G::sb(0) + (l == 0 ? 2 : 0), e1 = G::sb(1) + (l == 1 ? 2 : 0);
+            const int ne = e0 * e1 * (G::sb(2) + (l == 2 ? 2 : 0));
+            for (int id = (int)threadIdx.x; id < ne; id += NT) {
+                int i = id % e0, r = id / e0, j = r % e1, k = r / e1;
+                int x = i + G::H0 - 1 - (l == 0), y = j + (D >= 2 ? G::H1 - 1 : 0) - (l == 1), z = k + (D >= 3 ? G::H2 - 1 : 0) - (l == 2);
+                const int sx = l == 0, sy = l == 1, sz = l == 2;
+                T um = ub[G::cidx(x - sx, y - sy, z - sz)], u0 = ub[G::cidx(x, y, z)], up = ub[G::cidx(x + sx, y + sy, z + sz)];
+                stl[G::st_off(l) + id] = fabs(um - T(2) * u0 + up) / (fabs(um) + T(2) * fabs(u0) + fabs(up) + T(1e-13));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < D; l++) {
+            const int e0 = G::sb(0) + (l == 0 ? 2 : 0), e1 = G::sb(1) + (l == 1 ? 2 : 0);
+            box_loop<G::sb(0), G::sb(1), G::sb(2), NT>([&](int i, int j, int k) {
+                const int si = i + (l == 0), sj = j + (l == 1), sk = k + (l == 2);
+                const int st = l == 0 ? 1 : (l == 1 ? e0 : e0 * e1);
+                const int c = G::st_off(l) + si + e0 * (sj + e1 * sk);
+                ssm[l * G::NSB + i + G::sb(0) * (j + G::sb(1) * k)] = (stl[c - st] + T(4) * stl[c] + stl[c + st]) * T(1.0 / 6.0);
+            });
+        }
+    }
+    __syncthreads();
+
+    // s_l at region cell (x, y, z) (inside the s box)
+    auto s_at = [&](int l, int x, int y, int z) -> T {
+        return ssm[l * G::NSB + (x - (G::H0 - 1)) +
+                   G::sb(0) * ((D >= 2 ? y - (G::H1 - 1) : 0) + G::sb(1) * (D >= 3 ? z - (G::H2 - 1) : 0))];
+    };
+    const T gam = (T)I.si_gamma;
+
+    double clamp_mag = 0.0;
+    bool bad = false;
+
+    // ---- C: point values of the tile (Eq. 2d_af_dc, projection Sec. 5.1.2)
+    box_loop<G::T0, G::T1, G::T2, NT>([&](int i, int j, int k) {
+        const bool own = ox + i < n0 && oy + j < n1 && oz + k < n2;
+        const int x = i + G::H0, y = j + G::H1, z = k + G::H2;
+        const long long gi = (ox + i) + (long long)n0 * ((oy + j) + (long long)n1 * (oz + k));
+#pragma unroll
+        for (int zk = 1; zk < NB; zk++) {
+            const int m = zeta_mask<D>(zk);
+            const int px = 2 * x + (m & 1), py = 2 * y + ((m >> 1) & 1), pz = 2 * z + ((m >> 2) & 1);
+            const T u0 = hg[G::hidx(px, py, pz)];
+            T R = T(0);
+#pragma unroll
+            for (int l = 0; l < D; l++) {
+                const int sx = l == 0, sy = l == 1, sz = l == 2;
+                T zz[5], ff[5], aa[5];
+                T alpha = T(0);
+#pragma unroll
+                for (int s = -2; s <= 2; s++) {
+                    zz[s + 2] = hg[G::hidx(px + s * sx, py + s * sy, pz + s * sz)];
+                    ff[s + 2] = P.f(l, zz[s + 2]);
+                    aa[s + 2] = P.a(zz[s + 2]);
+                    alpha = fmax(alpha, P.adf(l, zz[s + 2]));
+                }
+                T conv = -((ff[0] - T(8) * ff[1] + T(8) * ff[3] - ff[4]) +
+                           alpha * (zz[0] - T(4) * zz[1] + T(6) * zz[2] - T(4) * zz[3] + zz[4])) * i6dx[l];
+                if constexpr (SI) {
+                    if (!residual) {
+                        // low-order LLF right-hand side on the half grid; a cell
+                        // average replaces a reconstructed centre
+                        T nm = zz[1], np = zz[3];
+                        if (m == (1 << l)) {
+                            nm = ub[G::cidx(x, y, z)];
+                            np = ub[G::cidx(x + sx, y + sy, z + sz)];
+                        }
+                        const T fm = P.f(l, nm), fp = P.f(l, np);
+                        const T Fr = T(0.5) * (ff[2] + fp) - T(0.5) * alpha * (np - u0);
+                        const T Fl = T(0.5) * (fm + ff[2]) - T(0.5) * alpha * (u0 - nm);
+                        const T convL = -T(2) * idx1[l] * (Fr - Fl);
+                        // mean of s_l over the cells whose closure contains the point
+                        T ssum = T(0);
+                        int cnt = 0;
+#pragma unroll
+                        for (int dz = 0; dz <= ((m >> 2) & 1); dz++)
+#pragma unroll
+                            for (int dy = 0; dy <= ((m >> 1) & 1); dy++)
+#pragma unroll
+                                for (int dxx = 0; dxx <= (m & 1); dxx++) {
+                                    ssum += s_at(l, x + dxx, y + dy, z + dz);
+                                    cnt++;
+                                }
+                        const T th = exp(-gam * ssum / T(cnt));
+                        conv = th * conv + (T(1) - th) * convL;
+                    }
+                }
+                const T d2 = (-(aa[0] + aa[4]) * T(1.0 / 3.0) + (aa[1] + aa[3]) * T(16.0 / 3.0) - T(10) * aa[2]) * idx2[l];
+                R += conv + d2;
+            }
+            if (!own) continue;
+            if (residual) {
+                out[zk * kst + gi] = R;
+                continue;
+            }
+            T v = u0 + dt * R;
+            if (!isfinite(v)) bad = true;
+            if constexpr (LIM) v = clampb(v, P.umin, P.umax);
+            v = rk_combine(p.stage, v, un[zk * kst + gi]);
+            if constexpr (LIM) v = clampb(v, P.umin, P.umax);
+            out[zk * kst + gi] = v;
+        }
+    });
+
+    // ---- D1: per direction, faces and cells of the average update.
+    // Face array of direction l: index f along l <-> left cell h_l - 2 + f,
+    // f in [0, t_l + 3); other axes: own range.  Cell array: index c along l
+    // <-> cell h_l - 1 + c, c in [0, t_l + 2).
+    const bool use_si = SI && !residual;
+#pragma unroll
+    for (int l = 0; l < D; l++) {
+        const int sx = l == 0, sy = l == 1, sz = l == 2;
+        const int E0 = l == 0 ? G::T0 + 3 : G::T0, E1 = l == 1 ? G::T1 + 3 : G::T1, E2 = l == 2 ? G::T2 + 3 : G::T2;
+        const int NF = E0 * E1 * E2;
+        for (int id = (int)threadIdx.x; id < NF; id += NT) {
+            const int i = id % E0, r = id / E0, j = r % E1, k = r / E1;
+            const int fidx = l == 0 ? i : (l == 1 ? j : k);
+            // left cell of the face in region coordinates
+            const int x = i + G::H0 - 2 * sx, y = j + G::H1 - 2 * sy, z = k + G::H2 - 2 * sz;
+            const bool need_hi = fidx >= 1 && fidx < G::t(l) + 2;
+            if (!LIM && !need_hi) continue;
+            const T ua = ub[G::cidx(x, y, z)], ubb = ub[G::cidx(x + sx, y + sy, z + sz)];
+            T fL = T(0), up = T(0), um = T(0);
+            if (LIM || use_si) {
+                const T fa = P.f(l, ua), fb = P.f(l, ubb);
+                const T al = P.alpha_int(l, ua, ubb);
+                fL = T(0.5) * (fa + fb) - T(0.5) * al * (ubb - ua);
+                if constexpr (LIM) {
+                    const T dA = (P.a(ubb) - P.a(ua)) * idx1[l];
+                    const T Km = K * mu[l];
+                    up = ua - Km * (fL - fa) + Km * dA;   // u^{L,+} of the left cell
+                    um = ubb - Km * (fb - fL) - Km * dA;  // u^{L,-} of the right cell
+                    const int fo = G::face_off(l) + id;
+                    ulp[fo] = up;
+                    ulm[fo] = um;
+                }
+            }
+            if (!need_hi) continue;
+            // high-order flux: Simpson average of f_l over the face (Sec. 4)
+            T fH = T(0);
+            {
+                const int bx = 2 * x + sx, by = 2 * y + sy, bz = 2 * z + sz;
+#pragma unroll
+                for (int oz = (D >= 3 && l != 2 ? -1 : 0); oz <= (D >= 3 && l != 2 ? 1 : 0); oz++)
+#pragma unroll
+                    for (int oy = (D >= 2 && l != 1 ? -1 : 0); oy <= (D >= 2 && l != 1 ? 1 : 0); oy++)
+#pragma unroll
+                        for (int oxx = (l != 0 ? -1 : 0); oxx <= (l != 0 ? 1 : 0); oxx++) {
+                            const T w = T((l != 0 && oxx == 0 ? 4 : 1) * (l != 1 && D >= 2 && oy == 0 ? 4 : 1) *
+                                          (l != 2 && D >= 3 && oz == 0 ? 4 : 1));
+                            fH += w * P.f(l, hg[G::hidx(bx + oxx, by + oy, bz + oz)]);
+                        }
+                fH *= D == 1 ? T(1) : (D == 2 ? T(1.0 / 6.0) : T(1.0 / 36.0));
+            }
+            if (use_si) {
+                const T th = exp(-gam * T(0.5) * (s_at(l, x, y, z) + s_at(l, x + sx, y + sy, z + sz)));
+                fH = th * fH + (T(1) - th) * fL;
+            }
+            T F = fH;
+            if constexpr (LIM) {
+                if (!residual) {
+                    const T df = fH - fL;
+                    const T s3 = T(3) * K * mu[l] * df;
+                    const T tc = fmin(Theta(up, up - s3, P.umin, P.umax), Theta(um, um + s3, P.umin, P.umax));
+                    F = fL + tc * df;
+                }
+            }
+            fl[G::face_off(l) + id] = F;
+        }
+    }
+    __syncthreads();
+
+    // ---- D2: per direction, cell-centred potentials (Prop. 2.1 and its
+    // tensor form), limited with theta^d (Sec. 5.1.1 / 5.2.1)
+#pragma unroll
+    for (int l = 0; l < D; l++) {
+        const int sx = l == 0, sy = l == 1, sz = l == 2;
+        const int E0 = l == 0 ? G::T0 + 2 : G::T0, E1 = l == 1 ? G::T1 + 2 : G::T1, E2 = l == 2 ? G::T2 + 2 : G::T2;
+        const int FE0 = l == 0 ? G::T0 + 3 : G::T0, FE1 = l == 1 ? G::T1 + 3 : G::T1;
+        const int NC = E0 * E1 * E2;
+        for (int id = (int)threadIdx.x; id < NC; id += NT) {
+            const int i = id % E0, r = id / E0, j = r % E1, k = r / E1;
+            const int x = i + G::H0 - sx, y = j + G::H1 - sy, z = k + G::H2 - sz;
+            T aH = T(0);
+#pragma unroll
+            for (int oz = (D >= 3 ? -1 : 0); oz <= (D >= 3 ? 1 : 0); oz++)
+#pragma unroll
+                for (int oy = (D >= 2 ? -1 : 0); oy <= (D >= 2 ? 1 : 0); oy++)
+#pragma unroll
+                    for (int oxx = -1; oxx <= 1; oxx++) {
+                        const int ol = l == 0 ? oxx : (l == 1 ? oy : oz);
+                        T w = ol == 0 ? T(8) : T(-1);
+                        if (l != 0) w *= oxx == 0 ? T(4) : T(1);
+                        if (l != 1 && D >= 2) w *= oy == 0 ? T(4) : T(1);
+                        if (l != 2 && D >= 3) w *= oz == 0 ? T(4) : T(1);
+                        aH += w * P.a(hg[G::hidx(2 * x + oxx, 2 * y + oy, 2 * z + oz)]);
+                    }
+            aH *= D == 1 ? T(1.0 / 6.0) : (D == 2 ? T(1.0 / 36.0) : T(1.0 / 216.0));
+            const T aL = P.a(ub[G::cidx(x, y, z)]);
+            if (use_si) {
+                const T th = exp(-gam * s_at(l, x, y, z));
+                aH = th * aH + (T(1) - th) * aL;
+            }
+            T Pv = aH;
+            if constexpr (LIM) {
+                if (!residual) {
+                    // faces c-1/2 and c+1/2 in the face array of direction l
+                    const int f0 = G::face_off(l) + i + FE0 * (j + FE1 * k);
+                    const int step = l == 0 ? 1 : (l == 1 ? FE0 : FE0 * FE1);
+                    const T pL = ulp[f0], mC = ulm[f0];                  // u^{L,+}_{c-1}, u^{L,-}_c
+                    const T pC = ulp[f0 + step], mR = ulm[f0 + step];    // u^{L,+}_c, u^{L,-}_{c+1}
+                    const T da = aH - aL;
+                    const T s3 = T(3) * K * nu[l] * da;
+                    const T td = fmin(fmin(Theta(pL, pL + s3, P.umin, P.umax), Theta(pC, pC - s3, P.umin, P.umax)),
+                                      fmin(Theta(mC, mC - s3, P.umin, P.umax), Theta(mR, mR + s3, P.umin, P.umax)));
+                    Pv = aL + td * da;
+                }
+            }
+            pc[G::cell_off(l) + id] = Pv;
+        }
+    }
+    __syncthreads();
+
+    // ---- D3: averages of the tile (Eq. multid_limited_average; with theta = 1
+    // and no blending this is the high-order update of Eq. 2d_af_dc)
+    box_loop<G::T0, G::T1, G::T2, NT>([&](int i, int j, int k) {
+        if (ox + i >= n0 || oy + j >= n1 || oz + k >= n2) return;
+        const long long gi = (ox + i) + (long long)n0 * ((oy + j) + (long long)n1 * (oz + k));
+        const T u = ub[G::cidx(i + G::H0, j + G::H1, k + G::H2)];
+        T dF = T(0), dP = T(0), rF = T(0), rP = T(0);
+#pragma unroll
+        for (int l = 0; l < D; l++) {
+            const int FE0 = l == 0 ? G::T0 + 3 : G::T0, FE1 = l == 1 ? G::T1 + 3 : G::T1;
+            const int CE0 = l == 0 ? G::T0 + 2 : G::T0, CE1 = l == 1 ? G::T1 + 2 : G::T1;
+            const int fstep = l == 0 ? 1 : (l == 1 ? FE0 : FE0 * FE1);
+            const int cstep = l == 0 ? 1 : (l == 1 ? CE0 : CE0 * CE1);
+            // face c+1/2 has face index t+2 along l for tile index t; cell c has index t+1
+            const int fi = i + (l == 0 ? 2 : 0), fj = j + (l == 1 ? 2 : 0), fk = k + (l == 2 ? 2 : 0);
+            const int ci = i + (l == 0 ? 1 : 0), cj = j + (l == 1 ? 1 : 0), ck = k + (l == 2 ? 1 : 0);
+            const int fo = G::face_off(l) + fi + FE0 * (fj + FE1 * fk);
+            const int co = G::cell_off(l) + ci + CE0 * (cj + CE1 * ck);
+            const T Fp = fl[fo], Fm = fl[fo - fstep];
+            const T Pm = pc[co - cstep], P0 = pc[co], Pp = pc[co + cstep];
+            dF += mu[l] * (Fp - Fm);
+            dP += nu[l] * (Pp - T(2) * P0 + Pm);
+            rF += idx1[l] * (Fp - Fm);
+            rP += idx2[l] * (Pp - T(2) * P0 + Pm);
+        }
+        if (residual) {
+            out[gi] = rP - rF;
+            return;
+        }
+        T v = u - dF + dP;
+        if (!isfinite(v)) bad = true;
+        if constexpr (LIM) {
+            T c = clampb(v, P.umin, P.umax);
+            clamp_mag = fmax(clamp_mag, (double)fabs(c - v));
+            v = c;
+        }
+        v = rk_combine(p.stage, v, un[gi]);
+        if constexpr (LIM) {
+            T c = clampb(v, P.umin, P.umax);
+            clamp_mag = fmax(clamp_mag, (double)fabs(c - v));
+            v = c;
+        }
+        out[gi] = v;
+    });
+    if (!residual) {
+        if (bad) atomicOr(&p.st[wk.x].flags, 1u);
+        if constexpr (LIM) atomic_max_wave(&p.st[wk.x].clampmax, clamp_mag);
+    }
+}
+
+// LDS bytes of a stage-kernel instantiation (used to skip oversized ones)
+template <int D, class T, bool LIM, bool SI, int TX, int TY, int TZ>
+constexpr long stage_lds_bytes()
+{
+    using G = Geo<D, TX, TY, TZ, SI ? 3 : 2>;
+    return (long)sizeof(T) * (G::NCELL + G::NHG + G::NFACE * (LIM ? 3 : 1) + G::NCL + (SI ? D * G::NSB + G::NST : 2));
+}
+
+}  // namespace af4

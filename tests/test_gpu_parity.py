@@ -1,0 +1,258 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 CPU
+oracle on identical seeded inputs.  Bar: relative l1 <= 1e-12 (FP64) and
+<= 1e-5 (FP32, same FP32-rounded inputs), exact bounds with the limiter."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_11527_amd import af
+from paper_2510_11527_amd import workloads as W
+from gpu_common import TOL, gpu_run, oracle_fe, prepare, random_state, rel_l1
+
+pytestmark = pytest.mark.gpu
+
+FLUXES = [("quad", 0.5, 0.0), ("bl", 0.0, 0.0), ("bl_grav", 0.0, 5.0), ("linear", -0.7, 0.0)]
+DIFFS = [("power", 0.05, 2.0), ("deadzone", 0.05, 0.25), ("bl", 0.01, 0.0), ("ramp2", 0.1, 0.3), ("linear", 0.02, 0)]
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def small_spec(d, n, fl, df, limiter=False, si=False, precision=64, cfl=None):
+    return dict(name="t", dim=d, n=[n + l for l in range(d)], lo=[0.0] * d, hi=[1.0 + 0.1 * l for l in range(d)],
+                flux=[fl] * d, diff=df, umin=0.0, umax=1.0, limiter=limiter, si=si, si_gamma=1.0,
+                precision=precision, cfl=cfl or 0.3 / (2 * d))
+
+
+def state_for(spec, rng, smooth=False):
+    d = spec["dim"]
+    N = int(np.prod(spec["n"][:d]))
+    if smooth:
+        g = W.rescale01(W.fourier_dofs(spec, [((1,) * d, 1.0, 0.4), ((2,) + (0,) * (d - 1), 0.3, 1.1)]))
+        return g
+    U = [rng.uniform(0, 1, size=N) for _ in range(2 ** d)]
+    U[0] = np.where(rng.uniform(size=N) < 0.6, U[0], rng.choice([0.0, 1.0], size=N))
+    return U
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("prec", [64, 32])
+def test_residual_matches_oracle(d, prec):
+    rng = np.random.default_rng(10 * d + prec)
+    n = {1: 37, 2: 21, 3: 9}[d]
+    for k in range(4):
+        spec = small_spec(d, n, FLUXES[k], DIFFS[(k + d) % 5], precision=prec)
+        U = state_for(spec, rng, smooth=(k % 2 == 0))
+        s, U = prepare(spec, U, prec)
+        note("residual d=%d prec=%d flux=%s diff=%s n=%s" % (d, prec, FLUXES[k][0], DIFFS[(k + d) % 5][0], s["n"]))
+        ctx = af.Context(s)
+        ctx.set_state(0, U)
+        R = ctx.residual(0)
+        ctx.close()
+        Ro = oracle.rhs(oracle.problem(s), U)
+        err = rel_l1(R, Ro)
+        assert err <= TOL[prec] * (10 if prec == 32 else 1), err
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("lim,si", [(False, False), (True, False), (True, True), (False, True)])
+def test_forward_euler_stage_matches_oracle(d, prec, lim, si):
+    rng = np.random.default_rng(100 * d + prec + 7 * lim + 3 * si)
+    n = {1: 41, 2: 19, 3: 9}[d]
+    for k in range(2):
+        fl, df = FLUXES[(k + d) % 4], DIFFS[(k + 2 * d) % 5]
+        spec = small_spec(d, n, fl, df, limiter=lim, si=si, precision=prec)
+        U = state_for(spec, rng, smooth=(k == 1))
+        s, U = prepare(spec, U, prec)
+        P = oracle.problem(s)
+        dt = oracle.dt_cfl(P, U, s["cfl"])
+        note("fe d=%d prec=%d lim=%d si=%d flux=%s diff=%s dt=%.3e" % (d, prec, lim, si, fl[0], df[0], dt))
+        V, t, used, nrm = gpu_run(s, U, dts=[dt], integrator="euler")
+        Vo, dg = oracle.fe(P, U, dt)
+        err = rel_l1(V, Vo)
+        assert err <= TOL[prec], err
+        if lim:
+            assert min(v.min() for v in V) >= s["umin"] and max(v.max() for v in V) <= s["umax"]
+
+
+def _steps_case(name):
+    if name == "c2":
+        spec, U = W.config2(n=48)
+    elif name == "c3_64":
+        spec, U = W.config3(n=48, precision=64)
+    elif name == "c3_32":
+        spec, U = W.config3(n=48, precision=32)
+    elif name == "c4":
+        spec, U = W.config4(n_inst=3, sizes=(32,))[2]
+    elif name == "c5":
+        spec, U = W.config5(n=12)
+    elif name == "c1":
+        spec, U = W.config1()
+    return spec, U
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3_64", "c3_32", "c4", "c5"])
+def test_ssprk3_steps_match_oracle(name):
+    """Ten SSP-RK3 steps with the oracle's own CFL time steps, prescribed to
+    both sides (the config-like problems at reduced size)."""
+    spec, U = _steps_case(name)
+    prec = spec["precision"]
+    s, U = prepare(spec, U, prec)
+    P = oracle.problem(s)
+    Uo, t, dts = oracle.run(P, U, nsteps=10, cfl=s["cfl"])
+    note("steps %s prec=%d n=%s dt0=%.3e" % (name, prec, s["n"], dts[0]))
+    V, tg, used, nrm = gpu_run(s, U, dts=dts)
+    err = rel_l1(V, Uo)
+    assert err <= TOL[prec], err
+    assert abs(tg - t) <= 1e-15 * max(1.0, t) + 1e-300
+    if s.get("limiter"):
+        assert min(v.min() for v in V) >= s["umin"] and max(v.max() for v in V) <= s["umax"]
+        ulp = np.spacing(np.float32(1.0)) if prec == 32 else np.spacing(1.0)
+        assert nrm["max_clamp"] <= 4 * ulp * max(1.0, abs(s["umax"]), abs(s["umin"]))
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3_32", "c5"])
+def test_cfl_time_step_matches_oracle(name):
+    spec, U = _steps_case(name)
+    prec = spec["precision"]
+    s, U = prepare(spec, U, prec)
+    P = oracle.problem(s)
+    dto = oracle.dt_cfl(P, U, s["cfl"])
+    ctx = af.Context(s)
+    ctx.set_state(0, U)
+    used = ctx.step(1)
+    ctx.close()
+    note("dt %s gpu=%.17g oracle=%.17g" % (name, used[0], dto))
+    assert abs(used[0] - dto) <= (1e-15 if prec == 64 else 1e-6) * dto
+
+
+def test_config1_full_run_matches_exact_and_oracle():
+    spec, U = W.config1()
+    P = oracle.problem(spec)
+    Uo, t, dts = oracle.run(P, U, cfl=spec["cfl"], t_end=spec["t_end"])
+    ctx = af.Context(spec)
+    ctx.set_state(0, U)
+    used = ctx.step(len(dts) + 3, t_end=spec["t_end"])  # extra steps are no-ops
+    V, tg = ctx.get_state(0)
+    nrm = ctx.norms(0)
+    ctx.close()
+    assert abs(tg - 1.0) < 1e-13 and nrm["steps"] == len(dts) == 480
+    assert rel_l1(V, Uo) <= 1e-12
+    ex = W.rescale_free_fourier_1d(spec, spec["phi"], 1.0)
+    assert max(np.abs(a - b).mean() for a, b in zip(V, ex)) < 5e-6
+
+
+def test_divergence_is_reported():
+    spec, U = W.config1(cfl=0.4)
+    ctx = af.Context(spec)
+    ctx.set_state(0, U)
+    with pytest.raises(af.AFError) as e:
+        ctx.step(400)
+    assert e.value.status == af.AF_ERR_NONFINITE
+    ctx.close()
+
+
+def test_argument_validation():
+    spec, U = W.config2(n=16)
+    with pytest.raises(af.AFError) as e:
+        af.Context(dict(spec, cfl=0.3))
+    assert e.value.status == af.AF_ERR_CFL
+    ctx = af.Context(spec)
+    bad = [u.copy() for u in U]
+    bad[1][3] = spec["umax"] + 0.5
+    with pytest.raises(af.AFError) as e:
+        ctx.set_state(0, bad)
+    assert e.value.status == af.AF_ERR_BOUNDS
+    bad[1][3] = math.nan
+    with pytest.raises(af.AFError) as e:
+        ctx.set_state(0, bad)
+    assert e.value.status == af.AF_ERR_NONFINITE
+    with pytest.raises(af.AFError) as e:
+        ctx.step(1)
+    assert e.value.status == af.AF_ERR_STATE
+    ctx.close()
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_tile_variants_bitwise_identical(d):
+    """Every tile shape computes the same per-cell arithmetic: identical bits."""
+    rng = np.random.default_rng(d)
+    n = {1: 300, 2: 70, 3: 20}[d]
+    spec = small_spec(d, n, FLUXES[2 % 4], DIFFS[1], limiter=True, precision=32)
+    U = state_for(spec, rng)
+    s, U = prepare(spec, U, 32)
+    ref = None
+    ctx = af.Context(s)
+    for v in range(ctx.num_variants()):
+        note("variant d=%d %s" % (d, ctx.variant_name(v)))
+        ctx.set_variant(v)
+        ctx.set_state(0, U)
+        ctx.step(2, dt=1e-4)
+        V, _ = ctx.get_state(0)
+        if ref is None:
+            ref = V
+        else:
+            for a, b in zip(V, ref):
+                assert np.array_equal(a, b)
+    ctx.close()
+
+
+def test_graph_equals_eager_and_checkpoint_resume():
+    spec, U = W.config2(n=64)
+    ctx = af.Context(spec)
+    ctx.set_state(0, U)
+    ctx.step(6)                     # one graph launch
+    A, ta = ctx.get_state(0)
+    ctx.set_state(0, U)
+    for _ in range(3):
+        ctx.step(1)                 # eager
+    mid, tm = ctx.get_state(0)
+    ctx.set_state(0, mid, tm)       # checkpoint / resume
+    for _ in range(3):
+        ctx.step(1)
+    B, tb = ctx.get_state(0)
+    ctx.close()
+    assert ta == tb
+    for a, b in zip(A, B):
+        assert np.array_equal(a, b)
+
+
+def test_batched_instances_match_oracle():
+    """Uneven batched instances (config-4 construction, small sizes) in one
+    context: each matches its own oracle run with its own CFL steps."""
+    items = W.config4(n_inst=6, sizes=(16, 24, 40))
+    specs = [s for s, _ in items]
+    ctx = af.Context(specs)
+    for i, (s, U) in enumerate(items):
+        ctx.set_state(i, U)
+    dts = []
+    for _ in range(5):
+        dts.append(ctx.step(1))
+    for i, (s, U) in enumerate(items):
+        V, _ = ctx.get_state(i)
+        P = oracle.problem(s)
+        Uo, _, odts = oracle.run(P, U, dts=[d[i] for d in dts])
+        dto = oracle.dt_cfl(P, U, s["cfl"])
+        assert abs(dts[0][i] - dto) <= 1e-6 * dto
+        assert rel_l1(V, Uo) <= TOL[32]
+    ctx.close()
+
+
+def test_conservation_and_bounds_long_run():
+    spec, U = W.config2(n=96)
+    ctx = af.Context(spec)
+    ctx.set_state(0, U)
+    m0 = ctx.norms(0)["mass"]
+    ctx.step(100)
+    nrm = ctx.norms(0)
+    ctx.close()
+    assert abs(nrm["mass"] - m0) <= 1e-13 * abs(m0)
+    assert nrm["min_avg"] >= spec["umin"] and nrm["max_avg"] <= spec["umax"]
+    assert nrm["min_pv"] >= spec["umin"] and nrm["max_pv"] <= spec["umax"]
+    assert nrm["max_clamp"] <= 4 * np.spacing(1.0)
