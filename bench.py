@@ -45,9 +45,9 @@ def workload(name):
     raise SystemExit("unknown workload " + name)
 
 
-def make_ctx(items, precision=None, variant=None):
+def make_ctx(items, precision=None, variant=None, integrator="ssprk3"):
     from paper_2510_11527_amd import af
-    ctx = af.Context([s for s, _ in items], precision=precision)
+    ctx = af.Context([s for s, _ in items], precision=precision, integrator=integrator)
     if variant is not None:
         ctx.set_variant(variant)
     for i, (_, U) in enumerate(items):
@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--integrator", default="ssprk3", choices=["ssprk3", "euler"],
+                    help="euler: one forward-Euler stage plus a plain state copy per step (profiling reference)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -128,7 +130,7 @@ def main():
     wname, items = workload(args.workload)
     log("workload %s: %d instances generated in %.1f s" % (wname, len(items), time.perf_counter() - t0))
     prec = items[0][0]["precision"]
-    ctx = make_ctx(items, variant=args.variant)
+    ctx = make_ctx(items, variant=args.variant, integrator=args.integrator)
     work = ctx.work()
     variant_name = ctx.variant_name(args.variant if args.variant is not None else 0)
     if args.warmup > 0:
@@ -141,7 +143,8 @@ def main():
     ctx.step(args.steps)
     t2 = time.perf_counter()
     el = t2 - t1
-    stages = 3 * args.steps
+    per_step = 3 if args.integrator == "ssprk3" else 1
+    stages = per_step * args.steps
     value = work["dofs"] * stages / el
     log("timed %d steps in %.4f s" % (args.steps, el))
 
@@ -163,7 +166,7 @@ def main():
             "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == 32 else "f64", "data": "synthetic",
             "config": {"workload": wname, "instances": len(items), "cells": work["cells"], "dofs": work["dofs"],
-                       "integrator": "ssprk3", "limiter": bool(items[0][0]["limiter"]),
+                       "integrator": args.integrator, "limiter": bool(items[0][0]["limiter"]),
                        "si": bool(items[0][0]["si"]), "cfl": items[0][0]["cfl"], "tile": variant_name,
                        "graph": "one hipGraph launch of %d steps" % args.steps},
             "cell_updates_per_s": work["cells"] * stages / el,

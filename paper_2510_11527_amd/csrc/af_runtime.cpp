@@ -22,6 +22,7 @@ using af4::StepCtl;
 
 struct af_ctx {
     int n_inst = 0, dim = 0, prec = 64, lim = 0, si = 0, integ = 0;
+    bool qf = true;   // every flux is linear or quadratic
     std::vector<af_problem> prob;
     std::vector<InstDev> ih;
     std::vector<int> have_state;
@@ -243,12 +244,12 @@ hipError_t launch_stage(af_ctx *c, int in, int out, int stage, bool lim, bool si
         StageParams<float> p = stage_params<float>(c, in, out, stage);
         p.work += wstart;
         p.nwork = wcount;
-        return af4::stage_launch(c->dim, 32, lim, si, c->variant, wcount, &p, c->stream);
+        return af4::stage_launch(c->dim, 32, lim, si, c->qf, c->variant, wcount, &p, c->stream);
     }
     StageParams<double> p = stage_params<double>(c, in, out, stage);
     p.work += wstart;
     p.nwork = wcount;
-    return af4::stage_launch(c->dim, 64, lim, si, c->variant, wcount, &p, c->stream);
+    return af4::stage_launch(c->dim, 64, lim, si, c->qf, c->variant, wcount, &p, c->stream);
 }
 
 // One time step over all instances, enqueued on the context stream.  With
@@ -382,11 +383,14 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
         if (!std::isnan(P.umin) && !std::isnan(P.umax)) derive_bounds_params(I, P, P.dim);
     }
     c->total = off;
+    for (int i = 0; i < n_inst; i++)
+        for (int l = 0; l < c->dim; l++)
+            if (probs[i].flux[l] != AF_F_LINEAR && probs[i].flux[l] != AF_F_QUAD) c->qf = false;
     // default tile variant: the first one built for this combination (the
     // residual kernel, unlimited and unblended, fits wherever the stage does)
     c->variant = -1;
     for (int v = 0; v < af4::stage_num_variants(c->dim); v++)
-        if (af4::stage_supported(c->dim, c->prec, c->lim, c->si, v)) {
+        if (af4::stage_supported(c->dim, c->prec, c->lim, c->si, c->qf, v)) {
             c->variant = v;
             break;
         }
@@ -429,7 +433,11 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
     // wave-speed chunks
     std::vector<int2> chunks;
     for (int i = 0; i < n_inst; i++) {
-        long long nch = (c->ih[i].ncell + af4::kWaveChunk - 1) / af4::kWaveChunk;
+        // whole rows per chunk (the wave-speed kernel walks rows)
+        const InstDev &I = c->ih[i];
+        const long long rows = (long long)I.n[1] * I.n[2];
+        const long long rpc = (af4::kWaveChunk + I.n[0] - 1) / I.n[0];
+        const long long nch = (rows + rpc - 1) / rpc;
         for (long long k = 0; k < nch; k++) chunks.push_back(make_int2(i, (int)k));
     }
     c->nchunks = (int)chunks.size();
@@ -486,7 +494,7 @@ af_status af_set_variant(af_ctx *c, int v)
 {
     if (!c) return AF_ERR_ARG;
     if (v < 0 || v >= af4::stage_num_variants(c->dim)) return fail(c, AF_ERR_ARG, "variant out of range");
-    if (!af4::stage_supported(c->dim, c->prec, c->lim, c->si, v))
+    if (!af4::stage_supported(c->dim, c->prec, c->lim, c->si, c->qf, v))
         return fail(c, AF_ERR_UNSUPPORTED, "tile variant not built for this combination");
     HIPOK(c, hipStreamSynchronize(c->stream));
     drop_graph(c);

@@ -9,6 +9,7 @@ namespace af4 {
 // alpha_l / dx_l + kappa_max / dx_l^2 (Eqs. 1d_av_pp_dt, multid_av_pp_dt), in
 // FP64 from the stored averages, reduced per wave and merged per instance by
 // an integer atomic max on the bit pattern (valid for non-negative doubles).
+// A block covers whole grid rows of one instance (no per-cell division).
 template <class T>
 __global__ void __launch_bounds__(256) wavespeed_kernel(const InstDev *inst, const int2 *chunks, const T *U,
                                                         InstState *st, int dim)
@@ -18,27 +19,29 @@ __global__ void __launch_bounds__(256) wavespeed_kernel(const InstDev *inst, con
     Phys<double> P;
     P.load(I, dim);
     const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2];
+    const int rpc = (kWaveChunk + n0 - 1) / n0;   // rows per chunk
+    const int r0 = ch.y * rpc, r1 = min(r0 + rpc, n1 * n2);
     const T *u = U + I.off;
-    const long long c0 = (long long)ch.y * kWaveChunk;
+    double idx[3], kdx2[3];
+    for (int l = 0; l < 3; l++) {
+        idx[l] = 1.0 / I.dx[l];
+        kdx2[l] = I.kmax * idx[l] * idx[l];
+    }
     const double big = 1e6 * fmax(fmax(fabs(I.umin), fabs(I.umax)), 1.0);
     double w = 0.0;
     bool bad = false;
-    for (int t = threadIdx.x; t < kWaveChunk; t += blockDim.x) {
-        const long long c = c0 + t;
-        if (c >= I.ncell) break;
-        const int i = (int)(c % n0);
-        const long long r = c / n0;
-        const int j = (int)(r % n1), k = (int)(r / n1);
-        const double uc = (double)u[c];
-        if (!(fabs(uc) <= big)) bad = true;  // also catches NaN
-        for (int l = 0; l < dim; l++) {
-            long long cn;
-            if (l == 0) cn = (i + 1 == n0 ? c - i : c + 1);
-            else if (l == 1) cn = (j + 1 == n1 ? c - (long long)j * n0 : c + n0);
-            else cn = (k + 1 == n2 ? c - (long long)k * n0 * n1 : c + (long long)n0 * n1);
-            const double un = (double)u[cn];
-            const double v = P.alpha_int(l, uc, un) / I.dx[l] + I.kmax / (I.dx[l] * I.dx[l]);
-            w = fmax(w, v);
+    for (int r = r0; r < r1; r++) {
+        const int j = r % n1, k = r / n1;
+        const long long row = (long long)n0 * r;
+        const long long rowy = (long long)n0 * ((j + 1 == n1 ? 0 : j + 1) + (long long)n1 * k);
+        const long long rowz = (long long)n0 * (j + (long long)n1 * (k + 1 == n2 ? 0 : k + 1));
+        for (int i = threadIdx.x; i < n0; i += blockDim.x) {
+            const double uc = (double)u[row + i];
+            if (!(fabs(uc) <= big)) bad = true;  // also catches NaN
+            const double ux = (double)u[row + (i + 1 == n0 ? 0 : i + 1)];
+            w = fmax(w, P.alpha_int(0, uc, ux) * idx[0] + kdx2[0]);
+            if (dim >= 2) w = fmax(w, P.alpha_int(1, uc, (double)u[rowy + i]) * idx[1] + kdx2[1]);
+            if (dim >= 3) w = fmax(w, P.alpha_int(2, uc, (double)u[rowz + i]) * idx[2] + kdx2[2]);
         }
     }
     atomic_max_wave(&st[ch.x].wmax, w);
@@ -196,10 +199,12 @@ int stage_num_variants(int dim)
 {
     int n = 0;
 #define AF4_COUNT(V, TX, TY, TZ, NT, NAME) n++;
+#define AF4_COUNT2(V, TX, TY, TZ, NT, KIND, NAME) n++;
     if (dim == 1) { AF4_VARIANTS_D1(AF4_COUNT) }
-    if (dim == 2) { AF4_VARIANTS_D2(AF4_COUNT) }
+    if (dim == 2) { AF4_VARIANTS_D2(AF4_COUNT2) }
     if (dim == 3) { AF4_VARIANTS_D3(AF4_COUNT) }
 #undef AF4_COUNT
+#undef AF4_COUNT2
     return n;
 }
 
@@ -208,27 +213,30 @@ VariantInfo stage_variant(int dim, int v)
     VariantInfo r = {{1, 1, 1}, 0, ""};
 #define AF4_INFO(V, TX, TY, TZ, NT, NAME) \
     if (v == V) r = VariantInfo{{TX, TY, TZ}, NT, NAME};
+#define AF4_INFO2(V, TX, TY, TZ, NT, KIND, NAME) \
+    if (v == V) r = VariantInfo{{TX, TY, TZ}, NT, NAME};
     if (dim == 1) { AF4_VARIANTS_D1(AF4_INFO) }
-    if (dim == 2) { AF4_VARIANTS_D2(AF4_INFO) }
+    if (dim == 2) { AF4_VARIANTS_D2(AF4_INFO2) }
     if (dim == 3) { AF4_VARIANTS_D3(AF4_INFO) }
 #undef AF4_INFO
+#undef AF4_INFO2
     for (int l = dim; l < 3; l++) r.tile[l] = 1;
     return r;
 }
 
-bool stage_supported(int dim, int prec, bool lim, bool si, int variant)
+bool stage_supported(int dim, int prec, bool lim, bool si, bool qf, int variant)
 {
     if (dim == 1) return stage_supported_d1(prec, lim, si, variant);
-    if (dim == 2) return stage_supported_d2(prec, lim, si, variant);
+    if (dim == 2) return stage_supported_d2(prec, lim, si, qf, variant);
     if (dim == 3) return stage_supported_d3(prec, lim, si, variant);
     return false;
 }
 
-hipError_t stage_launch(int dim, int prec, bool lim, bool si, int variant, int nblocks, const void *params,
+hipError_t stage_launch(int dim, int prec, bool lim, bool si, bool qf, int variant, int nblocks, const void *params,
                         hipStream_t s)
 {
     if (dim == 1) return stage_launch_d1(prec, lim, si, variant, nblocks, params, s);
-    if (dim == 2) return stage_launch_d2(prec, lim, si, variant, nblocks, params, s);
+    if (dim == 2) return stage_launch_d2(prec, lim, si, qf, variant, nblocks, params, s);
     if (dim == 3) return stage_launch_d3(prec, lim, si, variant, nblocks, params, s);
     return hipErrorInvalidValue;
 }

@@ -16,20 +16,22 @@ VariantInfo stage_variant(int dim, int v);
 // One stage launch over nblocks (instance, tile) work items.
 // params points to a StageParams<float> or StageParams<double>.
 // Returns hipErrorInvalidValue for a combination that is not built.
-hipError_t stage_launch(int dim, int prec, bool lim, bool si, int variant, int nblocks, const void *params,
+hipError_t stage_launch(int dim, int prec, bool lim, bool si, bool qf, int variant, int nblocks, const void *params,
                         hipStream_t s);
 // true if the (dim, prec, lim, si, variant) kernel is built (LDS fits)
-bool stage_supported(int dim, int prec, bool lim, bool si, int variant);
+// qf: every flux of every instance is c1 u + c2 u^2 (linear or Burgers)
+bool stage_supported(int dim, int prec, bool lim, bool si, bool qf, int variant);
 bool stage_supported_d1(int prec, bool lim, bool si, int variant);
-bool stage_supported_d2(int prec, bool lim, bool si, int variant);
+bool stage_supported_d2(int prec, bool lim, bool si, bool qf, int variant);
 bool stage_supported_d3(int prec, bool lim, bool si, int variant);
 hipError_t stage_launch_d1(int prec, bool lim, bool si, int variant, int nblocks, const void *params, hipStream_t s);
-hipError_t stage_launch_d2(int prec, bool lim, bool si, int variant, int nblocks, const void *params, hipStream_t s);
+hipError_t stage_launch_d2(int prec, bool lim, bool si, bool qf, int variant, int nblocks, const void *params,
+                           hipStream_t s);
 hipError_t stage_launch_d3(int prec, bool lim, bool si, int variant, int nblocks, const void *params, hipStream_t s);
 
 // FP64 max over faces of alpha_l/dx_l + kappa_max/dx_l^2 of the averages of
 // U (per instance, into InstState::wmax), plus the divergence check.
-constexpr int kWaveChunk = 2048;  // cells per wave-speed block
+constexpr int kWaveChunk = 2048;  // cells per wave-speed block (rounded up to whole rows)
 hipError_t wavespeed_launch(int dim, int prec, const InstDev *inst, const int2 *chunks, int nchunks, const void *U,
                             InstState *st, hipStream_t s);
 

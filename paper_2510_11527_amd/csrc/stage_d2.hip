@@ -1,73 +1,98 @@
 // stage_d2.hip -- instantiations and dispatch of the 2D stage kernels.
-#include "stage_kernel.hpp"
+#include "stage2d_kernel.hpp"
 #include "variants.h"
 
 namespace af4 {
 
 namespace {
 
-template <class T, bool LIM, bool SI, int TX, int TY, int TZ, int NT>
-hipError_t launch_one(int nblocks, const void *params, hipStream_t s)
+constexpr long kLdsCap = 160L * 1024L;
+
+template <class T, bool LIM, bool SI, int TX, int TY, int NT>
+hipError_t launch_generic(int nblocks, const void *params, hipStream_t s)
 {
-    if constexpr (stage_lds_bytes<2, T, LIM, SI, TX, TY, TZ>() > 160L * 1024L) {
+    if constexpr (stage_lds_bytes<2, T, LIM, SI, TX, TY, 1>() > kLdsCap) {
         return hipErrorInvalidValue;
     } else {
-        hipLaunchKernelGGL((stage_kernel<2, T, LIM, SI, TX, TY, TZ, NT>), dim3(nblocks), dim3(NT), 0, s,
+        hipLaunchKernelGGL((stage_kernel<2, T, LIM, SI, TX, TY, 1, NT>), dim3(nblocks), dim3(NT), 0, s,
                            *(const StageParams<T> *)params);
         return hipGetLastError();
     }
 }
 
-template <int TX, int TY, int TZ, int NT>
-hipError_t launch_tile(int prec, bool lim, bool si, int nblocks, const void *params, hipStream_t s)
+template <class T, bool LIM, bool QF, bool FT, int TX, int TY, int NT>
+hipError_t launch_tuned(int nblocks, const void *params, hipStream_t s)
 {
-    if (prec == 32) {
-        if (lim) return si ? launch_one<float, true, true, TX, TY, TZ, NT>(nblocks, params, s)
-                           : launch_one<float, true, false, TX, TY, TZ, NT>(nblocks, params, s);
-        return si ? launch_one<float, false, true, TX, TY, TZ, NT>(nblocks, params, s)
-                  : launch_one<float, false, false, TX, TY, TZ, NT>(nblocks, params, s);
+    if constexpr (stage2d_lds_bytes<T, LIM, QF, FT, TX, TY>() > kLdsCap) {
+        return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((stage2d_kernel<T, LIM, QF, FT, TX, TY, NT>), dim3(nblocks), dim3(NT), 0, s,
+                           *(const StageParams<T> *)params);
+        return hipGetLastError();
     }
-    if (lim) return si ? launch_one<double, true, true, TX, TY, TZ, NT>(nblocks, params, s)
-                       : launch_one<double, true, false, TX, TY, TZ, NT>(nblocks, params, s);
-    return si ? launch_one<double, false, true, TX, TY, TZ, NT>(nblocks, params, s)
-              : launch_one<double, false, false, TX, TY, TZ, NT>(nblocks, params, s);
 }
 
-template <int TX, int TY, int TZ>
-bool fits(int prec, bool lim, bool si)
+template <class T, int TX, int TY, int NT, int KIND>
+hipError_t launch_kind(bool lim, bool si, bool qf, int nblocks, const void *params, hipStream_t s)
 {
-    constexpr long cap = 160L * 1024L;
-    if (prec == 32) {
-        if (lim) return si ? stage_lds_bytes<2, float, true, true, TX, TY, TZ>() <= cap
-                           : stage_lds_bytes<2, float, true, false, TX, TY, TZ>() <= cap;
-        return si ? stage_lds_bytes<2, float, false, true, TX, TY, TZ>() <= cap
-                  : stage_lds_bytes<2, float, false, false, TX, TY, TZ>() <= cap;
+    if constexpr (KIND == 0) {
+        if (lim) return si ? launch_generic<T, true, true, TX, TY, NT>(nblocks, params, s)
+                           : launch_generic<T, true, false, TX, TY, NT>(nblocks, params, s);
+        return si ? launch_generic<T, false, true, TX, TY, NT>(nblocks, params, s)
+                  : launch_generic<T, false, false, TX, TY, NT>(nblocks, params, s);
+    } else {
+        constexpr bool FT = KIND == 1;
+        if (si) return hipErrorInvalidValue;
+        if (qf) return lim ? launch_tuned<T, true, true, FT, TX, TY, NT>(nblocks, params, s)
+                           : launch_tuned<T, false, true, FT, TX, TY, NT>(nblocks, params, s);
+        if constexpr (!FT) return hipErrorInvalidValue;  // general fluxes need the table
+        else
+            return lim ? launch_tuned<T, true, false, true, TX, TY, NT>(nblocks, params, s)
+                       : launch_tuned<T, false, false, true, TX, TY, NT>(nblocks, params, s);
     }
-    if (lim) return si ? stage_lds_bytes<2, double, true, true, TX, TY, TZ>() <= cap
-                       : stage_lds_bytes<2, double, true, false, TX, TY, TZ>() <= cap;
-    return si ? stage_lds_bytes<2, double, false, true, TX, TY, TZ>() <= cap
-              : stage_lds_bytes<2, double, false, false, TX, TY, TZ>() <= cap;
+}
+
+template <class T, int TX, int TY, int KIND>
+bool fits_kind(bool lim, bool si, bool qf)
+{
+    if constexpr (KIND == 0) {
+        if (lim) return si ? stage_lds_bytes<2, T, true, true, TX, TY, 1>() <= kLdsCap
+                           : stage_lds_bytes<2, T, true, false, TX, TY, 1>() <= kLdsCap;
+        return si ? stage_lds_bytes<2, T, false, true, TX, TY, 1>() <= kLdsCap
+                  : stage_lds_bytes<2, T, false, false, TX, TY, 1>() <= kLdsCap;
+    } else {
+        constexpr bool FT = KIND == 1;
+        if (si) return false;
+        if (!qf && !FT) return false;
+        // the residual launch uses the unlimited instantiation: both must fit
+        const long lim_b = qf ? stage2d_lds_bytes<T, true, true, FT, TX, TY>() : stage2d_lds_bytes<T, true, false, true, TX, TY>();
+        const long un_b = qf ? stage2d_lds_bytes<T, false, true, FT, TX, TY>() : stage2d_lds_bytes<T, false, false, true, TX, TY>();
+        return (lim ? lim_b : un_b) <= kLdsCap && un_b <= kLdsCap;
+    }
 }
 
 }  // namespace
 
-bool stage_supported_d2(int prec, bool lim, bool si, int variant)
+bool stage_supported_d2(int prec, bool lim, bool si, bool qf, int variant)
 {
     switch (variant) {
-#define AF4_FITS(V, TX, TY, TZ, NT, NAME) \
-    case V: return fits<TX, TY, TZ>(prec, lim, si);
+#define AF4_FITS(V, TX, TY, TZ, NT, KIND, NAME) \
+    case V: return prec == 32 ? fits_kind<float, TX, TY, KIND>(lim, si, qf) : fits_kind<double, TX, TY, KIND>(lim, si, qf);
         AF4_VARIANTS_D2(AF4_FITS)
 #undef AF4_FITS
     }
     return false;
 }
 
-hipError_t stage_launch_d2(int prec, bool lim, bool si, int variant, int nblocks, const void *params, hipStream_t s)
+hipError_t stage_launch_d2(int prec, bool lim, bool si, bool qf, int variant, int nblocks, const void *params,
+                           hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
     switch (variant) {
-#define AF4_CASE(V, TX, TY, TZ, NT, NAME) \
-    case V: return launch_tile<TX, TY, TZ, NT>(prec, lim, si, nblocks, params, s);
+#define AF4_CASE(V, TX, TY, TZ, NT, KIND, NAME)                                                            \
+    case V:                                                                                                \
+        return prec == 32 ? launch_kind<float, TX, TY, NT, KIND>(lim, si, qf, nblocks, params, s)         \
+                          : launch_kind<double, TX, TY, NT, KIND>(lim, si, qf, nblocks, params, s);
         AF4_VARIANTS_D2(AF4_CASE)
 #undef AF4_CASE
     }

@@ -88,6 +88,9 @@ struct Phys {
         switch (ak) {
         case kALinear: return a0 * u;
         case kAPower: {
+            if (am == 2) return a0 * (u * u);
+            if (am == 3) return a0 * (u * u * u);
+            if (am == 1) return a0 * u;
             if (am > 0) {
                 T r = u;
                 for (int i = 1; i < am; i++) r *= u;

@@ -179,27 +179,38 @@ def test_argument_validation():
     ctx.close()
 
 
-@pytest.mark.parametrize("d", [1, 2, 3])
-def test_tile_variants_bitwise_identical(d):
-    """Every tile shape computes the same per-cell arithmetic: identical bits."""
-    rng = np.random.default_rng(d)
+@pytest.mark.parametrize("d,fl", [(1, 2), (2, 0), (2, 2), (3, 0)])
+def test_tile_variants_agree(d, fl):
+    """Tile shapes of one kernel family compute the same per-cell arithmetic
+    (identical bits); different families agree to the parity tolerance."""
+    rng = np.random.default_rng(d + 10 * fl)
     n = {1: 300, 2: 70, 3: 20}[d]
-    spec = small_spec(d, n, FLUXES[2 % 4], DIFFS[1], limiter=True, precision=32)
+    spec = small_spec(d, n, FLUXES[fl], DIFFS[1], limiter=True, precision=32)
     U = state_for(spec, rng)
     s, U = prepare(spec, U, 32)
-    ref = None
+    ref = {}
+    first = None
     ctx = af.Context(s)
     for v in range(ctx.num_variants()):
-        note("variant d=%d %s" % (d, ctx.variant_name(v)))
-        ctx.set_variant(v)
+        name = ctx.variant_name(v)
+        try:
+            ctx.set_variant(v)
+        except af.AFError as e:
+            assert e.status == af.AF_ERR_UNSUPPORTED
+            continue
+        note("variant d=%d flux=%s %s" % (d, FLUXES[fl][0], name))
         ctx.set_state(0, U)
         ctx.step(2, dt=1e-4)
         V, _ = ctx.get_state(0)
-        if ref is None:
-            ref = V
+        fam = name.rsplit("-", 1)[0]  # kernel family: the name without the tile
+        if fam in ref:
+            for a, b in zip(V, ref[fam]):
+                assert np.array_equal(a, b), name
         else:
-            for a, b in zip(V, ref):
-                assert np.array_equal(a, b)
+            ref[fam] = V
+        if first is None:
+            first = V
+        assert rel_l1(V, first) <= TOL[32]
     ctx.close()
 
 
