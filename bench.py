@@ -9,6 +9,8 @@ instances, inputs resident in HBM before the timed region).
     python bench.py [--steps K] [--warmup W] [--workload c4|c2|c3|c3f32|c5]
 """
 import argparse
+import glob
+import hashlib
 import json
 import math
 import os
@@ -27,6 +29,35 @@ HBM_PEAK_GBS = 8000.0
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    """Hash of the HIP sources; a traffic figure measured with other sources
+    is stale and not reported."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2510_11527_amd", "csrc", "*"))):
+        if f.endswith((".hpp", ".hip", ".h", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_name, tile):
+    """HBM bytes per stage launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary of this workload and tile, if the kernel sources are
+    the ones it was measured with; else None."""
+    sha = kernel_source_sha()
+    for f in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.txt")):
+        kv = {}
+        with open(f) as fh:
+            for line in fh:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.strip().split("=", 1)
+                    kv[k] = v
+        if kv.get("workload") == workload_name and kv.get("tile") == tile and kv.get("source_sha") == sha:
+            return float(kv["traffic_bytes_per_launch"])
+    return None
 
 
 def workload(name):
@@ -132,7 +163,7 @@ def main():
     prec = items[0][0]["precision"]
     ctx = make_ctx(items, variant=args.variant, integrator=args.integrator)
     work = ctx.work()
-    variant_name = ctx.variant_name(args.variant if args.variant is not None else 0)
+    variant_name = ctx.variant_name(ctx.variant())
     if args.warmup > 0:
         ctx.step(args.warmup)
     log("warmup done")
@@ -155,8 +186,8 @@ def main():
         ms, nl = ctx.step_timed(args.steps)
         achieved = work["bytes_per_stage"] / (ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "af4::stage_kernel (%s, tile %s)" % ("fp32" if prec == 32 else "fp64", variant_name),
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wname, variant_name),
+                "kernel": "stage kernel %s (%s)" % (variant_name, "fp32" if prec == 32 else "fp64"),
                 "mean_launch_ms": ms, "launches": nl,
                 "algorithmic_bytes_per_launch": work["bytes_per_stage"]}
         log("stage kernel mean %.4f ms over %d launches -> %.1f GB/s" % (ms, nl, achieved))
@@ -180,7 +211,7 @@ def main():
         except Exception as e:  # reported, not fatal
             line["fp64_plain"] = {"error": str(e)}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(items, 1_500_000 if items[0][0]["dim"] == 2 else 300_000)
+        line["cpu_baseline"] = cpu_baseline(items, 12_000_000 if items[0][0]["dim"] == 2 else 2_000_000)
     print(json.dumps(line), flush=True)
 
 

@@ -150,6 +150,7 @@ af_status af_set_stream(af_ctx *ctx, void *stream);
  * autotuner; cached graphs are dropped. */
 af_status af_set_variant(af_ctx *ctx, int variant);
 int af_num_variants(const af_ctx *ctx);
+int af_get_variant(const af_ctx *ctx);
 const char *af_variant_name(const af_ctx *ctx, int variant);
 
 /* Times the stage kernels: runs nsteps steps like af_step, launching

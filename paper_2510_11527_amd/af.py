@@ -23,7 +23,7 @@ INTEGRATORS = {"ssprk3": 0, "euler": 1}
 
 EXPORTS = ["af_create", "af_destroy", "af_set_state", "af_get_state", "af_step", "af_residual", "af_norms",
            "af_last_error", "af_set_stream", "af_set_variant", "af_num_variants", "af_variant_name",
-           "af_step_timed", "af_work"]
+           "af_step_timed", "af_work", "af_get_variant"]
 
 
 class AfProblem(ctypes.Structure):
@@ -84,13 +84,15 @@ def lib():
         L.af_set_stream.argtypes = [vp, vp]
         L.af_set_variant.argtypes = [vp, ctypes.c_int]
         L.af_num_variants.argtypes = [vp]
+        L.af_get_variant.argtypes = [vp]
         L.af_variant_name.argtypes = [vp, ctypes.c_int]
         L.af_variant_name.restype = ctypes.c_char_p
         L.af_work.argtypes = [vp, dp, dp, dp]
         for name in EXPORTS:
-            if name not in ("af_last_error", "af_num_variants", "af_variant_name"):
+            if name not in ("af_last_error", "af_num_variants", "af_variant_name", "af_get_variant"):
                 getattr(L, name).restype = ctypes.c_int
         L.af_num_variants.restype = ctypes.c_int
+        L.af_get_variant.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -226,6 +228,9 @@ class Context:
 
     def set_variant(self, v):
         self._check(lib().af_set_variant(self.h, int(v)))
+
+    def variant(self):
+        return lib().af_get_variant(self.h)
 
     def work(self):
         b, c, d = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -28,6 +28,14 @@ struct InstDev {
     double crit[3][kMaxCrit];  // interior local maxima of |f_l'|
     double vol;          // cell volume
     double si_gamma;     // smoothness-indicator blending strength
+    // potential in the unified form a(u) = s * v (pc1 + v (pc2 + v pc3)) with
+    // v = min(max((pabs ? |u| : u) - pu0, plo), phi), s = sign(u) if pabs
+    // else 1; ppow != 0: p0 * u^p1 by pow (powers other than 1..3)
+    double pu0, plo, phi, pc1, pc2, pc3;
+    int pabs, ppow;
+    double idx1[3];      // 1 / dx_l
+    double idx2[3];      // 1 / dx_l^2
+    double i6dx[3];      // 1 / (6 dx_l)
 };
 
 // Control block read by the time-step kernels (uploaded before each af_step).
@@ -46,6 +54,8 @@ struct InstState {
     unsigned int flags;  // bit 0: non-finite / divergent value produced
     unsigned int pad;
     long long steps;     // steps with dt > 0
+    double mu[3];        // dt / dx_l of the current step
+    double nu[3];        // dt / dx_l^2 of the current step
 };
 
 template <class T>

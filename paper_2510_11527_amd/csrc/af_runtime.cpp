@@ -150,6 +150,46 @@ void derive_bounds_params(InstDev &I, const af_problem &P, int dim)
     }
 }
 
+// Coefficients of the unified potential evaluation used by the kernels:
+// a(u) = s * v (c1 + v (c2 + v c3)), v = clamp((abs ? |u| : u) - u0, lo, hi).
+void set_unified_potential(InstDev &I, const af_problem &P)
+{
+    const double p0 = P.diff_par[0], p1 = P.diff_par[1];
+    const double inf = std::numeric_limits<double>::infinity();
+    I.pu0 = 0;
+    I.plo = -inf;
+    I.phi = inf;
+    I.pc1 = I.pc2 = I.pc3 = 0;
+    I.pabs = 0;
+    I.ppow = 0;
+    switch (P.diff) {
+    case AF_A_LINEAR: I.pc1 = p0; break;
+    case AF_A_POWER:
+        if (p1 == 1.0) I.pc1 = p0;
+        else if (p1 == 2.0) I.pc2 = p0;
+        else if (p1 == 3.0) I.pc3 = p0;
+        else I.ppow = 1;
+        break;
+    case AF_A_DEADZONE:
+        I.pabs = 1;
+        I.pu0 = p1;
+        I.plo = 0;
+        I.pc1 = p0;
+        break;
+    case AF_A_BL:
+        I.plo = 0;
+        I.phi = 1;
+        I.pc2 = 2 * p0;
+        I.pc3 = -4.0 / 3.0 * p0;
+        break;
+    case AF_A_RAMP2:
+        I.pu0 = p1;
+        I.plo = 0;
+        I.pc2 = 0.5 * p0;
+        break;
+    }
+}
+
 bool is_int_exponent(double p, int *m)
 {
     double r = std::round(p);
@@ -366,6 +406,9 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
             I.fp0[l] = l < P.dim ? P.flux_par[l][0] : 0.0;
             I.fp1[l] = l < P.dim ? P.flux_par[l][1] : 0.0;
             if (l < P.dim) I.vol *= I.dx[l];
+            I.idx1[l] = 1.0 / I.dx[l];
+            I.idx2[l] = 1.0 / (I.dx[l] * I.dx[l]);
+            I.i6dx[l] = 1.0 / (6.0 * I.dx[l]);
         }
         I.ncell = (long long)I.n[0] * I.n[1] * I.n[2];
         I.kstride = (I.ncell + 63) / 64 * 64;
@@ -376,6 +419,7 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
         I.ap1 = P.diff_par[1];
         int m = 0;
         I.am = (P.diff == AF_A_POWER && is_int_exponent(P.diff_par[1], &m)) ? m : 0;
+        set_unified_potential(I, P);
         I.umin = P.umin;
         I.umax = P.umax;
         I.cfl = P.cfl;
@@ -483,6 +527,8 @@ af_status af_set_stream(af_ctx *c, void *stream)
 }
 
 int af_num_variants(const af_ctx *c) { return c ? af4::stage_num_variants(c->dim) : 0; }
+
+int af_get_variant(const af_ctx *c) { return c ? c->variant : -1; }
 
 const char *af_variant_name(const af_ctx *c, int v)
 {

@@ -24,8 +24,8 @@ __global__ void __launch_bounds__(256) wavespeed_kernel(const InstDev *inst, con
     const T *u = U + I.off;
     double idx[3], kdx2[3];
     for (int l = 0; l < 3; l++) {
-        idx[l] = 1.0 / I.dx[l];
-        kdx2[l] = I.kmax * idx[l] * idx[l];
+        idx[l] = I.idx1[l];
+        kdx2[l] = I.kmax * I.idx2[l];
     }
     const double big = 1e6 * fmax(fmax(fabs(I.umin), fabs(I.umax)), 1.0);
     double w = 0.0;
@@ -68,6 +68,10 @@ __global__ void finalize_kernel(int n_inst, const InstDev *inst, const StepCtl *
         st[i].dt = dt;
         st[i].t += dt;
         if (dt > 0.0) st[i].steps++;
+        for (int l = 0; l < 3; l++) {
+            st[i].mu[l] = dt * inst[i].idx1[l];
+            st[i].nu[l] = dt * inst[i].idx2[l];
+        }
     }
 }
 

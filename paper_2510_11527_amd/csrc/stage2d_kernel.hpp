@@ -116,11 +116,11 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
     T idx1[2], idx2[2], i6dx[2], mu[2], nu[2];
 #pragma unroll
     for (int l = 0; l < 2; l++) {
-        idx1[l] = (T)(1.0 / I.dx[l]);
-        idx2[l] = (T)(1.0 / (I.dx[l] * I.dx[l]));
-        i6dx[l] = (T)(1.0 / (6.0 * I.dx[l]));
-        mu[l] = (T)(dtd / I.dx[l]);
-        nu[l] = (T)(dtd / (I.dx[l] * I.dx[l]));
+        idx1[l] = (T)I.idx1[l];
+        idx2[l] = (T)I.idx2[l];
+        i6dx[l] = (T)I.i6dx[l];
+        mu[l] = (T)p.st[wk.x].mu[l];
+        nu[l] = (T)p.st[wk.x].nu[l];
     }
     const T K = T(4);
 

@@ -1,5 +1,5 @@
 // stage_d2.hip -- instantiations and dispatch of the 2D stage kernels.
-#include "stage2d_kernel.hpp"
+#include "stage2q_kernel.hpp"
 #include "variants.h"
 
 namespace af4 {
@@ -32,10 +32,26 @@ hipError_t launch_tuned(int nblocks, const void *params, hipStream_t s)
     }
 }
 
+template <class T, bool LIM, int TX, int TY, int NT>
+hipError_t launch_quad(int nblocks, const void *params, hipStream_t s)
+{
+    if constexpr (stage2q_lds_bytes<T, LIM, TX, TY>() > kLdsCap) {
+        return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((stage2q_kernel<T, LIM, TX, TY, NT>), dim3(nblocks), dim3(NT), 0, s,
+                           *(const StageParams<T> *)params);
+        return hipGetLastError();
+    }
+}
+
 template <class T, int TX, int TY, int NT, int KIND>
 hipError_t launch_kind(bool lim, bool si, bool qf, int nblocks, const void *params, hipStream_t s)
 {
-    if constexpr (KIND == 0) {
+    if constexpr (KIND == 3) {
+        if (si || !qf) return hipErrorInvalidValue;
+        return lim ? launch_quad<T, true, TX, TY, NT>(nblocks, params, s)
+                   : launch_quad<T, false, TX, TY, NT>(nblocks, params, s);
+    } else if constexpr (KIND == 0) {
         if (lim) return si ? launch_generic<T, true, true, TX, TY, NT>(nblocks, params, s)
                            : launch_generic<T, true, false, TX, TY, NT>(nblocks, params, s);
         return si ? launch_generic<T, false, true, TX, TY, NT>(nblocks, params, s)
@@ -55,7 +71,10 @@ hipError_t launch_kind(bool lim, bool si, bool qf, int nblocks, const void *para
 template <class T, int TX, int TY, int KIND>
 bool fits_kind(bool lim, bool si, bool qf)
 {
-    if constexpr (KIND == 0) {
+    if constexpr (KIND == 3) {
+        if (si || !qf) return false;
+        return stage2q_lds_bytes<T, true, TX, TY>() <= kLdsCap && stage2q_lds_bytes<T, false, TX, TY>() <= kLdsCap;
+    } else if constexpr (KIND == 0) {
         if (lim) return si ? stage_lds_bytes<2, T, true, true, TX, TY, 1>() <= kLdsCap
                            : stage_lds_bytes<2, T, true, false, TX, TY, 1>() <= kLdsCap;
         return si ? stage_lds_bytes<2, T, false, true, TX, TY, 1>() <= kLdsCap

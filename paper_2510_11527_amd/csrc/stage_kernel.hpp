@@ -38,6 +38,8 @@ struct Phys {
     T umin, umax;
     int nc[3];
     const InstDev *ip;   // critical points are read from here (uniform loads)
+    T pu0, plo, phi, pc1, pc2, pc3;
+    bool pabs, ppow;
 
     __device__ void load(const InstDev &I, int D)
     {
@@ -50,6 +52,14 @@ struct Phys {
         }
         ak = I.ak;
         am = I.am;
+        pu0 = (T)I.pu0;
+        plo = (T)I.plo;
+        phi = (T)I.phi;
+        pc1 = (T)I.pc1;
+        pc2 = (T)I.pc2;
+        pc3 = (T)I.pc3;
+        pabs = I.pabs != 0;
+        ppow = I.ppow != 0;
         a0 = (T)I.ap0;
         a1 = (T)I.ap1;
         umin = (T)I.umin;
@@ -82,36 +92,15 @@ struct Phys {
         return fabs(d1 * (T(1) - fg[l] * v * v) + q * T(2) * fg[l] * v);
     }
 
-    // a(u)
+    // a(u): one branch-free form for every supported potential (linear,
+    // powers 1..3, dead zone, Buckley-Leverett cubic, squared ramp); other
+    // powers take the pow branch
     __device__ __forceinline__ T a(T u) const
     {
-        switch (ak) {
-        case kALinear: return a0 * u;
-        case kAPower: {
-            if (am == 2) return a0 * (u * u);
-            if (am == 3) return a0 * (u * u * u);
-            if (am == 1) return a0 * u;
-            if (am > 0) {
-                T r = u;
-                for (int i = 1; i < am; i++) r *= u;
-                return a0 * r;
-            }
-            return a0 * pow(u, a1);
-        }
-        case kADeadzone: {
-            T m = fabs(u) - a1;
-            if (!(m > T(0))) return T(0);
-            return u > T(0) ? a0 * m : -a0 * m;
-        }
-        case kABL:
-            if (u < T(0)) return T(0);
-            if (u > T(1)) return a0 * T(2.0 / 3.0);
-            return a0 * (T(2) * u * u - T(4.0 / 3.0) * u * u * u);
-        default: {
-            T m = u - a1;
-            return m > T(0) ? T(0.5) * a0 * m * m : T(0);
-        }
-        }
+        if (ppow) return a0 * pow(u, a1);
+        const T v = fmin(fmax((pabs ? fabs(u) : u) - pu0, plo), phi);
+        const T g = v * (pc1 + v * (pc2 + v * pc3));
+        return pabs ? copysign(g, u) : g;
     }
 
     // max of |f_l'| over [min(x,y), max(x,y)]: end points and interior local
@@ -272,11 +261,11 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
     T idx1[3], idx2[3], i6dx[3], mu[3], nu[3];
 #pragma unroll
     for (int l = 0; l < 3; l++) {
-        idx1[l] = (T)(1.0 / I.dx[l]);
-        idx2[l] = (T)(1.0 / (I.dx[l] * I.dx[l]));
-        i6dx[l] = (T)(1.0 / (6.0 * I.dx[l]));
-        mu[l] = (T)(dtd / I.dx[l]);
-        nu[l] = (T)(dtd / (I.dx[l] * I.dx[l]));
+        idx1[l] = (T)I.idx1[l];
+        idx2[l] = (T)I.idx2[l];
+        i6dx[l] = (T)I.i6dx[l];
+        mu[l] = (T)p.st[wk.x].mu[l];
+        nu[l] = (T)p.st[wk.x].nu[l];
     }
 
     // ---- A: stage tile + halo (averages -> ub, point values -> half grid)
