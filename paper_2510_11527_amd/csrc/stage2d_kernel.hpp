@@ -41,12 +41,30 @@ __device__ __forceinline__ float fast_rcp<float>(float v)
 
 // largest t in [0,1] with every low-order state + t * correction in bounds,
 // given the common correction magnitude s (> 0) and the smallest gap
+// (branch-free: selects only; s == 0 means no correction, any result works)
 template <class T>
 __device__ __forceinline__ T theta_from_gap(T gap, T s)
 {
-    if (gap >= s) return T(1);
-    if (!(gap > T(0))) return T(0);
-    return fmin(gap * fast_rcp(s), T(1));
+    const T r = fmin(fmax(gap, T(0)) * fast_rcp(s), T(1));
+    return gap >= s ? T(1) : r;
+}
+
+// smallest distance to the bound that a correction of sign(s) moves the
+// states z+ (moved by +s) and z- (moved by -s) towards
+template <class T>
+__device__ __forceinline__ T gap2(T s, T zp, T zm, T umin, T umax)
+{
+    const T g_pos = fmin(umax - zp, zm - umin), g_neg = fmin(zp - umin, umax - zm);
+    return s > T(0) ? g_pos : g_neg;
+}
+
+// same for two states moved by +s (a1, a2) and two moved by -s (b1, b2)
+template <class T>
+__device__ __forceinline__ T gap4(T s, T a1, T a2, T b1, T b2, T umin, T umax)
+{
+    const T g_pos = fmin(umax - fmax(a1, a2), fmin(b1, b2) - umin);
+    const T g_neg = fmin(fmin(a1, a2) - umin, umax - fmax(b1, b2));
+    return s > T(0) ? g_pos : g_neg;
 }
 
 // FT: keep f_x, f_y in the half-grid table (else recomputed from u; only
@@ -64,8 +82,11 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
     constexpr int NXC = CXE * TY, NYC = TX * CYE;
 
     constexpr bool TAB = FT || !QF;
+    // {u, a} table: the half grid split by parity into four cell-indexed
+    // sub-grids (centres, x-faces, y-faces, corners), rows padded by one
+    constexpr int SX = RX + 1, SG = SX * RY;
     __shared__ V4<T> hg[TAB ? GX * GY : 1];     // {u, a, f_x, f_y} on the half grid
-    __shared__ V2<T> hs[TAB ? 1 : GX * GY];     // {u, a} on the half grid
+    __shared__ V2<T> hs[TAB ? 1 : 4 * SG];      // {u, a} on the split half grid
     __shared__ V4<T> cg[RX * RY];               // {ubar, a, f_x, f_y} of the cells
     __shared__ T gq[QF ? 1 : 2 * GX * GY];      // |f_x'|, |f_y'| (general fluxes)
     __shared__ T fl[NXF + NYF];                 // flux used in the update
@@ -127,25 +148,27 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
     auto fq = [&](int l, T u) -> T { return QF ? u * (c1[l] + c2[l] * u) : P.f(l, u); };
     auto gq_of = [&](int l, T u) -> T { return QF ? fabs(c1[l] + T(2) * c2[l] * u) : P.adf(l, u); };
     auto tab = [&](T u) -> V4<T> { return V4<T>{u, P.a(u), fq(0, u), fq(1, u)}; };
-    auto put = [&](int idx, T u) {
-        if constexpr (TAB) hg[idx] = tab(u);
-        else hs[idx] = V2<T>{u, P.a(u)};
+    // index of half-grid point (x, y) in the split table
+    auto sidx = [&](int x, int y) -> int { return ((x & 1) + 2 * (y & 1)) * SG + (x >> 1) + SX * (y >> 1); };
+    auto put = [&](int x, int y, T u) {
+        if constexpr (TAB) hg[x + GX * y] = tab(u);
+        else hs[sidx(x, y)] = V2<T>{u, P.a(u)};
     };
     auto H = [&](int x, int y) -> V4<T> {
         if constexpr (TAB) {
             return hg[x + GX * y];
         } else {
-            const V2<T> v = hs[x + GX * y];
+            const V2<T> v = hs[sidx(x, y)];
             return V4<T>{v.x, v.y, fq(0, v.x), fq(1, v.x)};
         }
     };
     auto Hu = [&](int x, int y) -> T {
         if constexpr (TAB) return hg[x + GX * y].x;
-        else return hs[x + GX * y].x;
+        else return hs[sidx(x, y)].x;
     };
     auto Ha = [&](int x, int y) -> T {
         if constexpr (TAB) return hg[x + GX * y].y;
-        else return hs[x + GX * y].y;
+        else return hs[sidx(x, y)].y;
     };
 
     // U^n of the own cells (used by the RK combination), fetched early
@@ -163,9 +186,9 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
         const long long gi = gx + (long long)n0 * gy;
         const T ub = in[gi], ux = in[kst + gi], uy = in[2 * kst + gi], uc = in[3 * kst + gi];
         cg[id] = tab(ub);
-        put((2 * x + 1) + GX * (2 * y), ux);
-        put((2 * x) + GX * (2 * y + 1), uy);
-        put((2 * x + 1) + GX * (2 * y + 1), uc);
+        put(2 * x + 1, 2 * y, ux);
+        put(2 * x, 2 * y + 1, uy);
+        put(2 * x + 1, 2 * y + 1, uc);
         if constexpr (!QF) {
             const int px = (2 * x + 1) + GX * (2 * y), py = (2 * x) + GX * (2 * y + 1), pc_ = (2 * x + 1) + GX * (2 * y + 1);
             gq[2 * px] = gq_of(0, ux);
@@ -185,7 +208,7 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
         const T faces = Hu(hx - 1, hy) + Hu(hx + 1, hy) + Hu(hx, hy - 1) + Hu(hx, hy + 1);
         const T corners = Hu(hx - 1, hy - 1) + Hu(hx + 1, hy - 1) + Hu(hx - 1, hy + 1) + Hu(hx + 1, hy + 1);
         const T u = (T(36) * cg[x + RX * y].x - T(4) * faces - corners) * T(0.0625);
-        put(hx + GX * hy, u);
+        put(hx, hy, u);
         if constexpr (!QF) {
             gq[2 * (hx + GX * hy)] = gq_of(0, u);
             gq[2 * (hx + GX * hy) + 1] = gq_of(1, u);
@@ -310,8 +333,9 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
             if (!residual) {
                 const T df = fH - fL;
                 const T s3 = T(3) * K * mu[l] * df;
-                const T gap = s3 > T(0) ? fmin(up - umin, umax - um) : fmin(umax - up, um - umin);
-                F = fL + theta_from_gap(gap, fabs(s3)) * df;
+                // up moves by -s3, um by +s3
+                const T gap = gap2<T>(s3, um, up, umin, umax);
+                F = fL + theta_from_gap<T>(gap, (T)fabs(s3)) * df;
             }
         }
         fl[id] = F;
@@ -361,9 +385,9 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
                 const T pL = ulp[f0], mC = ulm[f0], pC = ulp[f1], mR = ulm[f1];
                 const T da = aH - aL;
                 const T s = T(3) * K * nu[xd ? 0 : 1] * da;
-                const T gap = s > T(0) ? fmin(fmin(umax - pL, umax - mR), fmin(pC - umin, mC - umin))
-                                       : fmin(fmin(pL - umin, mR - umin), fmin(umax - pC, umax - mC));
-                Pv = aL + theta_from_gap(gap, fabs(s)) * da;
+                // pL, mR move by +s; pC, mC by -s
+                const T gap = gap4<T>(s, pL, mR, pC, mC, umin, umax);
+                Pv = aL + theta_from_gap<T>(gap, (T)fabs(s)) * da;
             }
         }
         pc[id] = Pv;
@@ -415,7 +439,7 @@ constexpr long stage2d_lds_bytes()
     constexpr long RX = TX + 4, RY = TY + 4, G = 4 * RX * RY;
     constexpr long NF = (TX + 3) * TY + TX * (TY + 3), NC = (TX + 2) * TY + TX * (TY + 2);
     constexpr bool TAB = FT || !QF;
-    return (long)sizeof(T) * ((TAB ? 4 * G : 2 * G) + 4 * RX * RY + (QF ? 1 : 2 * G) + NF * (LIM ? 3 : 1) + NC);
+    return (long)sizeof(T) * ((TAB ? 4 * G : 8 * (RX + 1) * RY) + 4 * RX * RY + (QF ? 1 : 2 * G) + NF * (LIM ? 3 : 1) + NC);
 }
 
 }  // namespace af4

@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(NT) stage2q_kernel(StageParams<T> p)
             if (!residual) {
                 const T df = fH - fL;
                 const T s3 = T(3) * K * mu[l] * df;
-                const T gap = s3 > T(0) ? fmin(up - umin, umax - um) : fmin(umax - up, um - umin);
+                const T gap = gap2<T>(s3, um, up, umin, umax);
                 F = fL + theta_from_gap<T>(gap, (T)fabs(s3)) * df;
             }
         }
@@ -289,8 +289,7 @@ __global__ void __launch_bounds__(NT) stage2q_kernel(StageParams<T> p)
                 const T pL = ulp[f0], mC = ulm[f0], pC = ulp[f1], mR = ulm[f1];
                 const T da = aH - aL;
                 const T s = T(3) * K * nu[xd ? 0 : 1] * da;
-                const T gap = s > T(0) ? fmin(fmin(umax - pL, umax - mR), fmin(pC - umin, mC - umin))
-                                       : fmin(fmin(pL - umin, mR - umin), fmin(umax - pC, umax - mC));
+                const T gap = gap4<T>(s, pL, mR, pC, mC, umin, umax);
                 Pv = aL + theta_from_gap<T>(gap, (T)fabs(s)) * da;
             }
         }

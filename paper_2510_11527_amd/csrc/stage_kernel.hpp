@@ -29,6 +29,19 @@ namespace af4 {
 enum : int { kFLinear = 0, kFQuad = 1, kFBL = 2, kFBLGrav = 3 };
 enum : int { kALinear = 0, kAPower = 1, kADeadzone = 2, kABL = 3, kARamp2 = 4 };
 
+// p0 * u^p (powers other than 1, 2, 3): kept out of line so that the
+// stage kernels do not carry a pow expansion at every evaluation site
+template <class T>
+__device__ __noinline__ T power_potential(T p0, T p, int m, T u)
+{
+    if (m > 0) {
+        T r = u;
+        for (int i = 1; i < m; i++) r *= u;
+        return p0 * r;
+    }
+    return p0 * pow(u, p);
+}
+
 template <class T>
 struct Phys {
     int fk[3];
@@ -97,7 +110,7 @@ struct Phys {
     // powers take the pow branch
     __device__ __forceinline__ T a(T u) const
     {
-        if (ppow) return a0 * pow(u, a1);
+        if (ppow) return power_potential<T>(a0, a1, am, u);
         const T v = fmin(fmax((pabs ? fabs(u) : u) - pu0, plo), phi);
         const T g = v * (pc1 + v * (pc2 + v * pc3));
         return pabs ? copysign(g, u) : g;
