@@ -51,6 +51,8 @@ struct InstState {
     double t;            // time at the end of the current step
     unsigned long long wmax;      // bits of the FP64 max wave speed (non-negative)
     unsigned long long clampmax;  // bits of the largest average clamp (non-negative)
+    unsigned long long vmin_key;  // ordered keys of the min / max average written by
+    unsigned long long vmax_key;  // the last stage of a step (see ordered_key)
     unsigned int flags;  // bit 0: non-finite / divergent value produced
     unsigned int pad;
     long long steps;     // steps with dt > 0
@@ -68,6 +70,25 @@ struct StageParams {
     T *out;              // stage output (or right-hand side)
     InstState *st;
     int stage;           // 0: forward Euler, 1..3: SSP-RK3 stage, 4: residual
+    int minmax;          // 1: reduce min / max of the written averages into vmin_key / vmax_key
 };
+
+// Order-preserving map of doubles to unsigned integers: a < b <=> key(a) <
+// key(b) for non-NaN values, so that unsigned atomic min / max reduce doubles.
+__host__ __device__ inline unsigned long long ordered_key(double v)
+{
+    unsigned long long b;
+    __builtin_memcpy(&b, &v, sizeof b);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__host__ __device__ inline double ordered_value(unsigned long long k)
+{
+    const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    double v;
+    __builtin_memcpy(&v, &b, sizeof v);
+    return v;
+}
+constexpr unsigned long long kKeyMinEmpty = ~0ull;  // neutral element of the min key
+constexpr unsigned long long kKeyMaxEmpty = 0ull;   // neutral element of the max key
 
 }  // namespace af4

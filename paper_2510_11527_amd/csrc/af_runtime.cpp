@@ -22,7 +22,7 @@ using af4::StepCtl;
 
 struct af_ctx {
     int n_inst = 0, dim = 0, prec = 64, lim = 0, si = 0, integ = 0;
-    bool qf = true;   // every flux is linear or quadratic
+    unsigned caps = 0;  // af4::kCap* properties of all instances
     std::vector<af_problem> prob;
     std::vector<InstDev> ih;
     std::vector<int> have_state;
@@ -43,6 +43,10 @@ struct af_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_steps = 0;
+    bool graph_ws = true;   // the cached graph's first step runs the wave-speed kernel
+    // the last stage of the previous step reduced the min / max averages of
+    // every instance, so the next step's CFL needs no wave-speed pass
+    bool keys_fresh = false;
     std::string err;
 };
 
@@ -233,7 +237,12 @@ void drop_graph(af_ctx *c)
     c->gexec = nullptr;
     c->graph = nullptr;
     c->graph_steps = 0;
+    c->graph_ws = true;
 }
+
+// Fluxes with convex |f'| (linear, quadratic): the CFL wave speed is a
+// function of the min / max average, which the last stage of a step reduces.
+bool cfl_from_keys(const af_ctx *c) { return (c->caps & af4::kCapQF) != 0; }
 
 // Work list (instance, tile) for the current variant; instances are kept
 // contiguous so that one instance can be launched alone.
@@ -275,44 +284,53 @@ StageParams<T> stage_params(af_ctx *c, int in, int out, int stage)
     p.out = (T *)c->buf[out];
     p.st = c->d_st;
     p.stage = stage;
+    p.minmax = 0;
     return p;
 }
 
-hipError_t launch_stage(af_ctx *c, int in, int out, int stage, bool lim, bool si, int wstart, int wcount)
+hipError_t launch_stage(af_ctx *c, int in, int out, int stage, bool lim, bool si, int wstart, int wcount,
+                        bool minmax = false)
 {
     if (c->prec == 32) {
         StageParams<float> p = stage_params<float>(c, in, out, stage);
         p.work += wstart;
         p.nwork = wcount;
-        return af4::stage_launch(c->dim, 32, lim, si, c->qf, c->variant, wcount, &p, c->stream);
+        p.minmax = minmax ? 1 : 0;
+        return af4::stage_launch(c->dim, 32, lim, si, c->caps, c->variant, wcount, &p, c->stream);
     }
     StageParams<double> p = stage_params<double>(c, in, out, stage);
     p.work += wstart;
     p.nwork = wcount;
-    return af4::stage_launch(c->dim, 64, lim, si, c->qf, c->variant, wcount, &p, c->stream);
+    p.minmax = minmax ? 1 : 0;
+    return af4::stage_launch(c->dim, 64, lim, si, c->caps, c->variant, wcount, &p, c->stream);
 }
 
 // One time step over all instances, enqueued on the context stream.  With
-// events != nullptr, records an event pair around every stage launch.
-hipError_t enqueue_step(af_ctx *c, std::vector<hipEvent_t> *events, size_t *ev_next)
+// events != nullptr, records an event pair around every stage launch.  The
+// wave-speed pass runs unless the previous step's last stage reduced the
+// min / max averages (ws == false).
+hipError_t enqueue_step(af_ctx *c, bool ws, std::vector<hipEvent_t> *events, size_t *ev_next)
 {
     hipError_t e;
-    e = af4::wavespeed_launch(c->dim, c->prec, c->d_inst, c->d_chunks, c->nchunks, c->buf[0], c->d_st, c->stream);
+    if (ws) {
+        e = af4::wavespeed_launch(c->dim, c->prec, c->d_inst, c->d_chunks, c->nchunks, c->buf[0], c->d_st, c->stream);
+        if (e != hipSuccess) return e;
+    }
+    e = af4::finalize_launch(c->n_inst, c->d_inst, c->d_ctl, c->d_dtp, c->d_st, c->dim, !ws, c->stream);
     if (e != hipSuccess) return e;
-    e = af4::finalize_launch(c->n_inst, c->d_inst, c->d_ctl, c->d_dtp, c->d_st, c->stream);
-    if (e != hipSuccess) return e;
-    auto stage = [&](int in, int out, int st) -> hipError_t {
+    const bool mm = cfl_from_keys(c);
+    auto stage = [&](int in, int out, int st, bool last) -> hipError_t {
         if (events) (void)hipEventRecord((*events)[(*ev_next)++], c->stream);
-        hipError_t r = launch_stage(c, in, out, st, c->lim, c->si, 0, c->nwork);
+        hipError_t r = launch_stage(c, in, out, st, c->lim, c->si, 0, c->nwork, last && mm);
         if (events) (void)hipEventRecord((*events)[(*ev_next)++], c->stream);
         return r;
     };
     if (c->integ == AF_RK_SSP3) {
-        if ((e = stage(0, 1, 1)) != hipSuccess) return e;
-        if ((e = stage(1, 2, 2)) != hipSuccess) return e;
-        if ((e = stage(2, 0, 3)) != hipSuccess) return e;
+        if ((e = stage(0, 1, 1, false)) != hipSuccess) return e;
+        if ((e = stage(1, 2, 2, false)) != hipSuccess) return e;
+        if ((e = stage(2, 0, 3, true)) != hipSuccess) return e;
     } else {
-        if ((e = stage(0, 1, 0)) != hipSuccess) return e;
+        if ((e = stage(0, 1, 0, true)) != hipSuccess) return e;
         e = af4::copy_launch(c->prec, c->buf[1], c->buf[0], c->total, c->stream);
     }
     return e;
@@ -427,14 +445,21 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
         if (!std::isnan(P.umin) && !std::isnan(P.umax)) derive_bounds_params(I, P, P.dim);
     }
     c->total = off;
-    for (int i = 0; i < n_inst; i++)
+    c->caps = af4::kCapQF | af4::kCapPP | af4::kCapI32;
+    for (int i = 0; i < n_inst; i++) {
+        const InstDev &I = c->ih[i];
         for (int l = 0; l < c->dim; l++)
-            if (probs[i].flux[l] != AF_F_LINEAR && probs[i].flux[l] != AF_F_QUAD) c->qf = false;
+            if (probs[i].flux[l] != AF_F_LINEAR && probs[i].flux[l] != AF_F_QUAD) c->caps &= ~af4::kCapQF;
+        const bool pure_poly = !I.ppow && !I.pabs && I.pu0 == 0.0 && std::isinf(I.plo) && I.plo < 0 &&
+                               std::isinf(I.phi) && I.phi > 0;
+        if (!pure_poly) c->caps &= ~af4::kCapPP;
+        if ((double)I.ncell * (double)vbytes(c) >= 4294967296.0) c->caps &= ~af4::kCapI32;
+    }
     // default tile variant: the first one built for this combination (the
     // residual kernel, unlimited and unblended, fits wherever the stage does)
     c->variant = -1;
     for (int v = 0; v < af4::stage_num_variants(c->dim); v++)
-        if (af4::stage_supported(c->dim, c->prec, c->lim, c->si, c->qf, v)) {
+        if (af4::stage_supported(c->dim, c->prec, c->lim, c->si, c->caps, v)) {
             c->variant = v;
             break;
         }
@@ -540,7 +565,7 @@ af_status af_set_variant(af_ctx *c, int v)
 {
     if (!c) return AF_ERR_ARG;
     if (v < 0 || v >= af4::stage_num_variants(c->dim)) return fail(c, AF_ERR_ARG, "variant out of range");
-    if (!af4::stage_supported(c->dim, c->prec, c->lim, c->si, c->qf, v))
+    if (!af4::stage_supported(c->dim, c->prec, c->lim, c->si, c->caps, v))
         return fail(c, AF_ERR_UNSUPPORTED, "tile variant not built for this combination");
     HIPOK(c, hipStreamSynchronize(c->stream));
     drop_graph(c);
@@ -592,9 +617,12 @@ af_status af_set_state(af_ctx *c, int inst, const double *const *dofs, double t)
     InstState st;
     std::memset(&st, 0, sizeof st);
     st.t = t;
+    st.vmin_key = af4::kKeyMinEmpty;
+    st.vmax_key = af4::kKeyMaxEmpty;
     HIPOK(c, hipMemcpyAsync(c->d_st + inst, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
     HIPOK(c, hipStreamSynchronize(c->stream));
     c->have_state[inst] = 1;
+    c->keys_fresh = false;  // the new state's min / max are not reduced yet
     return AF_OK;
 }
 
@@ -633,14 +661,16 @@ af_status af_step(af_ctx *c, int nsteps, double t_end, const double *dt_prescrib
                 return fail(c, AF_ERR_ARG, "af_step: prescribed dt must be finite and >= 0");
     if ((s = upload_ctl(c, t_end, dt_prescribed)) != AF_OK) return s;
     if (nsteps == 0) return finish_step(c, dt_used);
+    const bool ws0 = !(c->keys_fresh && cfl_from_keys(c)), ws = !cfl_from_keys(c);
+    c->keys_fresh = false;  // until the launch below has completed
     if (nsteps == 1) {
-        HIPOK(c, enqueue_step(c, nullptr, nullptr));
+        HIPOK(c, enqueue_step(c, ws0, nullptr, nullptr));
     } else {
-        if (!c->gexec || c->graph_steps != nsteps) {
+        if (!c->gexec || c->graph_steps != nsteps || c->graph_ws != ws0) {
             drop_graph(c);
             HIPOK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
             hipError_t e = hipSuccess;
-            for (int k = 0; k < nsteps && e == hipSuccess; k++) e = enqueue_step(c, nullptr, nullptr);
+            for (int k = 0; k < nsteps && e == hipSuccess; k++) e = enqueue_step(c, k == 0 ? ws0 : ws, nullptr, nullptr);
             hipGraph_t g = nullptr;
             hipError_t e2 = hipStreamEndCapture(c->stream, &g);
             if (e != hipSuccess || e2 != hipSuccess) {
@@ -651,10 +681,13 @@ af_status af_step(af_ctx *c, int nsteps, double t_end, const double *dt_prescrib
             c->graph = g;
             HIPOK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
             c->graph_steps = nsteps;
+            c->graph_ws = ws0;
         }
         HIPOK(c, hipGraphLaunch(c->gexec, c->stream));
     }
-    return finish_step(c, dt_used);
+    s = finish_step(c, dt_used);
+    c->keys_fresh = s == AF_OK && cfl_from_keys(c);
+    return s;
 }
 
 af_status af_step_timed(af_ctx *c, int nsteps, double t_end, const double *dt_prescribed, double *mean_stage_ms,
@@ -669,7 +702,9 @@ af_status af_step_timed(af_ctx *c, int nsteps, double t_end, const double *dt_pr
     for (auto &e : ev) HIPOK(c, hipEventCreate(&e));
     size_t next = 0;
     hipError_t err = hipSuccess;
-    for (int k = 0; k < nsteps && err == hipSuccess; k++) err = enqueue_step(c, &ev, &next);
+    const bool ws0 = !(c->keys_fresh && cfl_from_keys(c)), ws = !cfl_from_keys(c);
+    c->keys_fresh = false;
+    for (int k = 0; k < nsteps && err == hipSuccess; k++) err = enqueue_step(c, k == 0 ? ws0 : ws, &ev, &next);
     hipError_t se = hipStreamSynchronize(c->stream);
     double total = 0;
     for (size_t k = 0; k + 1 < next; k += 2) {
@@ -682,7 +717,9 @@ af_status af_step_timed(af_ctx *c, int nsteps, double t_end, const double *dt_pr
         return fail(c, AF_ERR_DEVICE, std::string("af_step_timed: ") + hipGetErrorString(err != hipSuccess ? err : se));
     if (mean_stage_ms) *mean_stage_ms = next ? total / (next / 2) : 0.0;
     if (launches) *launches = (int)(next / 2);
-    return finish_step(c, nullptr);
+    s = finish_step(c, nullptr);
+    c->keys_fresh = s == AF_OK && cfl_from_keys(c);
+    return s;
 }
 
 af_status af_residual(af_ctx *c, int inst, double *const *rhs)

@@ -48,18 +48,37 @@ __global__ void __launch_bounds__(256) wavespeed_kernel(const InstDev *inst, con
     if (bad) atomicOr(&st[ch.x].flags, 1u);
 }
 
-__global__ void finalize_kernel(int n_inst, const InstDev *inst, const StepCtl *ctl, const double *dtp, InstState *st)
+// from_keys: the wave speed comes from the min / max average written by the
+// previous step's last stage.  Valid when every |f_l'| is convex on the
+// bounds interval (linear and quadratic fluxes, no interior maxima): then the
+// maximum of alpha_int over all faces is max(|f_l'(min)|, |f_l'(max)|),
+// evaluated here in FP64 exactly as the wave-speed kernel evaluates it per
+// face, so the time step is the same to the bit.
+__global__ void finalize_kernel(int n_inst, const InstDev *inst, const StepCtl *ctl, const double *dtp, InstState *st,
+                                int dim, int from_keys)
 {
     for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n_inst; i += blockDim.x * gridDim.x) {
         const double te = ctl->t_end;
+        const InstDev &I = inst[i];
+        double w = __longlong_as_double((long long)st[i].wmax);
+        if (from_keys) {
+            const double lo = ordered_value(st[i].vmin_key), hi = ordered_value(st[i].vmax_key);
+            const double big = 1e6 * fmax(fmax(fabs(I.umin), fabs(I.umax)), 1.0);
+            if (!(fabs(lo) <= big && fabs(hi) <= big)) st[i].flags |= 1u;  // divergent or non-finite
+            Phys<double> P;
+            P.load(I, dim);
+            w = 0.0;
+            for (int l = 0; l < dim; l++) w = fmax(w, P.alpha_int(l, lo, hi) * I.idx1[l] + I.kmax * I.idx2[l]);
+        }
         double dt;
         if (ctl->prescribed) {
             dt = dtp[i];
         } else {
-            const double w = __longlong_as_double((long long)st[i].wmax);
-            dt = w > 0.0 ? inst[i].cfl / w : (te > 0.0 ? te - st[i].t : 0.0);
+            dt = w > 0.0 ? I.cfl / w : (te > 0.0 ? te - st[i].t : 0.0);
         }
         st[i].wmax = 0ull;
+        st[i].vmin_key = kKeyMinEmpty;
+        st[i].vmax_key = kKeyMaxEmpty;
         if (te > 0.0) {
             const double rem = te - st[i].t;
             if (rem <= 1e-12 * te) dt = 0.0;  // remainder is rounding, not a step
@@ -160,10 +179,10 @@ hipError_t wavespeed_launch(int dim, int prec, const InstDev *inst, const int2 *
 }
 
 hipError_t finalize_launch(int n_inst, const InstDev *inst, const StepCtl *ctl, const double *dtp, InstState *st,
-                           hipStream_t s)
+                           int dim, bool from_keys, hipStream_t s)
 {
     int nb = (n_inst + 255) / 256;
-    hipLaunchKernelGGL(finalize_kernel, dim3(nb), dim3(256), 0, s, n_inst, inst, ctl, dtp, st);
+    hipLaunchKernelGGL(finalize_kernel, dim3(nb), dim3(256), 0, s, n_inst, inst, ctl, dtp, st, dim, from_keys ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -228,19 +247,19 @@ VariantInfo stage_variant(int dim, int v)
     return r;
 }
 
-bool stage_supported(int dim, int prec, bool lim, bool si, bool qf, int variant)
+bool stage_supported(int dim, int prec, bool lim, bool si, unsigned caps, int variant)
 {
     if (dim == 1) return stage_supported_d1(prec, lim, si, variant);
-    if (dim == 2) return stage_supported_d2(prec, lim, si, qf, variant);
+    if (dim == 2) return stage_supported_d2(prec, lim, si, caps, variant);
     if (dim == 3) return stage_supported_d3(prec, lim, si, variant);
     return false;
 }
 
-hipError_t stage_launch(int dim, int prec, bool lim, bool si, bool qf, int variant, int nblocks, const void *params,
+hipError_t stage_launch(int dim, int prec, bool lim, bool si, unsigned caps, int variant, int nblocks, const void *params,
                         hipStream_t s)
 {
     if (dim == 1) return stage_launch_d1(prec, lim, si, variant, nblocks, params, s);
-    if (dim == 2) return stage_launch_d2(prec, lim, si, qf, variant, nblocks, params, s);
+    if (dim == 2) return stage_launch_d2(prec, lim, si, caps, variant, nblocks, params, s);
     if (dim == 3) return stage_launch_d3(prec, lim, si, variant, nblocks, params, s);
     return hipErrorInvalidValue;
 }

@@ -13,19 +13,26 @@ struct VariantInfo {
 int stage_num_variants(int dim);
 VariantInfo stage_variant(int dim, int v);
 
+// Properties of a context that specialised stage kernels rely on.
+enum : unsigned {
+    kCapQF = 1,   // every flux of every instance is c1 u + c2 u^2 (linear or Burgers)
+    kCapPP = 2,   // every potential is c1 u + c2 u^2 + c3 u^3 without clamps or signs
+    kCapI32 = 4,  // every DoF plane of every instance holds fewer than 2^32 bytes
+};
+
 // One stage launch over nblocks (instance, tile) work items.
 // params points to a StageParams<float> or StageParams<double>.
 // Returns hipErrorInvalidValue for a combination that is not built.
-hipError_t stage_launch(int dim, int prec, bool lim, bool si, bool qf, int variant, int nblocks, const void *params,
+hipError_t stage_launch(int dim, int prec, bool lim, bool si, unsigned caps, int variant, int nblocks, const void *params,
                         hipStream_t s);
-// true if the (dim, prec, lim, si, variant) kernel is built (LDS fits)
-// qf: every flux of every instance is c1 u + c2 u^2 (linear or Burgers)
-bool stage_supported(int dim, int prec, bool lim, bool si, bool qf, int variant);
+// true if the (dim, prec, lim, si, variant) kernel is built (LDS fits) and
+// applies to a context with the given capabilities
+bool stage_supported(int dim, int prec, bool lim, bool si, unsigned caps, int variant);
 bool stage_supported_d1(int prec, bool lim, bool si, int variant);
-bool stage_supported_d2(int prec, bool lim, bool si, bool qf, int variant);
+bool stage_supported_d2(int prec, bool lim, bool si, unsigned caps, int variant);
 bool stage_supported_d3(int prec, bool lim, bool si, int variant);
 hipError_t stage_launch_d1(int prec, bool lim, bool si, int variant, int nblocks, const void *params, hipStream_t s);
-hipError_t stage_launch_d2(int prec, bool lim, bool si, bool qf, int variant, int nblocks, const void *params,
+hipError_t stage_launch_d2(int prec, bool lim, bool si, unsigned caps, int variant, int nblocks, const void *params,
                            hipStream_t s);
 hipError_t stage_launch_d3(int prec, bool lim, bool si, int variant, int nblocks, const void *params, hipStream_t s);
 
@@ -35,9 +42,11 @@ constexpr int kWaveChunk = 2048;  // cells per wave-speed block (rounded up to w
 hipError_t wavespeed_launch(int dim, int prec, const InstDev *inst, const int2 *chunks, int nchunks, const void *U,
                             InstState *st, hipStream_t s);
 
-// dt and t of every instance from the wave speeds (or the prescribed steps).
+// dt and t of every instance from the wave speeds (or the prescribed steps);
+// from_keys: from the min / max averages reduced by the previous step's last
+// stage instead of the wave-speed kernel (fluxes with convex |f'| only).
 hipError_t finalize_launch(int n_inst, const InstDev *inst, const StepCtl *ctl, const double *dtp, InstState *st,
-                           hipStream_t s);
+                           int dim, bool from_keys, hipStream_t s);
 
 // dst = src over n values.
 hipError_t copy_launch(int prec, const void *src, void *dst, long long n, hipStream_t s);

@@ -115,10 +115,21 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
     const bool own0 = ownx && oy + cj < n1, own1 = ownx && oy + cj + 1 < n1;
     const long long g0 = (ox + ci) + (long long)n0 * (oy + cj), g1 = g0 + n0;
 
+    const T inf = __builtin_huge_val();
+    T vlo = inf, vhi = -inf;  // min / max of the averages written
     if (!residual && dtd == 0.0) {
+        // the instance has reached its end time: the stage leaves it unchanged
         for (int z = 0; z < 4; z++) {
             if (own0) out[z * kst + g0] = in[z * kst + g0];
             if (own1) out[z * kst + g1] = in[z * kst + g1];
+        }
+        if (p.minmax) {
+            if (own0) vlo = vhi = in[g0];
+            if (own1) {
+                vlo = fmin(vlo, in[g1]);
+                vhi = fmax(vhi, in[g1]);
+            }
+            minmax_wave(&p.st[wk.x], vlo, vhi);
         }
         return;
     }
@@ -425,11 +436,14 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
             clamp_mag = fmax(clamp_mag, (double)fabs(cl - v));
             v = cl;
         }
+        vlo = fmin(vlo, v);
+        vhi = fmax(vhi, v);
         out[gi] = v;
     }
     if (!residual) {
         if (bad) atomicOr(&p.st[wk.x].flags, 1u);
         if constexpr (LIM) atomic_max_wave(&p.st[wk.x].clampmax, clamp_mag);
+        if (p.minmax) minmax_wave(&p.st[wk.x], vlo, vhi);
     }
 }
 

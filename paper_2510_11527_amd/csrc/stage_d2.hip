@@ -1,5 +1,5 @@
 // stage_d2.hip -- instantiations and dispatch of the 2D stage kernels.
-#include "stage2q_kernel.hpp"
+#include "stage2o_kernel.hpp"
 #include "variants.h"
 
 namespace af4 {
@@ -32,25 +32,29 @@ hipError_t launch_tuned(int nblocks, const void *params, hipStream_t s)
     }
 }
 
-template <class T, bool LIM, int TX, int TY, int NT>
-hipError_t launch_quad(int nblocks, const void *params, hipStream_t s)
+template <class T, bool LIM, bool PP, int TX, int TY, int NT>
+hipError_t launch_own(int nblocks, const void *params, hipStream_t s)
 {
-    if constexpr (stage2q_lds_bytes<T, LIM, TX, TY>() > kLdsCap) {
+    if constexpr (stage2o_lds_bytes<T, LIM, TX, TY>() > kLdsCap) {
         return hipErrorInvalidValue;
     } else {
-        hipLaunchKernelGGL((stage2q_kernel<T, LIM, TX, TY, NT>), dim3(nblocks), dim3(NT), 0, s,
+        hipLaunchKernelGGL((stage2o_kernel<T, LIM, PP, TX, TY, NT>), dim3(nblocks), dim3(NT), 0, s,
                            *(const StageParams<T> *)params);
         return hipGetLastError();
     }
 }
 
 template <class T, int TX, int TY, int NT, int KIND>
-hipError_t launch_kind(bool lim, bool si, bool qf, int nblocks, const void *params, hipStream_t s)
+hipError_t launch_kind(bool lim, bool si, unsigned caps, int nblocks, const void *params, hipStream_t s)
 {
-    if constexpr (KIND == 3) {
-        if (si || !qf) return hipErrorInvalidValue;
-        return lim ? launch_quad<T, true, TX, TY, NT>(nblocks, params, s)
-                   : launch_quad<T, false, TX, TY, NT>(nblocks, params, s);
+    const bool qf = (caps & kCapQF) != 0;
+    if constexpr (KIND == 4) {
+        if (si || !qf || !(caps & kCapI32)) return hipErrorInvalidValue;
+        const bool pp = (caps & kCapPP) != 0;
+        if (lim) return pp ? launch_own<T, true, true, TX, TY, NT>(nblocks, params, s)
+                           : launch_own<T, true, false, TX, TY, NT>(nblocks, params, s);
+        return pp ? launch_own<T, false, true, TX, TY, NT>(nblocks, params, s)
+                  : launch_own<T, false, false, TX, TY, NT>(nblocks, params, s);
     } else if constexpr (KIND == 0) {
         if (lim) return si ? launch_generic<T, true, true, TX, TY, NT>(nblocks, params, s)
                            : launch_generic<T, true, false, TX, TY, NT>(nblocks, params, s);
@@ -69,11 +73,12 @@ hipError_t launch_kind(bool lim, bool si, bool qf, int nblocks, const void *para
 }
 
 template <class T, int TX, int TY, int KIND>
-bool fits_kind(bool lim, bool si, bool qf)
+bool fits_kind(bool lim, bool si, unsigned caps)
 {
-    if constexpr (KIND == 3) {
-        if (si || !qf) return false;
-        return stage2q_lds_bytes<T, true, TX, TY>() <= kLdsCap && stage2q_lds_bytes<T, false, TX, TY>() <= kLdsCap;
+    const bool qf = (caps & kCapQF) != 0;
+    if constexpr (KIND == 4) {
+        if (si || !qf || !(caps & kCapI32)) return false;
+        return stage2o_lds_bytes<T, true, TX, TY>() <= kLdsCap && stage2o_lds_bytes<T, false, TX, TY>() <= kLdsCap;
     } else if constexpr (KIND == 0) {
         if (lim) return si ? stage_lds_bytes<2, T, true, true, TX, TY, 1>() <= kLdsCap
                            : stage_lds_bytes<2, T, true, false, TX, TY, 1>() <= kLdsCap;
@@ -92,26 +97,26 @@ bool fits_kind(bool lim, bool si, bool qf)
 
 }  // namespace
 
-bool stage_supported_d2(int prec, bool lim, bool si, bool qf, int variant)
+bool stage_supported_d2(int prec, bool lim, bool si, unsigned caps, int variant)
 {
     switch (variant) {
 #define AF4_FITS(V, TX, TY, TZ, NT, KIND, NAME) \
-    case V: return prec == 32 ? fits_kind<float, TX, TY, KIND>(lim, si, qf) : fits_kind<double, TX, TY, KIND>(lim, si, qf);
+    case V: return prec == 32 ? fits_kind<float, TX, TY, KIND>(lim, si, caps) : fits_kind<double, TX, TY, KIND>(lim, si, caps);
         AF4_VARIANTS_D2(AF4_FITS)
 #undef AF4_FITS
     }
     return false;
 }
 
-hipError_t stage_launch_d2(int prec, bool lim, bool si, bool qf, int variant, int nblocks, const void *params,
+hipError_t stage_launch_d2(int prec, bool lim, bool si, unsigned caps, int variant, int nblocks, const void *params,
                            hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
     switch (variant) {
 #define AF4_CASE(V, TX, TY, TZ, NT, KIND, NAME)                                                            \
     case V:                                                                                                \
-        return prec == 32 ? launch_kind<float, TX, TY, NT, KIND>(lim, si, qf, nblocks, params, s)         \
-                          : launch_kind<double, TX, TY, NT, KIND>(lim, si, qf, nblocks, params, s);
+        return prec == 32 ? launch_kind<float, TX, TY, NT, KIND>(lim, si, caps, nblocks, params, s)         \
+                          : launch_kind<double, TX, TY, NT, KIND>(lim, si, caps, nblocks, params, s);
         AF4_VARIANTS_D2(AF4_CASE)
 #undef AF4_CASE
     }

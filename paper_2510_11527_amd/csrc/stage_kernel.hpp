@@ -215,6 +215,23 @@ __device__ __forceinline__ T rk_combine(int stage, T fe, T un)
     return fe;
 }
 
+// Wave-wide min and max of the averages a thread wrote, then one atomic pair
+// per wave into the instance's ordered keys (the CFL wave speed of the next
+// step is evaluated from them when every flux has a convex |f'|).
+template <class T>
+__device__ __forceinline__ void minmax_wave(InstState *st, T lo, T hi)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o));
+        hi = fmax(hi, __shfl_xor(hi, o));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&st->vmin_key, ordered_key((double)lo));
+        atomicMax(&st->vmax_key, ordered_key((double)hi));
+    }
+}
+
 // Wave-wide max of a non-negative double, then one atomic per wave.
 __device__ __forceinline__ void atomic_max_wave(unsigned long long *dst, double v)
 {
@@ -257,13 +274,18 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
     const bool residual = p.stage == 4;
     const double dtd = p.st[wk.x].dt;
 
+    const T inf = __builtin_huge_val();
+    T vlo = inf, vhi = -inf;  // min / max of the averages written
     if (!residual && dtd == 0.0) {
         // the instance has reached its end time: the stage leaves it unchanged
         box_loop<G::T0, G::T1, G::T2, NT>([&](int i, int j, int k) {
             if (ox + i >= n0 || oy + j >= n1 || oz + k >= n2) return;
             long long gi = (ox + i) + (long long)n0 * ((oy + j) + (long long)n1 * (oz + k));
             for (int z = 0; z < NB; z++) out[z * kst + gi] = in[z * kst + gi];
+            vlo = fmin(vlo, in[gi]);
+            vhi = fmax(vhi, in[gi]);
         });
+        if (p.minmax) minmax_wave(&p.st[wk.x], vlo, vhi);
         return;
     }
 
@@ -590,11 +612,14 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
             clamp_mag = fmax(clamp_mag, (double)fabs(c - v));
             v = c;
         }
+        vlo = fmin(vlo, v);
+        vhi = fmax(vhi, v);
         out[gi] = v;
     });
     if (!residual) {
         if (bad) atomicOr(&p.st[wk.x].flags, 1u);
         if constexpr (LIM) atomic_max_wave(&p.st[wk.x].clampmax, clamp_mag);
+        if (p.minmax) minmax_wave(&p.st[wk.x], vlo, vhi);
     }
 }
 

@@ -5,14 +5,15 @@
 namespace af4 {
 
 #define AF4_VARIANTS_D1(X) X(0, 256, 1, 1, 256, "generic-256") X(1, 128, 1, 1, 128, "generic-128")
-// 2D: KIND 3 = quadratic-flux kernel on parity-split sub-grids, 1 = tuned
-// kernel with {u,a,f_x,f_y} table, 2 = tuned kernel with {u,a} table,
-// 0 = generic kernel (the only one with SI blending)
+// 2D: KIND 4 = thread-owned-items kernel for fluxes c1 u + c2 u^2, 1 = tuned
+// kernel with a {u,a,f_x,f_y} half-grid table (any flux), 2 = tuned kernel
+// with a {u,a} table (fluxes c1 u + c2 u^2), 0 = generic kernel (the only one
+// with SI blending)
 #define AF4_VARIANTS_D2(X)                                                                          \
-    X(0, 32, 16, 1, 256, 2, "2d-table2-32x16") X(1, 32, 16, 1, 256, 3, "2d-quad-32x16")              \
-    X(2, 32, 16, 1, 256, 1, "2d-table4-32x16") X(3, 16, 16, 1, 128, 2, "2d-table2-16x16")            \
-    X(4, 32, 8, 1, 128, 2, "2d-table2-32x8") X(5, 32, 8, 1, 128, 3, "2d-quad-32x8")                  \
-    X(6, 32, 8, 1, 256, 0, "generic-32x8") X(7, 16, 16, 1, 256, 0, "generic-16x16")
+    X(0, 32, 16, 1, 256, 4, "2d-own-32x16") X(1, 32, 8, 1, 128, 4, "2d-own-32x8")                    \
+    X(2, 32, 16, 1, 256, 1, "2d-table4-32x16") X(3, 32, 8, 1, 128, 1, "2d-table4-32x8")              \
+    X(4, 32, 16, 1, 256, 2, "2d-table2-32x16") X(5, 32, 8, 1, 256, 0, "generic-32x8")                \
+    X(6, 16, 16, 1, 256, 0, "generic-16x16")
 #define AF4_VARIANTS_D3(X) X(0, 8, 8, 4, 256, "generic-8x8x4") X(1, 8, 4, 4, 128, "generic-8x4x4") X(2, 4, 4, 4, 64, "generic-4x4x4")
 
 }  // namespace af4

@@ -267,3 +267,37 @@ def test_conservation_and_bounds_long_run():
     assert nrm["min_avg"] >= spec["umin"] and nrm["max_avg"] <= spec["umax"]
     assert nrm["min_pv"] >= spec["umin"] and nrm["max_pv"] <= spec["umax"]
     assert nrm["max_clamp"] <= 4 * np.spacing(1.0)
+
+
+@pytest.mark.parametrize("name,integ", [("c2", "ssprk3"), ("c4", "ssprk3"), ("c5", "ssprk3"), ("c1", "ssprk3"),
+                                        ("c2", "euler")])
+def test_cfl_from_last_stage_minmax_equals_wave_speed_pass(name, integ):
+    """For convex |f'| the last stage of a step reduces the min / max average
+    and the next step's CFL step comes from them; it must equal, to the bit,
+    the step the separate FP64 wave-speed pass computes on the same state."""
+    if name == "c4":
+        items = W.config4(n_inst=4, sizes=(32, 48))
+    else:
+        items = [_steps_case(name)]
+    specs = [s for s, _ in items]
+    a = af.Context(specs, integrator=integ)
+    for i, (_, U) in enumerate(items):
+        a.set_state(i, U)
+    a.step(1)                      # wave-speed pass
+    a.step(3)                      # min / max of the last stage (graph)
+    mids = [a.get_state(i) for i in range(len(items))]
+    used_keys = a.step(1)
+    b = af.Context(specs, integrator=integ)
+    for i, (V, t) in enumerate(mids):
+        b.set_state(i, V, t)
+    used_ws = b.step(1)            # fresh state: wave-speed pass
+    note("cfl %s %s keys=%s ws=%s" % (name, integ, used_keys[:2], used_ws[:2]))
+    assert np.array_equal(np.asarray(used_keys), np.asarray(used_ws))
+    for i in range(len(items)):
+        A, ta = a.get_state(i)
+        B, tb = b.get_state(i)
+        assert ta == tb
+        for x, y in zip(A, B):
+            assert np.array_equal(x, y)
+    a.close()
+    b.close()
