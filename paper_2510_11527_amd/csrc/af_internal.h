@@ -36,6 +36,11 @@ struct InstDev {
     double idx1[3];      // 1 / dx_l
     double idx2[3];      // 1 / dx_l^2
     double i6dx[3];      // 1 / (6 dx_l)
+    // the same parameters rounded to FP32 on the host, for the FP32 kernels
+    float f_umin, f_umax;
+    float f_fp0[3];
+    float f_pc[3];       // pc1, pc2, pc3
+    float f_idx1[3], f_idx2[3], f_i6dx[3];
 };
 
 // Control block read by the time-step kernels (uploaded before each af_step).
@@ -58,12 +63,15 @@ struct InstState {
     long long steps;     // steps with dt > 0
     double mu[3];        // dt / dx_l of the current step
     double nu[3];        // dt / dx_l^2 of the current step
+    float f_dt;          // dt, mu and nu rounded to FP32
+    float f_mu[3], f_nu[3];
+    float pad2;
 };
 
 template <class T>
 struct StageParams {
     const InstDev *inst;
-    const int2 *work;    // (instance, tile) per block
+    const int4 *work;    // (instance, tile x, tile y, tile z) per block
     int nwork;
     const T *in;         // stage input U^(s-1)
     const T *un;         // U^n for the RK combination
@@ -72,6 +80,17 @@ struct StageParams {
     int stage;           // 0: forward Euler, 1..3: SSP-RK3 stage, 4: residual
     int minmax;          // 1: reduce min / max of the written averages into vmin_key / vmax_key
 };
+
+// Read-only per-launch parameters are read through the constant address
+// space so that uniform reads become scalar loads into SGPRs (the compiler
+// does not prove that on its own once the kernel also writes memory).
+template <class T>
+using const_ptr = const __attribute__((address_space(4))) T *;
+template <class T>
+__device__ __forceinline__ const_ptr<T> as_constant(const T *p)
+{
+    return (const_ptr<T>)p;
+}
 
 // Order-preserving map of doubles to unsigned integers: a < b <=> key(a) <
 // key(b) for non-NaN values, so that unsigned atomic min / max reduce doubles.

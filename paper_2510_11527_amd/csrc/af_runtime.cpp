@@ -30,7 +30,7 @@ struct af_ctx {
     InstState *d_st = nullptr;
     StepCtl *d_ctl = nullptr;
     double *d_dtp = nullptr;
-    int2 *d_work = nullptr;
+    int4 *d_work = nullptr;
     int nwork = 0;
     std::vector<int> work_start, work_count;
     int2 *d_chunks = nullptr;
@@ -141,6 +141,23 @@ double host_kappa_max(int kind, double p0, double p1, double lo, double hi)
     return 0.0;
 }
 
+// FP32 copies of the parameters the FP32 kernels read (rounded to nearest,
+// as a device-side conversion would).
+void set_f32_params(InstDev &I)
+{
+    I.f_umin = (float)I.umin;
+    I.f_umax = (float)I.umax;
+    I.f_pc[0] = (float)I.pc1;
+    I.f_pc[1] = (float)I.pc2;
+    I.f_pc[2] = (float)I.pc3;
+    for (int l = 0; l < 3; l++) {
+        I.f_fp0[l] = (float)I.fp0[l];
+        I.f_idx1[l] = (float)I.idx1[l];
+        I.f_idx2[l] = (float)I.idx2[l];
+        I.f_i6dx[l] = (float)I.i6dx[l];
+    }
+}
+
 void derive_bounds_params(InstDev &I, const af_problem &P, int dim)
 {
     I.kmax = host_kappa_max(P.diff, P.diff_par[0], P.diff_par[1], I.umin, I.umax);
@@ -249,7 +266,7 @@ bool cfl_from_keys(const af_ctx *c) { return (c->caps & af4::kCapQF) != 0; }
 af_status build_work(af_ctx *c)
 {
     af4::VariantInfo vi = af4::stage_variant(c->dim, c->variant);
-    std::vector<int2> work;
+    std::vector<int4> work;
     c->work_start.assign(c->n_inst, 0);
     c->work_count.assign(c->n_inst, 0);
     for (int i = 0; i < c->n_inst; i++) {
@@ -261,13 +278,15 @@ af_status build_work(af_ctx *c)
         }
         c->work_start[i] = (int)work.size();
         c->work_count[i] = (int)nt;
-        for (long long t = 0; t < nt; t++) work.push_back(make_int2(i, (int)t));
+        for (int tz = 0; tz < I.tiles[2]; tz++)
+            for (int ty = 0; ty < I.tiles[1]; ty++)
+                for (int tx = 0; tx < I.tiles[0]; tx++) work.push_back(make_int4(i, tx, ty, tz));
     }
     if (c->d_work) (void)hipFree(c->d_work);
     c->d_work = nullptr;
     c->nwork = (int)work.size();
-    HIPOK(c, hipMalloc(&c->d_work, sizeof(int2) * work.size()));
-    HIPOK(c, hipMemcpy(c->d_work, work.data(), sizeof(int2) * work.size(), hipMemcpyHostToDevice));
+    HIPOK(c, hipMalloc(&c->d_work, sizeof(int4) * work.size()));
+    HIPOK(c, hipMemcpy(c->d_work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice));
     HIPOK(c, hipMemcpy(c->d_inst, c->ih.data(), sizeof(InstDev) * c->n_inst, hipMemcpyHostToDevice));
     return AF_OK;
 }
@@ -443,6 +462,7 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
         I.cfl = P.cfl;
         I.si_gamma = P.si_blend ? P.si_gamma : 0.0;
         if (!std::isnan(P.umin) && !std::isnan(P.umax)) derive_bounds_params(I, P, P.dim);
+        set_f32_params(I);
     }
     c->total = off;
     c->caps = af4::kCapQF | af4::kCapPP | af4::kCapI32;
@@ -453,7 +473,7 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
         const bool pure_poly = !I.ppow && !I.pabs && I.pu0 == 0.0 && std::isinf(I.plo) && I.plo < 0 &&
                                std::isinf(I.phi) && I.phi > 0;
         if (!pure_poly) c->caps &= ~af4::kCapPP;
-        if ((double)I.ncell * (double)vbytes(c) >= 4294967296.0) c->caps &= ~af4::kCapI32;
+        if ((double)(1 << c->dim) * (double)I.kstride * (double)vbytes(c) >= 4294967296.0) c->caps &= ~af4::kCapI32;
     }
     // default tile variant: the first one built for this combination (the
     // residual kernel, unlimited and unblended, fits wherever the stage does)
@@ -603,6 +623,7 @@ af_status af_set_state(af_ctx *c, int inst, const double *const *dofs, double t)
         I.umin = umin;
         I.umax = umax;
         derive_bounds_params(I, P, c->dim);
+        set_f32_params(I);
         HIPOK(c, hipMemcpy(c->d_inst + inst, &I, sizeof I, hipMemcpyHostToDevice));
     }
     std::vector<char> stage((size_t)n * vbytes(c));

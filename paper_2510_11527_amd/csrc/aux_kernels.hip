@@ -87,9 +87,12 @@ __global__ void finalize_kernel(int n_inst, const InstDev *inst, const StepCtl *
         st[i].dt = dt;
         st[i].t += dt;
         if (dt > 0.0) st[i].steps++;
+        st[i].f_dt = (float)dt;
         for (int l = 0; l < 3; l++) {
             st[i].mu[l] = dt * inst[i].idx1[l];
             st[i].nu[l] = dt * inst[i].idx2[l];
+            st[i].f_mu[l] = (float)st[i].mu[l];
+            st[i].f_nu[l] = (float)st[i].nu[l];
         }
     }
 }

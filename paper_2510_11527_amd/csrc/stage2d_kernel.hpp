@@ -97,10 +97,10 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
     const int nb = (int)gridDim.x, b = (int)blockIdx.x;
     const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
     const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3);
-    const int2 wk = p.work[logical];
+    const int4 wk = p.work[logical];
     const InstDev &I = p.inst[wk.x];
     const int n0 = I.n[0], n1 = I.n[1];
-    const int tx0 = wk.y % I.tiles[0], ty0 = wk.y / I.tiles[0];
+    const int tx0 = wk.y, ty0 = wk.z;
     const int ox = tx0 * TX, oy = ty0 * TY;
     const long long kst = I.kstride;
     const T *__restrict__ in = p.in + I.off;

@@ -27,15 +27,25 @@
 
 namespace af4 {
 
+// Buffer-resource word 3 of the gfx9 family (untyped 32-bit data format);
+// raw buffer accesses then range-check byte offsets against num_records:
+// loads beyond it return 0, stores beyond it are dropped.
+constexpr int kBufWord3 = 0x00020000;
+
 template <class T>
-__device__ __forceinline__ T ld_plane(const T *base, unsigned i)
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
 {
-    return *(const T *)((const char *)base + i * (unsigned)sizeof(T));
+    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 template <class T>
-__device__ __forceinline__ void st_plane(T *base, unsigned i, T v)
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, T v)
 {
-    *(T *)((char *)base + i * (unsigned)sizeof(T)) = v;
+    if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+    else {
+        typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+    }
 }
 
 template <class T, bool LIM, bool PP, int TX, int TY, int NT>
@@ -61,31 +71,44 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     const int nb = (int)gridDim.x, b = (int)blockIdx.x;
     const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
     const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3);
-    const int2 wk = p.work[logical];
+    const int4 wk = p.work[logical];
     const InstDev &I = p.inst[wk.x];
-    const int n0 = I.n[0], n1 = I.n[1];
-    const int tx0 = wk.y % I.tiles[0], ty0 = wk.y / I.tiles[0];
+    const auto Ic = as_constant(&p.inst[wk.x]);   // scalar reads of the parameters
+    const auto Sc = as_constant(&p.st[wk.x]);     // (fields this kernel does not write)
+    const int n0 = Ic->n[0], n1 = Ic->n[1];
+    const int tx0 = wk.y, ty0 = wk.z;
     const int ox = tx0 * TX, oy = ty0 * TY;
-    const long long kst = I.kstride;
-    const T *inz[4], *unz[4];
-    T *outz[4];
-#pragma unroll
-    for (int z = 0; z < 4; z++) {
-        inz[z] = p.in + I.off + z * kst;
-        unz[z] = p.un + I.off + z * kst;
-        outz[z] = p.out + I.off + z * kst;
-    }
     const bool residual = p.stage == 4;
-    const double dtd = p.st[wk.x].dt;
+    const double dtd = Sc->dt;
     const int tid = (int)threadIdx.x;
+    // the instance's DoF blocks of the three state buffers as buffer
+    // resources (32-bit offsets, hardware range check); plane z at byte
+    // offset z * kstride * sizeof(T)
+    const unsigned kb = (unsigned)Ic->kstride * (unsigned)sizeof(T);
+    const unsigned blk = 4u * kb;
+    const auto rin = __builtin_amdgcn_make_buffer_rsrc((void *)(p.in + Ic->off), 0, (int)blk, kBufWord3);
+    const auto run = __builtin_amdgcn_make_buffer_rsrc((void *)(p.un + Ic->off), 0, (int)blk, kBufWord3);
+    const auto rout = __builtin_amdgcn_make_buffer_rsrc((void *)(p.out + Ic->off), 0, (int)blk, kBufWord3);
+    auto ld = [&](const __amdgpu_buffer_rsrc_t &r, int z, unsigned gi) -> T {
+        return buf_load<T>(r, gi * (unsigned)sizeof(T), (unsigned)z * kb);
+    };
+    auto st = [&](int z, unsigned gi, T v) { buf_store<T>(rout, gi * (unsigned)sizeof(T), (unsigned)z * kb, v); };
+    // periodic indices: one fold when the grid is wider than a tile plus its
+    // halo (the usual case), a remainder otherwise
+    const bool fold0 = n0 >= TX + 4, fold1 = n1 >= TY + 4;
+    auto wrap = [&](int v, int n, bool fold) -> int {
+        if (fold) return v < 0 ? v + n : (v >= n ? v - n : v);
+        const int r = v % n;
+        return r < 0 ? r + n : r;
+    };
     // own cells: region column x, rows y and y + 1
     const int ci = tid % TX, cj = 2 * (tid / TX);
     const int x = ci + 2, y = cj + 2;
     const bool ownx = ox + ci < n0;
     const bool own0 = ownx && oy + cj < n1, own1 = ownx && oy + cj + 1 < n1;
-    const int gxo = wrap_index(ox + ci, n0);
-    const unsigned g0 = (unsigned)(gxo + n0 * wrap_index(oy + cj, n1));
-    const unsigned g1 = (unsigned)(gxo + n0 * wrap_index(oy + cj + 1, n1));
+    const int gxo = wrap(ox + ci, n0, fold0);
+    const unsigned g0 = (unsigned)(gxo + n0 * wrap(oy + cj, n1, fold1));
+    const unsigned g1 = (unsigned)(gxo + n0 * wrap(oy + cj + 1, n1, fold1));
 
     const T inf = __builtin_huge_val();
     T vlo = inf, vhi = -inf;  // min / max of the averages written
@@ -93,45 +116,52 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         // the instance has reached its end time: the stage leaves it unchanged
 #pragma unroll
         for (int z = 0; z < 4; z++) {
-            if (own0) st_plane(outz[z], g0, ld_plane(inz[z], g0));
-            if (own1) st_plane(outz[z], g1, ld_plane(inz[z], g1));
-        }
-        if (p.minmax) {
-            if (own0) vlo = vhi = ld_plane(inz[0], g0);
-            if (own1) {
-                const T v = ld_plane(inz[0], g1);
-                vlo = fmin(vlo, v);
-                vhi = fmax(vhi, v);
+            const T a = ld(rin, z, g0), b = ld(rin, z, g1);
+            if (own0) st(z, g0, a);
+            if (own1) st(z, g1, b);
+            if (z == 0) {
+                if (own0) vlo = vhi = a;
+                if (own1) {
+                    vlo = fmin(vlo, b);
+                    vhi = fmax(vhi, b);
+                }
             }
-            minmax_wave(&p.st[wk.x], vlo, vhi);
         }
+        if (p.minmax) minmax_wave(&p.st[wk.x], vlo, vhi);
         return;
     }
 
+    // parameters in the kernel's precision (FP32 copies rounded on the host)
+    auto prm = [&](double d, float f) -> T {
+        if constexpr (sizeof(T) == 4) return f;
+        else return (T)d;
+    };
     Phys<T> P;
-    P.load(I, 2);
+    if constexpr (!PP) P.load(I, 2);
     T c1[2], c2[2], c2x2[2];
 #pragma unroll
     for (int l = 0; l < 2; l++) {
-        c1[l] = P.fk[l] == kFLinear ? P.fc[l] : T(0);
-        c2[l] = P.fk[l] == kFQuad ? P.fc[l] : T(0);
+        const T c = prm(Ic->fp0[l], Ic->f_fp0[l]);
+        c1[l] = Ic->fk[l] == kFLinear ? c : T(0);
+        c2[l] = Ic->fk[l] == kFQuad ? c : T(0);
         c2x2[l] = T(2) * c2[l];
     }
-    const T dt = (T)dtd;
-    const T umin = P.umin, umax = P.umax;
+    const T dt = prm(dtd, Sc->f_dt);
+    const T umin = prm(Ic->umin, Ic->f_umin), umax = prm(Ic->umax, Ic->f_umax);
+    const T pc1 = prm(Ic->pc1, Ic->f_pc[0]), pc2 = prm(Ic->pc2, Ic->f_pc[1]), pc3 = prm(Ic->pc3, Ic->f_pc[2]);
     T idx1[2], idx2[2], i6dx[2], mu[2], nu[2];
 #pragma unroll
     for (int l = 0; l < 2; l++) {
-        idx1[l] = (T)I.idx1[l];
-        idx2[l] = (T)I.idx2[l];
-        i6dx[l] = (T)I.i6dx[l];
-        mu[l] = (T)p.st[wk.x].mu[l];
-        nu[l] = (T)p.st[wk.x].nu[l];
+        idx1[l] = prm(Ic->idx1[l], Ic->f_idx1[l]);
+        idx2[l] = prm(Ic->idx2[l], Ic->f_idx2[l]);
+        i6dx[l] = prm(Ic->i6dx[l], Ic->f_i6dx[l]);
+        mu[l] = prm(Sc->mu[l], Sc->f_mu[l]);
+        nu[l] = prm(Sc->nu[l], Sc->f_nu[l]);
     }
     const T K = T(4);
 
     auto pot = [&](T u) -> T {
-        if constexpr (PP) return u * (P.pc1 + u * (P.pc2 + u * P.pc3));
+        if constexpr (PP) return u * (pc1 + u * (pc2 + u * pc3));
         else return P.a(u);
     };
     auto fq = [&](int l, T u) -> T { return u * (c1[l] + c2[l] * u); };
@@ -148,45 +178,61 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     auto pxi = [&](int xx, int yy) -> int { return (xx - 1) + CXE * (yy - 2); };
     auto pyi = [&](int xx, int yy) -> int { return NXC + (xx - 2) + TX * (yy - 1); };
 
-    // U^n of the own cells (used by the RK combination), fetched first
-    const bool rk = !residual && p.stage >= 2;
+    // ---- A: cells of the tile and its halo -> LDS with their potentials.
+    // Loads are issued in the order they are consumed (own cells, halo cells,
+    // then U^n, which is needed only by the updates): the memory counter the
+    // waits use is in order.
+    constexpr int NHR = 4 * RX, NH = NHR + 4 * TY;   // halo: 4 rows, then 4 columns
+    constexpr int NHI = (NH + NT - 1) / NT;          // halo cells per thread
+    T own[2][4], halo[NHI][4];
+    int hx[NHI], hy[NHI];
+#pragma unroll
+    for (int z = 0; z < 4; z++) {
+        own[0][z] = ld(rin, z, g0);
+        own[1][z] = ld(rin, z, g1);
+    }
+#pragma unroll
+    for (int k = 0; k < NHI; k++) {
+        // halo cell h: rows 0, 1, TY+2, TY+3 over all columns, then columns
+        // 0, 1, TX+2, TX+3 over rows [2, TY+2); threads past the end redo the
+        // last one (same value to the same place: no branch, and the loads
+        // stay ahead of the U^n loads)
+        const int h = min(tid + k * NT, NH - 1);
+        int xx, yy;
+        if (h < NHR) {
+            const int r = h / RX;
+            xx = h - r * RX;
+            yy = r < 2 ? r : r + TY;
+        } else {
+            const int h2 = h - NHR, q = h2 & 3;
+            yy = 2 + (h2 >> 2);
+            xx = q < 2 ? q : q + TX;
+        }
+        hx[k] = xx;
+        hy[k] = yy;
+        const unsigned gi = (unsigned)(wrap(ox + xx - 2, n0, fold0) + n0 * wrap(oy + yy - 2, n1, fold1));
+#pragma unroll
+        for (int z = 0; z < 4; z++) halo[k][z] = ld(rin, z, gi);
+    }
+    // U^n of the own cells (the RK combination of stages 2 and 3; the other
+    // stages read it too, from cache, which keeps the load sequence free of
+    // branches so that the waits above stay exact)
     T unv[2][4];
 #pragma unroll
     for (int z = 0; z < 4; z++) {
-        unv[0][z] = (rk && own0) ? ld_plane(unz[z], g0) : T(0);
-        unv[1][z] = (rk && own1) ? ld_plane(unz[z], g1) : T(0);
+        unv[0][z] = ld(run, z, g0);
+        unv[1][z] = ld(run, z, g1);
     }
-
-    // ---- A: cells of the tile and its halo -> LDS with their potentials
-    auto load_cell = [&](int xx, int yy, unsigned gi) {
-        const T ub = ld_plane(inz[0], gi), ux = ld_plane(inz[1], gi);
-        const T uy = ld_plane(inz[2], gi), uc = ld_plane(inz[3], gi);
-        cg[cgi(xx, yy)] = V2<T>{ub, pot(ub)};
-        hs[sg(SXF, xx, yy)] = V2<T>{ux, pot(ux)};
-        hs[sg(SYF, xx, yy)] = V2<T>{uy, pot(uy)};
-        hs[sg(SK, xx, yy)] = V2<T>{uc, pot(uc)};
+    auto put_cell = [&](int xx, int yy, const T *u) {
+        cg[cgi(xx, yy)] = V2<T>{u[0], pot(u[0])};
+        hs[sg(SXF, xx, yy)] = V2<T>{u[1], pot(u[1])};
+        hs[sg(SYF, xx, yy)] = V2<T>{u[2], pot(u[2])};
+        hs[sg(SK, xx, yy)] = V2<T>{u[3], pot(u[3])};
     };
-    load_cell(x, y, g0);
-    load_cell(x, y + 1, g1);
-    {
-        // halo: rows 0, 1, TY+2, TY+3 (all columns), then columns 0, 1,
-        // TX+2, TX+3 of rows [2, TY+2)
-        constexpr int NR = 4 * RX, NH = NR + 4 * TY;
-        for (int h = tid; h < NH; h += NT) {
-            int xx, yy;
-            if (h < NR) {
-                const int r = h / RX;
-                xx = h - r * RX;
-                yy = r < 2 ? r : r + TY;
-            } else {
-                const int h2 = h - NR, k = h2 & 3;
-                yy = 2 + (h2 >> 2);
-                xx = k < 2 ? k : k + TX;
-            }
-            const int gx = wrap_index(ox + xx - 2, n0), gy = wrap_index(oy + yy - 2, n1);
-            load_cell(xx, yy, (unsigned)(gx + n0 * gy));
-        }
-    }
+    put_cell(x, y, own[0]);
+    put_cell(x, y + 1, own[1]);
+#pragma unroll
+    for (int k = 0; k < NHI; k++) put_cell(hx[k], hy[k], halo[k]);
     __syncthreads();
 
     // ---- B: cell centres by inverting the tensor Simpson rule
@@ -218,7 +264,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     }
     __syncthreads();
 
-    double clamp_mag = 0.0;
+    T clamp_mag = T(0);  // largest safeguard clamp of an average
     bool bad = false;
 
     // ---- C: the six point values of the two own cells
@@ -254,7 +300,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
 #pragma unroll
             for (int z = 1; z < 4; z++) {
                 if (residual) {
-                    st_plane(outz[z], gi, R[c][z - 1]);
+                    st(z, gi, R[c][z - 1]);
                     continue;
                 }
                 const int s = z == 1 ? SXF : (z == 2 ? SYF : SK);
@@ -263,7 +309,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
                 if constexpr (LIM) v = clampb(v, umin, umax);
                 v = rk_combine(p.stage, v, unv[c][z]);
                 if constexpr (LIM) v = clampb(v, umin, umax);
-                st_plane(outz[z], gi, v);
+                st(z, gi, v);
             }
         }
     }
@@ -387,7 +433,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         const T dPx = pc[pxi(x + 1, yy)] - T(2) * pc[pxi(x, yy)] + pc[pxi(x - 1, yy)];
         const T dPy = pc[pyi(x, yy + 1)] - T(2) * pc[pyi(x, yy)] + pc[pyi(x, yy - 1)];
         if (residual) {
-            st_plane(outz[0], gi, (dPx * idx2[0] + dPy * idx2[1]) - (dFx * idx1[0] + dFy * idx1[1]));
+            st(0, gi, (dPx * idx2[0] + dPy * idx2[1]) - (dFx * idx1[0] + dFy * idx1[1]));
             continue;
         }
         const T u = cg[cgi(x, yy)].x;
@@ -395,22 +441,22 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         if (!isfinite(v)) bad = true;
         if constexpr (LIM) {
             const T cl = clampb(v, umin, umax);
-            clamp_mag = fmax(clamp_mag, (double)fabs(cl - v));
+            clamp_mag = fmax(clamp_mag, (T)fabs(cl - v));
             v = cl;
         }
         v = rk_combine(p.stage, v, unv[c][0]);
         if constexpr (LIM) {
             const T cl = clampb(v, umin, umax);
-            clamp_mag = fmax(clamp_mag, (double)fabs(cl - v));
+            clamp_mag = fmax(clamp_mag, (T)fabs(cl - v));
             v = cl;
         }
         vlo = fmin(vlo, v);
         vhi = fmax(vhi, v);
-        st_plane(outz[0], gi, v);
+        st(0, gi, v);
     }
     if (!residual) {
         if (bad) atomicOr(&p.st[wk.x].flags, 1u);
-        if constexpr (LIM) atomic_max_wave(&p.st[wk.x].clampmax, clamp_mag);
+        if constexpr (LIM) atomic_max_wave_t<T>(&p.st[wk.x].clampmax, clamp_mag);
         if (p.minmax) minmax_wave(&p.st[wk.x], vlo, vhi);
     }
 }

@@ -215,20 +215,59 @@ __device__ __forceinline__ T rk_combine(int stage, T fe, T un)
     return fe;
 }
 
+// Wave-wide maximum of an unsigned value in six DPP steps (shifts within rows
+// of 16 lanes, then two row broadcasts), read from the last lane.  Every lane
+// of the wave must be active; lanes shifted in from outside a row read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned dpp_umax_step(unsigned v)
+{
+    return max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, true));
+}
+__device__ __forceinline__ unsigned wave_umax(unsigned v)
+{
+    v = dpp_umax_step<0x111, 0xf>(v);   // row_shr:1
+    v = dpp_umax_step<0x112, 0xf>(v);   // row_shr:2
+    v = dpp_umax_step<0x114, 0xf>(v);   // row_shr:4
+    v = dpp_umax_step<0x118, 0xf>(v);   // row_shr:8
+    v = dpp_umax_step<0x142, 0xa>(v);   // row_bcast:15 into rows 1, 3
+    v = dpp_umax_step<0x143, 0xc>(v);   // row_bcast:31 into rows 2, 3
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// order-preserving map of floats to unsigned integers (non-NaN values)
+__device__ __forceinline__ unsigned ordered_key32(float v)
+{
+    const unsigned b = __float_as_uint(v);
+    return (b >> 31) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float ordered_value32(unsigned k)
+{
+    return __uint_as_float((k >> 31) ? (k & 0x7fffffffu) : ~k);
+}
+
 // Wave-wide min and max of the averages a thread wrote, then one atomic pair
 // per wave into the instance's ordered keys (the CFL wave speed of the next
 // step is evaluated from them when every flux has a convex |f'|).
 template <class T>
 __device__ __forceinline__ void minmax_wave(InstState *st, T lo, T hi)
 {
+    if constexpr (sizeof(T) == 4) {
+        const float l = ordered_value32(~wave_umax(~ordered_key32(lo)));
+        const float h = ordered_value32(wave_umax(ordered_key32(hi)));
+        if ((threadIdx.x & 63) == 0) {
+            atomicMin(&st->vmin_key, ordered_key((double)l));
+            atomicMax(&st->vmax_key, ordered_key((double)h));
+        }
+    } else {
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        lo = fmin(lo, __shfl_xor(lo, o));
-        hi = fmax(hi, __shfl_xor(hi, o));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        atomicMin(&st->vmin_key, ordered_key((double)lo));
-        atomicMax(&st->vmax_key, ordered_key((double)hi));
+        for (int o = 32; o >= 1; o >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, o));
+            hi = fmax(hi, __shfl_xor(hi, o));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            atomicMin(&st->vmin_key, ordered_key((double)lo));
+            atomicMax(&st->vmax_key, ordered_key((double)hi));
+        }
     }
 }
 
@@ -238,6 +277,20 @@ __device__ __forceinline__ void atomic_max_wave(unsigned long long *dst, double 
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     if ((threadIdx.x & 63) == 0 && v > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(v));
+}
+
+// Same for a non-negative value of the kernel's precision (FP32: the bit
+// patterns of non-negative floats order like the values).
+template <class T>
+__device__ __forceinline__ void atomic_max_wave_t(unsigned long long *dst, T v)
+{
+    if constexpr (sizeof(T) == 4) {
+        const unsigned m = wave_umax(__float_as_uint(v));
+        if ((threadIdx.x & 63) == 0 && m != 0u)
+            atomicMax(dst, (unsigned long long)__double_as_longlong((double)__uint_as_float(m)));
+    } else {
+        atomic_max_wave(dst, (double)v);
+    }
 }
 
 template <int D, class T, bool LIM, bool SI, int TX, int TY, int TZ, int NT>
@@ -260,12 +313,10 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
     const int nb = (int)gridDim.x, b = (int)blockIdx.x;
     const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
     const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3);
-    const int2 wk = p.work[logical];
+    const int4 wk = p.work[logical];
     const InstDev &I = p.inst[wk.x];
     const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2];
-    const int tx = wk.y % I.tiles[0];
-    const int ty = (wk.y / I.tiles[0]) % I.tiles[1];
-    const int tz = wk.y / (I.tiles[0] * I.tiles[1]);
+    const int tx = wk.y, ty = wk.z, tz = wk.w;
     const int ox = tx * G::T0, oy = ty * G::T1, oz = tz * G::T2;
     const long long kst = I.kstride;
     const T *__restrict__ in = p.in + I.off;
