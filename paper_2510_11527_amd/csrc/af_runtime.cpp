@@ -465,11 +465,14 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
         set_f32_params(I);
     }
     c->total = off;
-    c->caps = af4::kCapQF | af4::kCapPP | af4::kCapI32;
+    c->caps = af4::kCapQF | af4::kCapPP | af4::kCapI32 | af4::kCapBQ;
     for (int i = 0; i < n_inst; i++) {
         const InstDev &I = c->ih[i];
-        for (int l = 0; l < c->dim; l++)
+        for (int l = 0; l < c->dim; l++) {
             if (probs[i].flux[l] != AF_F_LINEAR && probs[i].flux[l] != AF_F_QUAD) c->caps &= ~af4::kCapQF;
+            if (probs[i].flux[l] != AF_F_QUAD && !(probs[i].flux[l] == AF_F_LINEAR && probs[i].flux_par[l][0] == 0.0))
+                c->caps &= ~af4::kCapBQ;
+        }
         const bool pure_poly = !I.ppow && !I.pabs && I.pu0 == 0.0 && std::isinf(I.plo) && I.plo < 0 &&
                                std::isinf(I.phi) && I.phi > 0;
         if (!pure_poly) c->caps &= ~af4::kCapPP;

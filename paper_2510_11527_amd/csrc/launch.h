@@ -18,6 +18,7 @@ enum : unsigned {
     kCapQF = 1,   // every flux of every instance is c1 u + c2 u^2 (linear or Burgers)
     kCapPP = 2,   // every potential is c1 u + c2 u^2 + c3 u^3 without clamps or signs
     kCapI32 = 4,  // the DoF block of every instance holds fewer than 2^32 bytes
+    kCapBQ = 8,   // every flux is c2 u^2 (no linear part)
 };
 
 // One stage launch over nblocks (instance, tile) work items.

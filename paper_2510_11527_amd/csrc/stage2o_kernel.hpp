@@ -19,7 +19,12 @@
 //   * f is recomputed from u (two instructions) instead of stored, which keeps
 //     the LDS footprint at three workgroups per CU;
 //   * the polynomial potentials without clamps (linear, u^2, u^3) take a
-//     three-instruction path (template flag PP);
+//     three-instruction path (flag kOwnPP);
+//   * for pure quadratic fluxes f_l = c2 u^2 (flag kOwnBQ) the point-value
+//     stencil works on u^2 and max|u|: |f_l'| = 2|c2| |u|, and the constant
+//     c2 moves into the per-direction scale;
+//   * the scales 1/(6 dx), 1/dx^2 and dt are folded into one multiply-add
+//     per term of the point-value update;
 //   * global memory is addressed with 32-bit byte offsets from per-DoF-kind
 //     base pointers (a plane holds fewer than 2^32 bytes; the host checks).
 #pragma once
@@ -48,9 +53,13 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
     }
 }
 
-template <class T, bool LIM, bool PP, int TX, int TY, int NT>
+// kernel variant flags
+enum : int { kOwnPP = 1, kOwnBQ = 2 };
+
+template <class T, bool LIM, int FL, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
 {
+    constexpr bool PP = (FL & kOwnPP) != 0, BQ = (FL & kOwnBQ) != 0;
     static_assert(TX * TY == 2 * NT && TY % 2 == 0, "two cells per thread");
     static_assert(NT % TX == 0 && NT % 64 == 0, "threads cover whole columns and waves");
     constexpr int RX = TX + 4, RY = TY + 4;     // tile + halo 2
@@ -269,28 +278,53 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
 
     // ---- C: the six point values of the two own cells
     {
-        // one direction of du/dt at a point from its 5-point window
-        auto pv_dir = [&](int l, V2<T> w0, V2<T> w1, V2<T> w2, V2<T> w3, V2<T> w4) -> T {
-            const T al = fmax(fmax(fmax(gq(l, w0.x), gq(l, w1.x)), fmax(gq(l, w2.x), gq(l, w3.x))), gq(l, w4.x));
-            const T dcf = (fq(l, w0.x) - fq(l, w4.x)) + T(8) * (fq(l, w3.x) - fq(l, w1.x));
+        // Per direction l, the point-value update adds kc_l t + kd_l d with
+        //   t = (f_{-2} - 8 f_{-1} + 8 f_1 - f_2) + alpha d4,  d4 = 4th difference of u,
+        //   d = 16 (a_{-1} + a_1) - (a_{-2} + a_2) - 30 a_0,
+        // kc_l = -sc / (6 dx_l) and kd_l = sc / (3 dx_l^2), sc = dt (sc = 1 for
+        // the residual); for pure quadratic fluxes t is c2 times
+        //   (u_{-2}^2 - 8 u_{-1}^2 + 8 u_1^2 - u_2^2) + 2 sgn(c2) max|u| d4.
+        const T sc = residual ? T(1) : dt;
+        T kc[2], kd[2], sg2[2];
+#pragma unroll
+        for (int l = 0; l < 2; l++) {
+            kc[l] = -(BQ ? c2[l] : T(1)) * i6dx[l] * sc;
+            kd[l] = idx2[l] * T(1.0 / 3.0) * sc;
+            sg2[l] = c2[l] > T(0) ? T(2) : (c2[l] < T(0) ? T(-2) : T(0));
+        }
+        auto pv_dir = [&](int l, V2<T> w0, V2<T> w1, V2<T> w2, V2<T> w3, V2<T> w4, T acc) -> T {
             const T d4 = (w0.x + w4.x) - T(4) * (w1.x + w3.x) + T(6) * w2.x;
-            const T conv = -(dcf + al * d4) * i6dx[l];
-            const T d2 = ((w1.y + w3.y) * T(16.0 / 3.0) - (w0.y + w4.y) * T(1.0 / 3.0) - T(10) * w2.y) * idx2[l];
-            return conv + d2;
+            T t;
+            if constexpr (BQ) {
+                const T m = vmax(vmax(vmax(T(fabs(w0.x)), T(fabs(w1.x))), T(fabs(w2.x))),
+                                 vmax(T(fabs(w3.x)), T(fabs(w4.x))));
+                const T e = (w0.x * w0.x - w4.x * w4.x) + T(8) * (w3.x * w3.x - w1.x * w1.x);
+                t = e + (sg2[l] * m) * d4;
+            } else {
+                const T al = fmax(fmax(fmax(gq(l, w0.x), gq(l, w1.x)), fmax(gq(l, w2.x), gq(l, w3.x))), gq(l, w4.x));
+                const T dcf = (fq(l, w0.x) - fq(l, w4.x)) + T(8) * (fq(l, w3.x) - fq(l, w1.x));
+                t = dcf + al * d4;
+            }
+            const T d = (T(16) * (w1.y + w3.y) - (w0.y + w4.y)) - T(30) * w2.y;
+            return (acc + kc[l] * t) + kd[l] * d;
         };
-        T R[2][3];  // per own cell: x-face, y-face, corner point value
+        T R[2][3];  // per own cell: x-face, y-face, corner point value (or du/dt)
 #pragma unroll
         for (int c = 0; c < 2; c++) {
             const int yy = y + c;
+            const bool z0 = residual;
             // x-face point (x+1/2, yy)
-            R[c][0] = pv_dir(0, S(SXF, x - 1, yy), S(SC, x, yy), S(SXF, x, yy), S(SC, x + 1, yy), S(SXF, x + 1, yy)) +
-                      pv_dir(1, S(SXF, x, yy - 1), S(SK, x, yy - 1), S(SXF, x, yy), S(SK, x, yy), S(SXF, x, yy + 1));
+            T r = z0 ? T(0) : Su(SXF, x, yy);
+            r = pv_dir(0, S(SXF, x - 1, yy), S(SC, x, yy), S(SXF, x, yy), S(SC, x + 1, yy), S(SXF, x + 1, yy), r);
+            R[c][0] = pv_dir(1, S(SXF, x, yy - 1), S(SK, x, yy - 1), S(SXF, x, yy), S(SK, x, yy), S(SXF, x, yy + 1), r);
             // y-face point (x, yy+1/2)
-            R[c][1] = pv_dir(0, S(SYF, x - 1, yy), S(SK, x - 1, yy), S(SYF, x, yy), S(SK, x, yy), S(SYF, x + 1, yy)) +
-                      pv_dir(1, S(SYF, x, yy - 1), S(SC, x, yy), S(SYF, x, yy), S(SC, x, yy + 1), S(SYF, x, yy + 1));
+            r = z0 ? T(0) : Su(SYF, x, yy);
+            r = pv_dir(0, S(SYF, x - 1, yy), S(SK, x - 1, yy), S(SYF, x, yy), S(SK, x, yy), S(SYF, x + 1, yy), r);
+            R[c][1] = pv_dir(1, S(SYF, x, yy - 1), S(SC, x, yy), S(SYF, x, yy), S(SC, x, yy + 1), S(SYF, x, yy + 1), r);
             // corner point (x+1/2, yy+1/2)
-            R[c][2] = pv_dir(0, S(SK, x - 1, yy), S(SYF, x, yy), S(SK, x, yy), S(SYF, x + 1, yy), S(SK, x + 1, yy)) +
-                      pv_dir(1, S(SK, x, yy - 1), S(SXF, x, yy), S(SK, x, yy), S(SXF, x, yy + 1), S(SK, x, yy + 1));
+            r = z0 ? T(0) : Su(SK, x, yy);
+            r = pv_dir(0, S(SK, x - 1, yy), S(SYF, x, yy), S(SK, x, yy), S(SYF, x + 1, yy), S(SK, x + 1, yy), r);
+            R[c][2] = pv_dir(1, S(SK, x, yy - 1), S(SXF, x, yy), S(SK, x, yy), S(SXF, x, yy + 1), S(SK, x, yy + 1), r);
         }
 #pragma unroll
         for (int c = 0; c < 2; c++) {
@@ -303,8 +337,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
                     st(z, gi, R[c][z - 1]);
                     continue;
                 }
-                const int s = z == 1 ? SXF : (z == 2 ? SYF : SK);
-                T v = Su(s, x, y + c) + dt * R[c][z - 1];
+                T v = R[c][z - 1];
                 if (!isfinite(v)) bad = true;
                 if constexpr (LIM) v = clampb(v, umin, umax);
                 v = rk_combine(p.stage, v, unv[c][z]);

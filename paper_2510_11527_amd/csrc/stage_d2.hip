@@ -32,16 +32,23 @@ hipError_t launch_tuned(int nblocks, const void *params, hipStream_t s)
     }
 }
 
-template <class T, bool LIM, bool PP, int TX, int TY, int NT>
+template <class T, bool LIM, int FL, int TX, int TY, int NT>
 hipError_t launch_own(int nblocks, const void *params, hipStream_t s)
 {
     if constexpr (stage2o_lds_bytes<T, LIM, TX, TY>() > kLdsCap) {
         return hipErrorInvalidValue;
     } else {
-        hipLaunchKernelGGL((stage2o_kernel<T, LIM, PP, TX, TY, NT>), dim3(nblocks), dim3(NT), 0, s,
+        hipLaunchKernelGGL((stage2o_kernel<T, LIM, FL, TX, TY, NT>), dim3(nblocks), dim3(NT), 0, s,
                            *(const StageParams<T> *)params);
         return hipGetLastError();
     }
+}
+
+template <class T, int FL, int TX, int TY, int NT>
+hipError_t launch_own_lim(bool lim, int nblocks, const void *params, hipStream_t s)
+{
+    return lim ? launch_own<T, true, FL, TX, TY, NT>(nblocks, params, s)
+               : launch_own<T, false, FL, TX, TY, NT>(nblocks, params, s);
 }
 
 template <class T, int TX, int TY, int NT, int KIND>
@@ -50,11 +57,13 @@ hipError_t launch_kind(bool lim, bool si, unsigned caps, int nblocks, const void
     const bool qf = (caps & kCapQF) != 0;
     if constexpr (KIND == 4) {
         if (si || !qf || !(caps & kCapI32)) return hipErrorInvalidValue;
-        const bool pp = (caps & kCapPP) != 0;
-        if (lim) return pp ? launch_own<T, true, true, TX, TY, NT>(nblocks, params, s)
-                           : launch_own<T, true, false, TX, TY, NT>(nblocks, params, s);
-        return pp ? launch_own<T, false, true, TX, TY, NT>(nblocks, params, s)
-                  : launch_own<T, false, false, TX, TY, NT>(nblocks, params, s);
+        const int fl = ((caps & kCapPP) ? kOwnPP : 0) | ((caps & kCapBQ) ? kOwnBQ : 0);
+        switch (fl) {
+        case 0: return launch_own_lim<T, 0, TX, TY, NT>(lim, nblocks, params, s);
+        case kOwnPP: return launch_own_lim<T, kOwnPP, TX, TY, NT>(lim, nblocks, params, s);
+        case kOwnBQ: return launch_own_lim<T, kOwnBQ, TX, TY, NT>(lim, nblocks, params, s);
+        default: return launch_own_lim<T, kOwnPP | kOwnBQ, TX, TY, NT>(lim, nblocks, params, s);
+        }
     } else if constexpr (KIND == 0) {
         if (lim) return si ? launch_generic<T, true, true, TX, TY, NT>(nblocks, params, s)
                            : launch_generic<T, true, false, TX, TY, NT>(nblocks, params, s);
