@@ -56,6 +56,17 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
 // kernel variant flags
 enum : int { kOwnPP = 1, kOwnBQ = 2 };
 
+// Layout of the face and potential arrays: x-faces (TX + 3 per tile row) and
+// x-potentials (TX + 2) row by row; y-faces (TY + 3 rows) and y-potentials
+// (TY + 2 rows) row by row with TX entries.
+template <int TX, int TY>
+struct Own2Geo {
+    static constexpr int FXS = TX + 3, CXS = TX + 2;
+    static constexpr int NXF = FXS * TY, NYF = TX * (TY + 3), NF = NXF + NYF;
+    static constexpr int NXC = CXS * TY, NYC = TX * (TY + 2), NC = NXC + NYC;
+    __device__ static __forceinline__ int yslot(int r) { return r; }
+};
+
 template <class T, bool LIM, int FL, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
 {
@@ -64,18 +75,16 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     static_assert(NT % TX == 0 && NT % 64 == 0, "threads cover whole columns and waves");
     constexpr int RX = TX + 4, RY = TY + 4;     // tile + halo 2
     constexpr int SX = RX + 1, SG = SX * RY;    // sub-grid row stride (padded) and size
-    constexpr int FXE = TX + 3, FYE = TY + 3;   // faces along the normal
-    constexpr int NXF = FXE * TY, NYF = TX * FYE;
-    constexpr int CXE = TX + 2, CYE = TY + 2;   // potentials along the direction
-    constexpr int NXC = CXE * TY, NYC = TX * CYE;
+    using FG = Own2Geo<TX, TY>;
+    constexpr int NXF = FG::NXF, NXC = FG::NXC;
     constexpr int SC = 0, SXF = 1, SYF = 2, SK = 3;  // sub-grids
 
     __shared__ V2<T> hs[4 * SG];                // {u, a} of the four sub-grids
     __shared__ V2<T> cg[RX * RY];               // {ubar, a(ubar)} of the cells
-    __shared__ T fl[NXF + NYF];                 // flux used in the update
-    __shared__ T ulp[LIM ? NXF + NYF : 1];      // u^{L,+} of the left cell of a face
-    __shared__ T ulm[LIM ? NXF + NYF : 1];      // u^{L,-} of the right cell
-    __shared__ T pc[NXC + NYC];                 // potential used in the update
+    __shared__ T fl[FG::NF];                    // flux used in the update
+    __shared__ T ulp[LIM ? FG::NF : 1];         // u^{L,+} of the left cell of a face
+    __shared__ T ulm[LIM ? FG::NF : 1];         // u^{L,-} of the right cell
+    __shared__ T pc[FG::NC];                    // potential used in the update
 
     const int nb = (int)gridDim.x, b = (int)blockIdx.x;
     const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
@@ -87,7 +96,8 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     const int n0 = Ic->n[0], n1 = Ic->n[1];
     const int tx0 = wk.y, ty0 = wk.z;
     const int ox = tx0 * TX, oy = ty0 * TY;
-    const bool residual = p.stage == 4;
+    // the right-hand side (stage 4) is evaluated by the unlimited instantiation
+    const bool residual = !LIM && p.stage == 4;
     const double dtd = Sc->dt;
     const int tid = (int)threadIdx.x;
     // the instance's DoF blocks of the three state buffers as buffer
@@ -167,7 +177,14 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         mu[l] = prm(Sc->mu[l], Sc->f_mu[l]);
         nu[l] = prm(Sc->nu[l], Sc->f_nu[l]);
     }
-    const T K = T(4);
+    // K = 2 d = 4: the LLF states use K mu, theta^c and theta^d 3 K mu and 3 K nu
+    T kmu[2], k3mu[2], k3nu[2];
+#pragma unroll
+    for (int l = 0; l < 2; l++) {
+        kmu[l] = T(4) * mu[l];
+        k3mu[l] = T(12) * mu[l];
+        k3nu[l] = T(12) * nu[l];
+    }
 
     auto pot = [&](T u) -> T {
         if constexpr (PP) return u * (pc1 + u * (pc2 + u * pc3));
@@ -182,10 +199,10 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     auto cgi = [&](int xx, int yy) -> int { return xx + RX * yy; };
     // face and potential slots: x-face between cells (xx, yy) and (xx+1, yy);
     // y-face between (xx, yy) and (xx, yy+1); potentials of cell (xx, yy)
-    auto fxi = [&](int xx, int yy) -> int { return xx + FXE * (yy - 2); };
-    auto fyi = [&](int xx, int yy) -> int { return NXF + (xx - 2) + TX * yy; };
-    auto pxi = [&](int xx, int yy) -> int { return (xx - 1) + CXE * (yy - 2); };
-    auto pyi = [&](int xx, int yy) -> int { return NXC + (xx - 2) + TX * (yy - 1); };
+    auto fxi = [&](int xx, int yy) -> int { return xx + FG::FXS * (yy - 2); };
+    auto fyi = [&](int xx, int yy) -> int { return NXF + (xx - 2) + TX * FG::yslot(yy); };
+    auto pxi = [&](int xx, int yy) -> int { return (xx - 1) + FG::CXS * (yy - 2); };
+    auto pyi = [&](int xx, int yy) -> int { return NXC + (xx - 2) + TX * FG::yslot(yy - 1); };
 
     // ---- A: cells of the tile and its halo -> LDS with their potentials.
     // Loads are issued in the order they are consumed (own cells, halo cells,
@@ -359,7 +376,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         if constexpr (LIM) {
             const T al = fmax(gq(l, A.x), gq(l, B.x));
             fL = T(0.5) * (fa + fb) - T(0.5) * al * (B.x - A.x);
-            const T Km = K * mu[l];
+            const T Km = kmu[l];
             const T dA = (B.y - A.y) * idx1[l];
             up = A.x + Km * (dA - fL + fa);
             um = B.x + Km * (fL - fb - dA);
@@ -377,7 +394,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         if constexpr (LIM) {
             if (!residual) {
                 const T df = fH - fL;
-                const T s3 = T(3) * K * mu[l] * df;
+                const T s3 = k3mu[l] * df;
                 // up moves by -s3, um by +s3
                 const T gap = gap2<T>(s3, um, up, umin, umax);
                 F = fL + theta_from_gap<T>(gap, (T)fabs(s3)) * df;
@@ -427,7 +444,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
                 const int f1 = l == 0 ? fxi(xx, yy) : fyi(xx, yy);
                 const T pL = ulp[f0], mC = ulm[f0], pC = ulp[f1], mR = ulm[f1];
                 const T da = aH - aL;
-                const T s = T(3) * K * nu[l] * da;
+                const T s = k3nu[l] * da;
                 // pL, mR move by +s; pC, mC by -s
                 const T gap = gap4<T>(s, pL, mR, pC, mC, umin, umax);
                 Pv = aL + theta_from_gap<T>(gap, (T)fabs(s)) * da;
@@ -498,8 +515,8 @@ template <class T, bool LIM, int TX, int TY>
 constexpr long stage2o_lds_bytes()
 {
     constexpr long RX = TX + 4, RY = TY + 4;
-    constexpr long NF = (TX + 3) * TY + TX * (TY + 3), NC = (TX + 2) * TY + TX * (TY + 2);
-    return (long)sizeof(T) * (8 * (RX + 1) * RY + 2 * RX * RY + NF * (LIM ? 3 : 1) + NC);
+    using FG = Own2Geo<TX, TY>;
+    return (long)sizeof(T) * (8 * (RX + 1) * RY + 2 * RX * RY + (long)FG::NF * (LIM ? 3 : 1) + FG::NC);
 }
 
 }  // namespace af4
