@@ -33,6 +33,7 @@ struct InstDev {
     // else 1; ppow != 0: p0 * u^p1 by pow (powers other than 1..3)
     double pu0, plo, phi, pc1, pc2, pc3;
     int pabs, ppow;
+    int wstart, wcount;  // the instance's range in the work list of the stage kernels
     double idx1[3];      // 1 / dx_l
     double idx2[3];      // 1 / dx_l^2
     double i6dx[3];      // 1 / (6 dx_l)
@@ -56,8 +57,6 @@ struct InstState {
     double t;            // time at the end of the current step
     unsigned long long wmax;      // bits of the FP64 max wave speed (non-negative)
     unsigned long long clampmax;  // bits of the largest average clamp (non-negative)
-    unsigned long long vmin_key;  // ordered keys of the min / max average written by
-    unsigned long long vmax_key;  // the last stage of a step (see ordered_key)
     unsigned int flags;  // bit 0: non-finite / divergent value produced
     unsigned int pad;
     long long steps;     // steps with dt > 0
@@ -78,8 +77,14 @@ struct StageParams {
     T *out;              // stage output (or right-hand side)
     InstState *st;
     int stage;           // 0: forward Euler, 1..3: SSP-RK3 stage, 4: residual
-    int minmax;          // 1: reduce min / max of the written averages into vmin_key / vmax_key
+    int pad;
+    // not null: every wave w of the block of work item k stores the ordered
+    // keys (see ordered_key) of the min and max average it wrote to
+    // mm[2 (k W + w)] and mm[2 (k W + w) + 1], W = waves per block
+    unsigned long long *mm;
 };
+
+constexpr int kMaxWavesPerBlock = 4;
 
 // Read-only per-launch parameters are read through the constant address
 // space so that uniform reads become scalar loads into SGPRs (the compiler
@@ -107,7 +112,6 @@ __host__ __device__ inline double ordered_value(unsigned long long k)
     __builtin_memcpy(&v, &b, sizeof v);
     return v;
 }
-constexpr unsigned long long kKeyMinEmpty = ~0ull;  // neutral element of the min key
-constexpr unsigned long long kKeyMaxEmpty = 0ull;   // neutral element of the max key
+
 
 }  // namespace af4

@@ -34,6 +34,8 @@ struct af_ctx {
     int nwork = 0;
     std::vector<int> work_start, work_count;
     int2 *d_chunks = nullptr;
+    unsigned long long *d_mm = nullptr;  // per-wave min / max slots of the last stage
+    int waves_per_block = 1;
     int nchunks = 0;
     void *buf[3] = {nullptr, nullptr, nullptr};
     long long total = 0;     // elements per state buffer
@@ -278,6 +280,8 @@ af_status build_work(af_ctx *c)
         }
         c->work_start[i] = (int)work.size();
         c->work_count[i] = (int)nt;
+        I.wstart = c->work_start[i];
+        I.wcount = c->work_count[i];
         for (int tz = 0; tz < I.tiles[2]; tz++)
             for (int ty = 0; ty < I.tiles[1]; ty++)
                 for (int tx = 0; tx < I.tiles[0]; tx++) work.push_back(make_int4(i, tx, ty, tz));
@@ -286,6 +290,11 @@ af_status build_work(af_ctx *c)
     c->d_work = nullptr;
     c->nwork = (int)work.size();
     HIPOK(c, hipMalloc(&c->d_work, sizeof(int4) * work.size()));
+    if (c->d_mm) (void)hipFree(c->d_mm);
+    c->d_mm = nullptr;
+    c->waves_per_block = (vi.nt + 63) / 64;
+    HIPOK(c, hipMalloc(&c->d_mm, sizeof(unsigned long long) * 2 * af4::kMaxWavesPerBlock * work.size()));
+    c->keys_fresh = false;
     HIPOK(c, hipMemcpy(c->d_work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice));
     HIPOK(c, hipMemcpy(c->d_inst, c->ih.data(), sizeof(InstDev) * c->n_inst, hipMemcpyHostToDevice));
     return AF_OK;
@@ -303,7 +312,8 @@ StageParams<T> stage_params(af_ctx *c, int in, int out, int stage)
     p.out = (T *)c->buf[out];
     p.st = c->d_st;
     p.stage = stage;
-    p.minmax = 0;
+    p.pad = 0;
+    p.mm = nullptr;
     return p;
 }
 
@@ -314,13 +324,13 @@ hipError_t launch_stage(af_ctx *c, int in, int out, int stage, bool lim, bool si
         StageParams<float> p = stage_params<float>(c, in, out, stage);
         p.work += wstart;
         p.nwork = wcount;
-        p.minmax = minmax ? 1 : 0;
+        p.mm = minmax ? c->d_mm + (size_t)2 * c->waves_per_block * wstart : nullptr;
         return af4::stage_launch(c->dim, 32, lim, si, c->caps, c->variant, wcount, &p, c->stream);
     }
     StageParams<double> p = stage_params<double>(c, in, out, stage);
     p.work += wstart;
     p.nwork = wcount;
-    p.minmax = minmax ? 1 : 0;
+    p.mm = minmax ? c->d_mm + (size_t)2 * c->waves_per_block * wstart : nullptr;
     return af4::stage_launch(c->dim, 64, lim, si, c->caps, c->variant, wcount, &p, c->stream);
 }
 
@@ -335,7 +345,8 @@ hipError_t enqueue_step(af_ctx *c, bool ws, std::vector<hipEvent_t> *events, siz
         e = af4::wavespeed_launch(c->dim, c->prec, c->d_inst, c->d_chunks, c->nchunks, c->buf[0], c->d_st, c->stream);
         if (e != hipSuccess) return e;
     }
-    e = af4::finalize_launch(c->n_inst, c->d_inst, c->d_ctl, c->d_dtp, c->d_st, c->dim, !ws, c->stream);
+    e = af4::finalize_launch(c->n_inst, c->d_inst, c->d_ctl, c->d_dtp, c->d_st, c->dim, ws ? nullptr : c->d_mm,
+                             c->waves_per_block, c->stream);
     if (e != hipSuccess) return e;
     const bool mm = cfl_from_keys(c);
     auto stage = [&](int in, int out, int st, bool last) -> hipError_t {
@@ -555,7 +566,7 @@ af_status af_destroy(af_ctx *c)
     drop_graph(c);
     for (int b = 0; b < 3; b++)
         if (c->buf[b]) (void)hipFree(c->buf[b]);
-    void *ptrs[] = {c->d_inst, c->d_st, c->d_ctl, c->d_dtp, c->d_work, c->d_chunks, c->d_npart, c->d_nout};
+    void *ptrs[] = {c->d_inst, c->d_st, c->d_ctl, c->d_dtp, c->d_work, c->d_chunks, c->d_npart, c->d_nout, c->d_mm};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -641,8 +652,6 @@ af_status af_set_state(af_ctx *c, int inst, const double *const *dofs, double t)
     InstState st;
     std::memset(&st, 0, sizeof st);
     st.t = t;
-    st.vmin_key = af4::kKeyMinEmpty;
-    st.vmax_key = af4::kKeyMaxEmpty;
     HIPOK(c, hipMemcpyAsync(c->d_st + inst, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
     HIPOK(c, hipStreamSynchronize(c->stream));
     c->have_state[inst] = 1;

@@ -48,52 +48,74 @@ __global__ void __launch_bounds__(256) wavespeed_kernel(const InstDev *inst, con
     if (bad) atomicOr(&st[ch.x].flags, 1u);
 }
 
-// from_keys: the wave speed comes from the min / max average written by the
-// previous step's last stage.  Valid when every |f_l'| is convex on the
-// bounds interval (linear and quadratic fluxes, no interior maxima): then the
-// maximum of alpha_int over all faces is max(|f_l'(min)|, |f_l'(max)|),
-// evaluated here in FP64 exactly as the wave-speed kernel evaluates it per
-// face, so the time step is the same to the bit.
-__global__ void finalize_kernel(int n_inst, const InstDev *inst, const StepCtl *ctl, const double *dtp, InstState *st,
-                                int dim, int from_keys)
+// One block per instance.  mm != nullptr: the wave speed comes from the min /
+// max average written by the previous step's last stage, reduced here from
+// the per-wave slots of the instance's work items.  Valid when every |f_l'|
+// is convex on the bounds interval (linear and quadratic fluxes, no interior
+// maxima): then the maximum of alpha_int over all faces is
+// max(|f_l'(min)|, |f_l'(max)|), evaluated in FP64 exactly as the wave-speed
+// kernel evaluates it per face, so the time step is the same to the bit.
+__global__ void __launch_bounds__(256) finalize_kernel(const InstDev *inst, const StepCtl *ctl, const double *dtp,
+                                                       InstState *st, int dim, const unsigned long long *mm,
+                                                       int waves_per_block)
 {
-    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n_inst; i += blockDim.x * gridDim.x) {
-        const double te = ctl->t_end;
-        const InstDev &I = inst[i];
-        double w = __longlong_as_double((long long)st[i].wmax);
-        if (from_keys) {
-            const double lo = ordered_value(st[i].vmin_key), hi = ordered_value(st[i].vmax_key);
-            const double big = 1e6 * fmax(fmax(fabs(I.umin), fabs(I.umax)), 1.0);
-            if (!(fabs(lo) <= big && fabs(hi) <= big)) st[i].flags |= 1u;  // divergent or non-finite
-            Phys<double> P;
-            P.load(I, dim);
-            w = 0.0;
-            for (int l = 0; l < dim; l++) w = fmax(w, P.alpha_int(l, lo, hi) * I.idx1[l] + I.kmax * I.idx2[l]);
+    const int i = blockIdx.x;
+    const InstDev &I = inst[i];
+    __shared__ unsigned long long klo[256], khi[256];
+    double w = __longlong_as_double((long long)st[i].wmax);
+    double lo = 0.0, hi = 0.0;
+    if (mm) {
+        unsigned long long a = ~0ull, b = 0ull;
+        const int n = I.wcount * waves_per_block;
+        const unsigned long long *m = mm + 2 * (long long)I.wstart * waves_per_block;
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            a = min(a, m[2 * k]);
+            b = max(b, m[2 * k + 1]);
         }
-        double dt;
-        if (ctl->prescribed) {
-            dt = dtp[i];
-        } else {
-            dt = w > 0.0 ? I.cfl / w : (te > 0.0 ? te - st[i].t : 0.0);
+        klo[threadIdx.x] = a;
+        khi[threadIdx.x] = b;
+        __syncthreads();
+        for (int o = 128; o >= 1; o >>= 1) {
+            if ((int)threadIdx.x < o) {
+                klo[threadIdx.x] = min(klo[threadIdx.x], klo[threadIdx.x + o]);
+                khi[threadIdx.x] = max(khi[threadIdx.x], khi[threadIdx.x + o]);
+            }
+            __syncthreads();
         }
-        st[i].wmax = 0ull;
-        st[i].vmin_key = kKeyMinEmpty;
-        st[i].vmax_key = kKeyMaxEmpty;
-        if (te > 0.0) {
-            const double rem = te - st[i].t;
-            if (rem <= 1e-12 * te) dt = 0.0;  // remainder is rounding, not a step
-            else if (dt > rem) dt = rem;
-        }
-        st[i].dt = dt;
-        st[i].t += dt;
-        if (dt > 0.0) st[i].steps++;
-        st[i].f_dt = (float)dt;
-        for (int l = 0; l < 3; l++) {
-            st[i].mu[l] = dt * inst[i].idx1[l];
-            st[i].nu[l] = dt * inst[i].idx2[l];
-            st[i].f_mu[l] = (float)st[i].mu[l];
-            st[i].f_nu[l] = (float)st[i].nu[l];
-        }
+        lo = ordered_value(klo[0]);
+        hi = ordered_value(khi[0]);
+    }
+    if (threadIdx.x != 0) return;
+    const double te = ctl->t_end;
+    if (mm) {
+        const double big = 1e6 * fmax(fmax(fabs(I.umin), fabs(I.umax)), 1.0);
+        if (!(fabs(lo) <= big && fabs(hi) <= big)) st[i].flags |= 1u;  // divergent or non-finite
+        Phys<double> P;
+        P.load(I, dim);
+        w = 0.0;
+        for (int l = 0; l < dim; l++) w = fmax(w, P.alpha_int(l, lo, hi) * I.idx1[l] + I.kmax * I.idx2[l]);
+    }
+    double dt;
+    if (ctl->prescribed) {
+        dt = dtp[i];
+    } else {
+        dt = w > 0.0 ? I.cfl / w : (te > 0.0 ? te - st[i].t : 0.0);
+    }
+    st[i].wmax = 0ull;
+    if (te > 0.0) {
+        const double rem = te - st[i].t;
+        if (rem <= 1e-12 * te) dt = 0.0;  // remainder is rounding, not a step
+        else if (dt > rem) dt = rem;
+    }
+    st[i].dt = dt;
+    st[i].t += dt;
+    if (dt > 0.0) st[i].steps++;
+    st[i].f_dt = (float)dt;
+    for (int l = 0; l < 3; l++) {
+        st[i].mu[l] = dt * I.idx1[l];
+        st[i].nu[l] = dt * I.idx2[l];
+        st[i].f_mu[l] = (float)st[i].mu[l];
+        st[i].f_nu[l] = (float)st[i].nu[l];
     }
 }
 
@@ -182,10 +204,9 @@ hipError_t wavespeed_launch(int dim, int prec, const InstDev *inst, const int2 *
 }
 
 hipError_t finalize_launch(int n_inst, const InstDev *inst, const StepCtl *ctl, const double *dtp, InstState *st,
-                           int dim, bool from_keys, hipStream_t s)
+                           int dim, const unsigned long long *mm, int waves_per_block, hipStream_t s)
 {
-    int nb = (n_inst + 255) / 256;
-    hipLaunchKernelGGL(finalize_kernel, dim3(nb), dim3(256), 0, s, n_inst, inst, ctl, dtp, st, dim, from_keys ? 1 : 0);
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_inst), dim3(256), 0, s, inst, ctl, dtp, st, dim, mm, waves_per_block);
     return hipGetLastError();
 }
 

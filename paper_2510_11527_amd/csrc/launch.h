@@ -44,10 +44,11 @@ hipError_t wavespeed_launch(int dim, int prec, const InstDev *inst, const int2 *
                             InstState *st, hipStream_t s);
 
 // dt and t of every instance from the wave speeds (or the prescribed steps);
-// from_keys: from the min / max averages reduced by the previous step's last
-// stage instead of the wave-speed kernel (fluxes with convex |f'| only).
+// mm != nullptr: from the min / max average slots written by the previous
+// step's last stage (waves_per_block slot pairs per work item) instead of the
+// wave-speed kernel (fluxes with convex |f'| only).
 hipError_t finalize_launch(int n_inst, const InstDev *inst, const StepCtl *ctl, const double *dtp, InstState *st,
-                           int dim, bool from_keys, hipStream_t s);
+                           int dim, const unsigned long long *mm, int waves_per_block, hipStream_t s);
 
 // dst = src over n values.
 hipError_t copy_launch(int prec, const void *src, void *dst, long long n, hipStream_t s);

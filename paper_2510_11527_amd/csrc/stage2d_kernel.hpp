@@ -142,13 +142,13 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
             if (own0) out[z * kst + g0] = in[z * kst + g0];
             if (own1) out[z * kst + g1] = in[z * kst + g1];
         }
-        if (p.minmax) {
+        if (p.mm) {
             if (own0) vlo = vhi = in[g0];
             if (own1) {
                 vlo = fmin(vlo, in[g1]);
                 vhi = fmax(vhi, in[g1]);
             }
-            minmax_wave(&p.st[wk.x], vlo, vhi);
+            minmax_slot(p.mm, logical, vlo, vhi);
         }
         return;
     }
@@ -462,7 +462,7 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
     if (!residual) {
         if (bad) atomicOr(&p.st[wk.x].flags, 1u);
         if constexpr (LIM) atomic_max_wave(&p.st[wk.x].clampmax, clamp_mag);
-        if (p.minmax) minmax_wave(&p.st[wk.x], vlo, vhi);
+        if (p.mm) minmax_slot(p.mm, logical, vlo, vhi);
     }
 }
 

@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
                 }
             }
         }
-        if (p.minmax) minmax_wave(&p.st[wk.x], vlo, vhi);
+        if (p.mm) minmax_slot(p.mm, logical, vlo, vhi);
         return;
     }
 
@@ -507,7 +507,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     if (!residual) {
         if (bad) atomicOr(&p.st[wk.x].flags, 1u);
         if constexpr (LIM) atomic_max_wave_t<T>(&p.st[wk.x].clampmax, clamp_mag);
-        if (p.minmax) minmax_wave(&p.st[wk.x], vlo, vhi);
+        if (p.mm) minmax_slot(p.mm, logical, vlo, vhi);
     }
 }
 

@@ -251,29 +251,30 @@ __device__ __forceinline__ float ordered_value32(unsigned k)
     return __uint_as_float((k >> 31) ? (k & 0x7fffffffu) : ~k);
 }
 
-// Wave-wide min and max of the averages a thread wrote, then one atomic pair
-// per wave into the instance's ordered keys (the CFL wave speed of the next
-// step is evaluated from them when every flux has a convex |f'|).
+// Wave-wide min and max of the averages the threads of a wave wrote, stored
+// as ordered keys by the wave's first lane into its slot pair of the block's
+// work item (no atomics: the finalize kernel reduces the slots of each
+// instance; the CFL wave speed of the next step is evaluated from them when
+// every flux has a convex |f'|).  Every lane of the wave must be active.
 template <class T>
-__device__ __forceinline__ void minmax_wave(InstState *st, T lo, T hi)
+__device__ __forceinline__ void minmax_slot(unsigned long long *mm, int item, T lo, T hi)
 {
     if constexpr (sizeof(T) == 4) {
         const float l = ordered_value32(~wave_umax(~ordered_key32(lo)));
         const float h = ordered_value32(wave_umax(ordered_key32(hi)));
-        if ((threadIdx.x & 63) == 0) {
-            atomicMin(&st->vmin_key, ordered_key((double)l));
-            atomicMax(&st->vmax_key, ordered_key((double)h));
-        }
+        lo = l;
+        hi = h;
     } else {
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
             lo = fmin(lo, __shfl_xor(lo, o));
             hi = fmax(hi, __shfl_xor(hi, o));
         }
-        if ((threadIdx.x & 63) == 0) {
-            atomicMin(&st->vmin_key, ordered_key((double)lo));
-            atomicMax(&st->vmax_key, ordered_key((double)hi));
-        }
+    }
+    if ((threadIdx.x & 63) == 0) {
+        unsigned long long *slot = mm + 2 * (item * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6));
+        slot[0] = ordered_key((double)lo);
+        slot[1] = ordered_key((double)hi);
     }
 }
 
@@ -342,7 +343,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
             vlo = fmin(vlo, in[gi]);
             vhi = fmax(vhi, in[gi]);
         });
-        if (p.minmax) minmax_wave(&p.st[wk.x], vlo, vhi);
+        if (p.mm) minmax_slot(p.mm, logical, vlo, vhi);
         return;
     }
 
@@ -676,7 +677,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
     if (!residual) {
         if (bad) atomicOr(&p.st[wk.x].flags, 1u);
         if constexpr (LIM) atomic_max_wave(&p.st[wk.x].clampmax, clamp_mag);
-        if (p.minmax) minmax_wave(&p.st[wk.x], vlo, vhi);
+        if (p.mm) minmax_slot(p.mm, logical, vlo, vhi);
     }
 }
 
