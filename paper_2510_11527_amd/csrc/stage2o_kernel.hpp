@@ -81,10 +81,14 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
 
     __shared__ V2<T> hs[4 * SG];                // {u, a} of the four sub-grids
     __shared__ V2<T> cg[RX * RY];               // {ubar, a(ubar)} of the cells
-    __shared__ T fl[FG::NF];                    // flux used in the update
-    __shared__ T ulp[LIM ? FG::NF : 1];         // u^{L,+} of the left cell of a face
-    __shared__ T ulm[LIM ? FG::NF : 1];         // u^{L,-} of the right cell
-    __shared__ T pc[FG::NC];                    // potential used in the update
+    // Face and potential arrays.  With the limiter, u^{L,+} (of the left cell
+    // of a face) and u^{L,-} (of the right cell) live there until the
+    // potentials have read them; the flux and the potential used in the
+    // update are kept in registers until then and take their place.
+    static_assert(FG::NC <= FG::NF, "potentials fit in a face array");
+    __shared__ T fbuf[LIM ? 2 * FG::NF : FG::NF + FG::NC];
+    T *const ulp = fbuf, *const ulm = fbuf + FG::NF;
+    T *const fl = fbuf, *const pc = fbuf + FG::NF;
 
     const int nb = (int)gridDim.x, b = (int)blockIdx.x;
     const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
@@ -367,7 +371,11 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     // ---- D1: faces.  The low-order (LLF) quantities on every face the
     // potentials' theta^d reads; the Simpson flux and theta^c on the faces
     // of the tile's cells (HI).
-    auto face = [&](int l, int xx, int yy, bool hi) {
+    struct Item {
+        T v;
+        int id;
+    };
+    auto face = [&](int l, int xx, int yy, bool hi) -> Item {
         const V2<T> A = cg[cgi(xx, yy)];
         const V2<T> B = l == 0 ? cg[cgi(xx + 1, yy)] : cg[cgi(xx, yy + 1)];
         const int id = l == 0 ? fxi(xx, yy) : fyi(xx, yy);
@@ -383,7 +391,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
             ulp[id] = up;
             ulm[id] = um;
         }
-        if (!hi) return;
+        if (!hi) return Item{T(0), -1};
         // Simpson average of f_l over the three points of the face
         T fH;
         if (l == 0)
@@ -400,31 +408,31 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
                 F = fL + theta_from_gap<T>(gap, (T)fabs(s3)) * df;
             }
         }
-        fl[id] = F;
+        if constexpr (!LIM) fl[id] = F;
+        return Item{F, id};
     };
-    face(0, x, y, true);
-    face(0, x, y + 1, true);
-    face(1, x, y, true);
-    face(1, x, y + 1, true);
-    {
-        // halo faces: x-faces at columns 0, 1 (HI), TX+2 over the tile rows;
-        // y-faces at rows 0, 1 (HI), TY+2 over the tile columns (from the
-        // next wave boundary on, so no wave mixes the two)
-        constexpr int NXH = 3 * TY, Y0 = (NXH + 63) / 64 * 64, NH = Y0 + 3 * TX;
-        for (int h = tid; h < NH; h += NT) {
-            if (h < NXH) {
-                const int k = h / TY;
-                face(0, k < 2 ? k : TX + 2, 2 + h - k * TY, k == 1);
-            } else if (h >= Y0) {
-                const int h2 = h - Y0, k = h2 / TX;
-                face(1, 2 + h2 - k * TX, k < 2 ? k : TY + 2, k == 1);
-            }
+    Item fo[4] = {face(0, x, y, true), face(0, x, y + 1, true), face(1, x, y, true), face(1, x, y + 1, true)};
+    // halo faces: x-faces at columns 0, 1 (HI), TX+2 over the tile rows;
+    // y-faces at rows 0, 1 (HI), TY+2 over the tile columns (from the next
+    // wave boundary on, so no wave mixes the two)
+    constexpr int NXHF = 3 * TY, Y0F = (NXHF + 63) / 64 * 64, NHF = Y0F + 3 * TX, NHFI = (NHF + NT - 1) / NT;
+    Item fh[NHFI];
+#pragma unroll
+    for (int k = 0; k < NHFI; k++) {
+        const int h = tid + k * NT;
+        fh[k] = Item{T(0), -1};
+        if (h < NXHF) {
+            const int q = h / TY;
+            fh[k] = face(0, q < 2 ? q : TX + 2, 2 + h - q * TY, q == 1);
+        } else if (h >= Y0F && h < NHF) {
+            const int h2 = h - Y0F, q = h2 / TX;
+            fh[k] = face(1, 2 + h2 - q * TX, q < 2 ? q : TY + 2, q == 1);
         }
     }
     __syncthreads();
 
     // ---- D2: cell-centred potentials a^H of Prop. 2.1 and their limited blend
-    auto potential = [&](int l, int xx, int yy) {
+    auto potential = [&](int l, int xx, int yy) -> Item {
         const T corners = Sa(SK, xx - 1, yy - 1) + Sa(SK, xx, yy - 1) + Sa(SK, xx - 1, yy) + Sa(SK, xx, yy);
         T aH;
         if (l == 0)
@@ -450,24 +458,41 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
                 Pv = aL + theta_from_gap<T>(gap, (T)fabs(s)) * da;
             }
         }
-        pc[l == 0 ? pxi(xx, yy) : pyi(xx, yy)] = Pv;
+        const int id = l == 0 ? pxi(xx, yy) : pyi(xx, yy);
+        if constexpr (!LIM) pc[id] = Pv;
+        return Item{Pv, id};
     };
-    potential(0, x, y);
-    potential(0, x, y + 1);
-    potential(1, x, y);
-    potential(1, x, y + 1);
-    {
-        // halo potentials: x at columns 1, TX+2; y at rows 1, TY+2
-        constexpr int NXH = 2 * TY, Y0 = (NXH + 63) / 64 * 64, NH = Y0 + 2 * TX;
-        for (int h = tid; h < NH; h += NT) {
-            if (h < NXH) {
-                const int k = h / TY;
-                potential(0, k ? TX + 2 : 1, 2 + h - k * TY);
-            } else if (h >= Y0) {
-                const int h2 = h - Y0, k = h2 / TX;
-                potential(1, 2 + h2 - k * TX, k ? TY + 2 : 1);
-            }
+    Item po[4] = {potential(0, x, y), potential(0, x, y + 1), potential(1, x, y), potential(1, x, y + 1)};
+    // halo potentials: x at columns 1, TX+2; y at rows 1, TY+2
+    constexpr int NXHP = 2 * TY, Y0P = (NXHP + 63) / 64 * 64, NHP = Y0P + 2 * TX, NHPI = (NHP + NT - 1) / NT;
+    Item ph[NHPI];
+#pragma unroll
+    for (int k = 0; k < NHPI; k++) {
+        const int h = tid + k * NT;
+        ph[k] = Item{T(0), -1};
+        if (h < NXHP) {
+            const int q = h / TY;
+            ph[k] = potential(0, q ? TX + 2 : 1, 2 + h - q * TY);
+        } else if (h >= Y0P && h < NHP) {
+            const int h2 = h - Y0P, q = h2 / TX;
+            ph[k] = potential(1, 2 + h2 - q * TX, q ? TY + 2 : 1);
         }
+    }
+    if constexpr (LIM) {
+        // every theta^d has read u^{L,+-}: the fluxes and potentials of the
+        // update take their place
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            fl[fo[k].id] = fo[k].v;
+            pc[po[k].id] = po[k].v;
+        }
+#pragma unroll
+        for (int k = 0; k < NHFI; k++)
+            if (fh[k].id >= 0) fl[fh[k].id] = fh[k].v;
+#pragma unroll
+        for (int k = 0; k < NHPI; k++)
+            if (ph[k].id >= 0) pc[ph[k].id] = ph[k].v;
     }
     __syncthreads();
 
@@ -516,7 +541,7 @@ constexpr long stage2o_lds_bytes()
 {
     constexpr long RX = TX + 4, RY = TY + 4;
     using FG = Own2Geo<TX, TY>;
-    return (long)sizeof(T) * (8 * (RX + 1) * RY + 2 * RX * RY + (long)FG::NF * (LIM ? 3 : 1) + FG::NC);
+    return (long)sizeof(T) * (8 * (RX + 1) * RY + 2 * RX * RY + (LIM ? 2L * FG::NF : (long)FG::NF + FG::NC));
 }
 
 }  // namespace af4
