@@ -103,6 +103,7 @@ def lib():
         L.orc_fe.argtypes = [PP, pp, ctypes.c_double, pp, DG]
         L.orc_fe_cells.argtypes = [PP, pp, ctypes.c_double, ctypes.POINTER(ctypes.c_long), ctypes.c_long, dp, DG]
         L.orc_ssprk3_step.argtypes = [PP, pp, ctypes.c_double, pp, pp, DG]
+        L.orc_ssprk54_step.argtypes = [PP, pp, ctypes.c_double, pp, pp, pp, pp, DG]
         L.orc_dt.argtypes = [PP, pp, ctypes.c_double]
         L.orc_dt.restype = ctypes.c_double
         L.orc_limiter_probe.argtypes = [PP, pp, ctypes.c_double, ctypes.c_int, ctypes.c_long, dp]
@@ -238,6 +239,28 @@ def ssprk3_step(P, U, dt, diag=None):
     return U
 
 
+def _merge_diag(diag, dg):
+    if diag is not None:
+        d = dg.as_dict()
+        diag["uL_out_of_bounds"] = diag.get("uL_out_of_bounds", 0) + d["uL_out_of_bounds"]
+        diag["n_theta"] = diag.get("n_theta", 0) + d["n_theta"]
+        diag["n_theta_lt1"] = diag.get("n_theta_lt1", 0) + d["n_theta_lt1"]
+        diag["max_avg_clamp"] = max(diag.get("max_avg_clamp", 0.0), d["max_avg_clamp"])
+        diag["max_pv_clamp"] = max(diag.get("max_pv_clamp", 0.0), d["max_pv_clamp"])
+
+
+def ssprk54_step(P, U, dt, diag=None):
+    """One SSP-RK(5,4) step (Spiteri-Ruuth, the paper's integrator); U is
+    updated in place."""
+    assert all(u.dtype == np.float64 and u.flags.c_contiguous for u in U)
+    W = [[np.empty(ncells(P)) for _ in range(ndofs(P))] for _ in range(4)]
+    dg = OrcDiag()
+    lib().orc_ssprk54_step(ctypes.byref(P), _ptrs([u.reshape(-1) for u in U]), float(dt), *[_ptrs(w) for w in W],
+                           ctypes.byref(dg))
+    _merge_diag(diag, dg)
+    return U
+
+
 def run(P, U, nsteps=None, cfl=None, t0=0.0, t_end=None, dts=None, integrator="ssprk3", diag=None):
     """Advance U.  Either a list of prescribed time steps ``dts`` or a CFL
     number (dt from the MPP CFL condition, the last step clipped to t_end).
@@ -261,6 +284,8 @@ def run(P, U, nsteps=None, cfl=None, t0=0.0, t_end=None, dts=None, integrator="s
                 dt = min(dt, t_end - t)
         if integrator == "ssprk3":
             ssprk3_step(P, U, dt, diag)
+        elif integrator == "ssprk54":
+            ssprk54_step(P, U, dt, diag)
         else:
             V, d = fe(P, U, dt)
             U = V

@@ -848,6 +848,55 @@ void orc_ssprk3_step(const orc_problem *P, double *const *U, double dt, double *
     if (P->limiter) clamp_all(P, U, dg);
 }
 
+/* SSP-RK(5,4) of Spiteri and Ruuth (2002), the paper's time integrator (Sec. 1;
+ * its stability polynomial is printed in Sec. 3.2 with the z^5 coefficient
+ * eta = 0.004477718303076), in Shu-Osher form:
+ *   U1 = U + b10 dt L(U)
+ *   U2 = a20 U + a21 U1 + b21 dt L(U1)
+ *   U3 = a30 U + a32 U2 + b32 dt L(U2)
+ *   U4 = a40 U + a43 U3 + b43 dt L(U3)
+ *   U5 = a52 U2 + a53 U3 + b53 dt L(U3) + a54 U4 + b54 dt L(U4)
+ * Every term a U_k + b dt L(U_k) is a times one limited forward-Euler stage
+ * of step (b / a) dt, so the step is a convex combination of such stages.
+ * W1..W4 are work arrays; U is overwritten with U5. */
+static const double RK54_B10 = 0.391752226571890;
+static const double RK54_A20 = 0.444370493651235, RK54_A21 = 0.555629506348765, RK54_B21 = 0.368410593050371;
+static const double RK54_A30 = 0.620101851488403, RK54_A32 = 0.379898148511597, RK54_B32 = 0.251891774271694;
+static const double RK54_A40 = 0.178079954393132, RK54_A43 = 0.821920045606868, RK54_B43 = 0.544974750228521;
+static const double RK54_A52 = 0.517231671970585, RK54_A53 = 0.096059710526147, RK54_B53 = 0.063692468666290;
+static const double RK54_A54 = 0.386708617503269, RK54_B54 = 0.226007483236906;
+
+void orc_ssprk54_step(const orc_problem *P, double *const *U, double dt, double *const *W1, double *const *W2,
+                      double *const *W3, double *const *W4, orc_diag *dg)
+{
+    long N = ncells(P);
+    int nb = 1 << P->dim;
+    /* W1 = U1 */
+    orc_fe(P, (const double *const *)U, RK54_B10 * dt, W1, dg);
+    /* W2 = U2 = a20 U + a21 FE_{(b21/a21) dt}(U1) */
+    orc_fe(P, (const double *const *)W1, (RK54_B21 / RK54_A21) * dt, W2, dg);
+    for (int z = 0; z < nb; z++)
+        for (long i = 0; i < N; i++) W2[z][i] = RK54_A20 * U[z][i] + RK54_A21 * W2[z][i];
+    if (P->limiter) clamp_all(P, W2, dg);
+    /* W3 = U3 = a30 U + a32 FE_{(b32/a32) dt}(U2) */
+    orc_fe(P, (const double *const *)W2, (RK54_B32 / RK54_A32) * dt, W3, dg);
+    for (int z = 0; z < nb; z++)
+        for (long i = 0; i < N; i++) W3[z][i] = RK54_A30 * U[z][i] + RK54_A32 * W3[z][i];
+    if (P->limiter) clamp_all(P, W3, dg);
+    /* W4 = U4 = a40 U + a43 FE_{(b43/a43) dt}(U3) */
+    orc_fe(P, (const double *const *)W3, (RK54_B43 / RK54_A43) * dt, W4, dg);
+    for (int z = 0; z < nb; z++)
+        for (long i = 0; i < N; i++) W4[z][i] = RK54_A40 * U[z][i] + RK54_A43 * W4[z][i];
+    if (P->limiter) clamp_all(P, W4, dg);
+    /* W1 = FE_{(b53/a53) dt}(U3) (the ratio equals b43/a43 to the printed digits),
+     * W3 = FE_{(b54/a54) dt}(U4); U5 = a52 U2 + a53 W1 + a54 W3 */
+    orc_fe(P, (const double *const *)W3, (RK54_B53 / RK54_A53) * dt, W1, dg);
+    orc_fe(P, (const double *const *)W4, (RK54_B54 / RK54_A54) * dt, W3, dg);
+    for (int z = 0; z < nb; z++)
+        for (long i = 0; i < N; i++) U[z][i] = RK54_A52 * W2[z][i] + RK54_A53 * W1[z][i] + RK54_A54 * W3[z][i];
+    if (P->limiter) clamp_all(P, U, dg);
+}
+
 /* time step from the MPP CFL condition (Eqs. 1d_av_pp_dt, multid_av_pp_dt):
  * dt = C / max_{l, faces} (alpha_L / dx_l + kappa_max / dx_l^2) */
 double orc_dt(const orc_problem *P, const double *const *U, double cfl)

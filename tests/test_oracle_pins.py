@@ -185,6 +185,58 @@ def test_one_ssprk3_step_is_amplification_polynomial():
     np.testing.assert_allclose(U1[1], np.real(vh[1] * np.exp(1j * xi * i)), atol=1e-13)
 
 
+def test_one_ssprk54_step_is_amplification_polynomial():
+    """One oracle SSP-RK(5,4) step on a Fourier mode multiplies its
+    coefficients by R(dt G) with the paper's R(z) = 1 + z + z^2/2 + z^3/6 +
+    z^4/24 + eta z^5, eta = 0.004477718303076 (Sec. 3.2): this pins the
+    Shu-Osher coefficients of the oracle's integrator to the printed eta."""
+    g = golden("table1_max_cfl.json")
+    coeffs = g["stability_polynomials"]["ssprk54"]
+    N, c, k0 = 16, 1.0, 0.02
+    dx = 1.0 / N
+    P = oracle.problem(spec1d(N, 1.0, ("linear", c, 0.0), ("linear", k0, 0.0)))
+    i = np.arange(N)
+    for k, uhat in ((3, np.array([1.0 + 0.3j, 0.7 - 0.2j])), (7, np.array([0.2 - 1.0j, -0.4 + 0.5j]))):
+        xi = 2 * math.pi * k / N
+        U = [np.real(uhat[0] * np.exp(1j * xi * i)), np.real(uhat[1] * np.exp(1j * xi * i))]
+        dt = 0.6 * dx
+        U1, _, _ = oracle.run(P, U, dts=[dt], integrator="ssprk54")
+        G = (c / dx) * paper_symbol("Gc", xi)[0] + (k0 / dx ** 2) * paper_symbol("Gd", xi)[0]
+        Z = dt * G
+        R = np.zeros((2, 2), dtype=complex)
+        Zk = np.eye(2, dtype=complex)
+        for co in coeffs:
+            R += co * Zk
+            Zk = Zk @ Z
+        vh = R @ uhat
+        np.testing.assert_allclose(U1[0], np.real(vh[0] * np.exp(1j * xi * i)), atol=1e-13)
+        np.testing.assert_allclose(U1[1], np.real(vh[1] * np.exp(1j * xi * i)), atol=1e-13)
+
+
+def test_ssprk54_fourth_order_in_time():
+    """On one Fourier mode of a fixed grid the SSP-RK(5,4) error against the
+    exact semi-discrete evolution exp(t G) falls as dt^4."""
+    N, c, k0 = 16, 1.0, 0.02
+    dx = 1.0 / N
+    P = oracle.problem(spec1d(N, 1.0, ("linear", c, 0.0), ("linear", k0, 0.0)))
+    i = np.arange(N)
+    k = 2
+    xi = 2 * math.pi * k / N
+    uhat = np.array([1.0, 0.5 + 0.5j])
+    G = (c / dx) * paper_symbol("Gc", xi)[0] + (k0 / dx ** 2) * paper_symbol("Gd", xi)[0]
+    w, V = np.linalg.eig(G)
+    T = 0.25
+    ex = V @ (np.exp(w * T) * np.linalg.solve(V, uhat))
+    errs = []
+    for m in (8, 16, 32):
+        U = [np.real(uhat[0] * np.exp(1j * xi * i)), np.real(uhat[1] * np.exp(1j * xi * i))]
+        U1, _, _ = oracle.run(P, U, dts=[T / m] * m, integrator="ssprk54")
+        errs.append(max(np.abs(U1[0] - np.real(ex[0] * np.exp(1j * xi * i))).max(),
+                        np.abs(U1[1] - np.real(ex[1] * np.exp(1j * xi * i))).max()))
+    rates = [math.log2(errs[j] / errs[j + 1]) for j in range(2)]
+    assert min(rates) > 3.7, (errs, rates)
+
+
 # ---------------------------------------------------------------------------
 # P5: fourth-order convergence (Example 6.1), 1D/2D/3D
 # ---------------------------------------------------------------------------
