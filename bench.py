@@ -86,7 +86,10 @@ def make_ctx(items, precision=None, variant=None, integrator="ssprk3"):
     return ctx
 
 
-def cpu_baseline(items, target_cells):
+STAGES = {"ssprk3": 3, "ssprk54": 5, "euler": 1}
+
+
+def cpu_baseline(items, target_cells, integrator="ssprk3"):
     """The FP64 oracle on a bounded sample: the first instances of the same
     workload up to target_cells cells, one SSP-RK3 step with CFL steps."""
     import oracle
@@ -101,14 +104,14 @@ def cpu_baseline(items, target_cells):
     t0 = time.perf_counter()
     for s, U in sample:
         P = oracle.problem(s)
-        oracle.run(P, U, nsteps=1, cfl=s["cfl"])
+        oracle.run(P, U, nsteps=1, cfl=s["cfl"], integrator=integrator)
     el = time.perf_counter() - t0
-    return {"value": cells * dofs_per_cell * 3 / el, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "first %d instances of the workload (%d cells), 1 SSP-RK3 step (3 stages), %.1f s"
-                      % (len(sample), cells, el)}
+    return {"value": cells * dofs_per_cell * STAGES[integrator] / el, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "first %d instances of the workload (%d cells), 1 %s step (%d stages), %.1f s"
+                      % (len(sample), cells, integrator, STAGES[integrator], el)}
 
 
-def fp64_plain(items, steps, max_cells):
+def fp64_plain(items, steps, max_cells, integrator="ssprk3"):
     """Same instances in FP64, one context per instance, stepped one after
     the other (no batching): the 'plain' form."""
     from paper_2510_11527_amd import af
@@ -120,7 +123,7 @@ def fp64_plain(items, steps, max_cells):
             break
     ctxs = []
     for s, U in sample:
-        c = af.Context(dict(s, precision=64))
+        c = af.Context(dict(s, precision=64), integrator=integrator)
         c.set_state(0, U)
         c.step(2)  # warm up (graph build)
         ctxs.append(c)
@@ -131,7 +134,7 @@ def fp64_plain(items, steps, max_cells):
     for c in ctxs:
         c.close()
     dpc = 2 ** items[0][0]["dim"]
-    return {"value": cells * dpc * 3 * steps / el, "unit": UNIT, "dtype": "f64", "instances": len(sample),
+    return {"value": cells * dpc * STAGES[integrator] * steps / el, "unit": UNIT, "dtype": "f64", "instances": len(sample),
             "cells": cells, "steps": steps, "seconds": el}
 
 
@@ -145,7 +148,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
-    ap.add_argument("--integrator", default="ssprk3", choices=["ssprk3", "euler"],
+    ap.add_argument("--integrator", default="ssprk3", choices=["ssprk3", "ssprk54", "euler"],
                     help="euler: one forward-Euler stage plus a plain state copy per step (profiling reference)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -174,7 +177,7 @@ def main():
     ctx.step(args.steps)
     t2 = time.perf_counter()
     el = t2 - t1
-    per_step = 3 if args.integrator == "ssprk3" else 1
+    per_step = STAGES[args.integrator]
     stages = per_step * args.steps
     value = work["dofs"] * stages / el
     log("timed %d steps in %.4f s" % (args.steps, el))
@@ -206,12 +209,13 @@ def main():
         line["roofline"] = roof
     if not args.no_fp64_plain and prec == 32:
         try:
-            line["fp64_plain"] = fp64_plain(items, max(10, args.steps // 10), 4_000_000)
+            line["fp64_plain"] = fp64_plain(items, max(10, args.steps // 10), 4_000_000, args.integrator)
             line["fp32_batched_over_fp64_plain"] = value / line["fp64_plain"]["value"]
         except Exception as e:  # reported, not fatal
             line["fp64_plain"] = {"error": str(e)}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(items, 12_000_000 if items[0][0]["dim"] == 2 else 2_000_000)
+        line["cpu_baseline"] = cpu_baseline(items, 12_000_000 if items[0][0]["dim"] == 2 else 2_000_000,
+                                              args.integrator)
     print(json.dumps(line), flush=True)
 
 

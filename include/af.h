@@ -62,7 +62,10 @@ typedef enum {
 
 typedef enum {
     AF_RK_SSP3 = 0,   /* SSP-RK3, Shu-Osher form; R(z) of Sec. 3.2 */
-    AF_RK_EULER = 1   /* one forward-Euler stage per step (Sec. 5)  */
+    AF_RK_EULER = 1,  /* one forward-Euler stage per step (Sec. 5)  */
+    AF_RK_SSP54 = 2   /* SSP-RK(5,4) of Spiteri and Ruuth, the paper's integrator
+                         (Sec. 1; R(z) with eta = 0.004477718303076 in Sec. 3.2);
+                         five stages, two more state buffers */
 } af_integrator;
 
 typedef struct {
@@ -75,7 +78,9 @@ typedef struct {
     double diff_par[2];      /* p0, p1 */
     double umin, umax;       /* bounds; NaN: min/max over the DoFs of the first af_set_state */
     double cfl;              /* C in dt = C / max_{l,faces}(alpha_l/dx_l + kappa_max/dx_l^2),
-                                Eqs. (1d_av_pp_dt, multid_av_pp_dt); with the limiter C <= 1/(2d) */
+                                Eqs. (1d_av_pp_dt, multid_av_pp_dt); with the limiter every
+                                forward-Euler stage needs C s <= 1/(2d), s its step in units of
+                                dt: C <= 1/(2d) for SSP-RK3 and Euler, C <= 0.7541/d for SSP-RK(5,4) */
     int limiter;             /* 1: monolithic convex limiting of the averages (Sec. 5.1.1, 5.2.1)
                                 and projection of the point values (Sec. 5.1.2) */
     int si_blend;            /* 1: smoothness-indicator blending (Sec. 5.1.3) */
@@ -102,8 +107,9 @@ typedef struct {
  * with its own time step).  All instances must share dim, precision,
  * limiter, si_blend and integrator (else AF_ERR_UNSUPPORTED); grids, fluxes,
  * potentials, bounds and CFL numbers may differ.  Validation: n >= 4 on used
- * axes, hi > lo, 0 < cfl, cfl <= 1/(2 dim) with the limiter (AF_ERR_CFL).
- * Allocates three state buffers per instance on the current HIP device. */
+ * axes, hi > lo, 0 < cfl, and with the limiter the stage bound on cfl above
+ * (AF_ERR_CFL).  Allocates three state buffers per instance (five for
+ * SSP-RK(5,4)) on the current HIP device. */
 af_status af_create(int n_inst, const af_problem *probs, af_ctx **out);
 
 /* Frees all device memory and graphs of the context.  NULL is accepted. */

@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "AF_OK", -1: "AF_ERR_ARG", -2: "AF_ERR_ALLOC", -3: "AF_ERR_DE
                 -5: "AF_ERR_NONFINITE", -6: "AF_ERR_CFL", -7: "AF_ERR_STATE", -8: "AF_ERR_UNSUPPORTED"}
 FLUX = {"linear": 0, "quad": 1, "bl": 2, "bl_grav": 3}
 DIFF = {"linear": 0, "power": 1, "deadzone": 2, "bl": 3, "ramp2": 4}
-INTEGRATORS = {"ssprk3": 0, "euler": 1}
+INTEGRATORS = {"ssprk3": 0, "euler": 1, "ssprk54": 2}
 
 EXPORTS = ["af_create", "af_destroy", "af_set_state", "af_get_state", "af_step", "af_residual", "af_norms",
            "af_last_error", "af_set_stream", "af_set_variant", "af_num_variants", "af_variant_name",

@@ -67,17 +67,28 @@ struct InstState {
     float pad2;
 };
 
+// How a stage combines its forward-Euler result v (of step dts * dt) with
+// other states (Shu-Osher form of the SSP Runge-Kutta methods):
+//   kCombFE:    out = v
+//   kCombBlend: out = X0 + w (v - X0)                  (a convex blend)
+//   kCombSum:   out = c0 X0 + c1 X1 + cin IN + w v      (IN: the stage input)
+enum : int { kCombFE = 0, kCombBlend = 1, kCombSum = 2 };
+constexpr int kStageRHS = -1;  // StageParams::stage of a right-hand-side evaluation
+
 template <class T>
 struct StageParams {
     const InstDev *inst;
     const int4 *work;    // (instance, tile x, tile y, tile z) per block
     int nwork;
     const T *in;         // stage input U^(s-1)
-    const T *un;         // U^n for the RK combination
+    const T *un;         // X0 of the combination (U^n)
+    const T *x1;         // X1 of a kCombSum stage, else null
     T *out;              // stage output (or right-hand side)
     InstState *st;
-    int stage;           // 0: forward Euler, 1..3: SSP-RK3 stage, 4: residual
-    int pad;
+    int stage;           // kStageRHS: right-hand side only; else the stage's index in the step (1, 2, ...)
+    int mode;            // kComb*
+    T w, c0, c1, cin;    // combination weights
+    T dts;               // the forward-Euler step of this stage is dts * dt
     // not null: every wave w of the block of work item k stores the ordered
     // keys (see ordered_key) of the min and max average it wrote to
     // mm[2 (k W + w)] and mm[2 (k W + w) + 1], W = waves per block

@@ -37,7 +37,7 @@ struct af_ctx {
     unsigned long long *d_mm = nullptr;  // per-wave min / max slots of the last stage
     int waves_per_block = 1;
     int nchunks = 0;
-    void *buf[3] = {nullptr, nullptr, nullptr};
+    void *buf[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // state buffers (A = U^n)
     long long total = 0;     // elements per state buffer
     double *d_npart = nullptr, *d_nout = nullptr;
     hipStream_t own_stream = nullptr, stream = nullptr;
@@ -213,6 +213,54 @@ void set_unified_potential(InstDev &I, const af_problem &P)
     }
 }
 
+// One stage of a time step in Shu-Osher form: the forward-Euler stage of
+// step dts * dt on buffer `in`, combined (af4::kComb*) with X0 = U^n (buffer
+// 0), X1 (buffer x1) and the stage input, into buffer `out`.
+struct StageSpec {
+    int in, out, x1;  // buffer indices; x1 < 0: none
+    int mode;
+    double w, c0, c1, cin, dts;
+    bool last;        // the step's last stage: stores the min / max slots
+};
+
+// SSP-RK3 (Shu-Osher form; stability polynomial of Sec. 3.2)
+const StageSpec kSSP3[3] = {
+    {0, 1, -1, af4::kCombFE, 1.0, 0, 0, 0, 1.0, false},
+    {1, 2, -1, af4::kCombBlend, 0.25, 0, 0, 0, 1.0, false},
+    {2, 0, -1, af4::kCombBlend, 2.0 / 3.0, 0, 0, 0, 1.0, true},
+};
+
+// SSP-RK(5,4) of Spiteri and Ruuth (2002), the paper's integrator (its
+// stability polynomial, with the z^5 coefficient 0.004477718303076, is printed
+// in Sec. 3.2), in Shu-Osher form:
+//   U1 = U + b10 dt L(U),  Uk = ak0 U + ak,k-1 U(k-1) + bk,k-1 dt L(U(k-1)), k = 2..4,
+//   U5 = a52 U2 + a53 U3 + b53 dt L(U3) + a54 U4 + b54 dt L(U4).
+// Each "a V + b dt L(V)" is a times a forward-Euler stage of step (b/a) dt.
+// b53/a53 equals b43/a43, so a53 (U3 + (b53/a53) dt L(U3)) is recovered from
+// U4 as (a53/a43)(U4 - a40 U), which spares a sixth stage: the last stage
+// sums a52 U2 - (a53 a40 / a43) U + (a53 / a43) U4 + a54 FE(U4).
+constexpr double kB10 = 0.391752226571890;
+constexpr double kA21 = 0.555629506348765, kB21 = 0.368410593050371;
+constexpr double kA32 = 0.379898148511597, kB32 = 0.251891774271694;
+constexpr double kA40 = 0.178079954393132, kA43 = 0.821920045606868, kB43 = 0.544974750228521;
+constexpr double kA52 = 0.517231671970585, kA53 = 0.096059710526147;
+constexpr double kA54 = 0.386708617503269, kB54 = 0.226007483236906;
+const StageSpec kSSP54[5] = {
+    {0, 1, -1, af4::kCombFE, 1.0, 0, 0, 0, kB10, false},
+    {1, 2, -1, af4::kCombBlend, kA21, 0, 0, 0, kB21 / kA21, false},
+    {2, 3, -1, af4::kCombBlend, kA32, 0, 0, 0, kB32 / kA32, false},
+    {3, 4, -1, af4::kCombBlend, kA43, 0, 0, 0, kB43 / kA43, false},
+    {4, 0, 2, af4::kCombSum, kA54, -kA53 * kA40 / kA43, kA52, kA53 / kA43, kB54 / kA54, true},
+};
+// largest forward-Euler step of a stage, in units of dt
+constexpr double kSSP54MaxStage = kB21 / kA21;
+
+const StageSpec kEuler[1] = {{0, 1, -1, af4::kCombFE, 1.0, 0, 0, 0, 1.0, true}};
+
+int num_stages(int integ) { return integ == AF_RK_SSP3 ? 3 : (integ == AF_RK_SSP54 ? 5 : 1); }
+const StageSpec *stages_of(int integ) { return integ == AF_RK_SSP3 ? kSSP3 : (integ == AF_RK_SSP54 ? kSSP54 : kEuler); }
+int num_buffers(int integ) { return integ == AF_RK_SSP54 ? 5 : 3; }
+
 bool is_int_exponent(double p, int *m)
 {
     double r = std::round(p);
@@ -238,10 +286,13 @@ af_status validate(const af_problem &P, int idx)
     }
     if (P.diff < AF_A_LINEAR || P.diff > AF_A_RAMP2) return bad(AF_ERR_ARG, "unknown potential kind");
     if (P.precision != 32 && P.precision != 64) return bad(AF_ERR_ARG, "precision must be 32 or 64");
-    if (P.integrator != AF_RK_SSP3 && P.integrator != AF_RK_EULER) return bad(AF_ERR_ARG, "unknown integrator");
+    if (P.integrator != AF_RK_SSP3 && P.integrator != AF_RK_EULER && P.integrator != AF_RK_SSP54)
+        return bad(AF_ERR_ARG, "unknown integrator");
     if (!(P.cfl > 0)) return bad(AF_ERR_CFL, "cfl must be positive");
-    if (P.limiter && P.cfl > 1.0 / (2 * P.dim) * (1 + 1e-12))
-        return bad(AF_ERR_CFL, "with the limiter cfl must not exceed 1/(2 dim)");
+    // every forward-Euler stage must satisfy the MPP condition C <= 1/(2 dim)
+    const double stage_max = P.integrator == AF_RK_SSP54 ? kSSP54MaxStage : 1.0;
+    if (P.limiter && P.cfl * stage_max > 1.0 / (2 * P.dim) * (1 + 1e-12))
+        return bad(AF_ERR_CFL, "with the limiter cfl times the largest stage step must not exceed 1/(2 dim)");
     if (!std::isnan(P.umin) && !std::isnan(P.umax) && !(P.umax >= P.umin)) return bad(AF_ERR_ARG, "umax < umin");
     if (P.si_blend && !(P.si_gamma >= 0)) return bad(AF_ERR_ARG, "si_gamma must be >= 0");
     return AF_OK;
@@ -301,33 +352,39 @@ af_status build_work(af_ctx *c)
 }
 
 template <class T>
-StageParams<T> stage_params(af_ctx *c, int in, int out, int stage)
+StageParams<T> stage_params(af_ctx *c, const StageSpec &sp, int stage)
 {
     StageParams<T> p;
     p.inst = c->d_inst;
     p.work = c->d_work;
     p.nwork = c->nwork;
-    p.in = (const T *)c->buf[in];
+    p.in = (const T *)c->buf[sp.in];
     p.un = (const T *)c->buf[0];
-    p.out = (T *)c->buf[out];
+    p.x1 = sp.x1 >= 0 ? (const T *)c->buf[sp.x1] : nullptr;
+    p.out = (T *)c->buf[sp.out];
     p.st = c->d_st;
     p.stage = stage;
-    p.pad = 0;
+    p.mode = sp.mode;
+    p.w = (T)sp.w;
+    p.c0 = (T)sp.c0;
+    p.c1 = (T)sp.c1;
+    p.cin = (T)sp.cin;
+    p.dts = (T)sp.dts;
     p.mm = nullptr;
     return p;
 }
 
-hipError_t launch_stage(af_ctx *c, int in, int out, int stage, bool lim, bool si, int wstart, int wcount,
+hipError_t launch_stage(af_ctx *c, const StageSpec &sp, int stage, bool lim, bool si, int wstart, int wcount,
                         bool minmax = false)
 {
     if (c->prec == 32) {
-        StageParams<float> p = stage_params<float>(c, in, out, stage);
+        StageParams<float> p = stage_params<float>(c, sp, stage);
         p.work += wstart;
         p.nwork = wcount;
         p.mm = minmax ? c->d_mm + (size_t)2 * c->waves_per_block * wstart : nullptr;
         return af4::stage_launch(c->dim, 32, lim, si, c->caps, c->variant, wcount, &p, c->stream);
     }
-    StageParams<double> p = stage_params<double>(c, in, out, stage);
+    StageParams<double> p = stage_params<double>(c, sp, stage);
     p.work += wstart;
     p.nwork = wcount;
     p.mm = minmax ? c->d_mm + (size_t)2 * c->waves_per_block * wstart : nullptr;
@@ -349,20 +406,14 @@ hipError_t enqueue_step(af_ctx *c, bool ws, std::vector<hipEvent_t> *events, siz
                              c->waves_per_block, c->stream);
     if (e != hipSuccess) return e;
     const bool mm = cfl_from_keys(c);
-    auto stage = [&](int in, int out, int st, bool last) -> hipError_t {
+    const StageSpec *sp = stages_of(c->integ);
+    for (int k = 0; k < num_stages(c->integ); k++) {
         if (events) (void)hipEventRecord((*events)[(*ev_next)++], c->stream);
-        hipError_t r = launch_stage(c, in, out, st, c->lim, c->si, 0, c->nwork, last && mm);
+        e = launch_stage(c, sp[k], k + 1, c->lim, c->si, 0, c->nwork, sp[k].last && mm);
         if (events) (void)hipEventRecord((*events)[(*ev_next)++], c->stream);
-        return r;
-    };
-    if (c->integ == AF_RK_SSP3) {
-        if ((e = stage(0, 1, 1, false)) != hipSuccess) return e;
-        if ((e = stage(1, 2, 2, false)) != hipSuccess) return e;
-        if ((e = stage(2, 0, 3, true)) != hipSuccess) return e;
-    } else {
-        if ((e = stage(0, 1, 0, true)) != hipSuccess) return e;
-        e = af4::copy_launch(c->prec, c->buf[1], c->buf[0], c->total, c->stream);
+        if (e != hipSuccess) return e;
     }
+    if (c->integ == AF_RK_EULER) e = af4::copy_launch(c->prec, c->buf[1], c->buf[0], c->total, c->stream);
     return e;
 }
 
@@ -517,7 +568,7 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
         return true;
     };
     bool ok = true;
-    for (int b = 0; b < 3 && ok; b++) ok = alloc(&c->buf[b], (size_t)c->total * vbytes(c));
+    for (int b = 0; b < num_buffers(c->integ) && ok; b++) ok = alloc(&c->buf[b], (size_t)c->total * vbytes(c));
     ok = ok && alloc((void **)&c->d_inst, sizeof(InstDev) * n_inst);
     ok = ok && alloc((void **)&c->d_st, sizeof(InstState) * n_inst);
     ok = ok && alloc((void **)&c->d_ctl, sizeof(StepCtl));
@@ -730,7 +781,7 @@ af_status af_step_timed(af_ctx *c, int nsteps, double t_end, const double *dt_pr
     af_status s = check_ready(c);
     if (s != AF_OK) return s;
     if ((s = upload_ctl(c, t_end, dt_prescribed)) != AF_OK) return s;
-    const int per = c->integ == AF_RK_SSP3 ? 3 : 1;
+    const int per = num_stages(c->integ);
     std::vector<hipEvent_t> ev((size_t)2 * per * nsteps);
     for (auto &e : ev) HIPOK(c, hipEventCreate(&e));
     size_t next = 0;
@@ -759,7 +810,8 @@ af_status af_residual(af_ctx *c, int inst, double *const *rhs)
 {
     if (!c || inst < 0 || inst >= c->n_inst || !rhs) return fail(c, AF_ERR_ARG, "af_residual: bad arguments");
     if (!c->have_state[inst]) return fail(c, AF_ERR_STATE, "af_residual before af_set_state");
-    HIPOK(c, launch_stage(c, 0, 1, 4, false, false, c->work_start[inst], c->work_count[inst]));
+    const StageSpec fe = {0, 1, -1, af4::kCombFE, 1.0, 0, 0, 0, 1.0, false};
+    HIPOK(c, launch_stage(c, fe, af4::kStageRHS, false, false, c->work_start[inst], c->work_count[inst]));
     const InstDev &I = c->ih[inst];
     std::vector<char> stage((size_t)I.ncell * vbytes(c));
     const char *base = (const char *)c->buf[1] + (size_t)I.off * vbytes(c);
@@ -806,8 +858,14 @@ af_status af_work(const af_ctx *c, double *bytes_per_stage, double *cells, doubl
     if (!c) return AF_ERR_ARG;
     double nc = 0;
     for (const InstDev &I : c->ih) nc += (double)I.ncell;
-    const double per_cell_stage =
-        (c->integ == AF_RK_SSP3 ? (2.0 + 3.0 + 3.0) / 3.0 : 2.0) * (1 << c->dim) * (double)vbytes(c);
+    // state arrays read or written per stage: input and output, plus X0 for
+    // blended stages and X0, X1 for summed ones, averaged over the step
+    double arrays = 0;
+    for (int k = 0; k < num_stages(c->integ); k++) {
+        const StageSpec &sp = stages_of(c->integ)[k];
+        arrays += 2.0 + (sp.mode == af4::kCombBlend ? 1.0 : 0.0) + (sp.mode == af4::kCombSum ? 2.0 : 0.0);
+    }
+    const double per_cell_stage = arrays / num_stages(c->integ) * (1 << c->dim) * (double)vbytes(c);
     if (bytes_per_stage) *bytes_per_stage = per_cell_stage * nc;
     if (cells) *cells = nc;
     if (dofs) *dofs = nc * (1 << c->dim);

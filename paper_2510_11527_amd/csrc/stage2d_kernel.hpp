@@ -124,8 +124,9 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
     const long long kst = I.kstride;
     const T *__restrict__ in = p.in + I.off;
     const T *__restrict__ un = p.un + I.off;
+    const T *__restrict__ x1 = p.x1 ? p.x1 + I.off : nullptr;
     T *__restrict__ out = p.out + I.off;
-    const bool residual = p.stage == 4;
+    const bool residual = p.stage == kStageRHS;
     const double dtd = p.st[wk.x].dt;
     const int tid = (int)threadIdx.x;
     // own cells of this thread: column i, rows j and j+1
@@ -162,7 +163,7 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
         c1[l] = P.fk[l] == kFLinear ? P.fc[l] : T(0);
         c2[l] = P.fk[l] == kFQuad ? P.fc[l] : T(0);
     }
-    const T dt = (T)dtd;
+    const T dt = (T)dtd * p.dts;
     const T umin = P.umin, umax = P.umax;
     T idx1[2], idx2[2], i6dx[2], mu[2], nu[2];
 #pragma unroll
@@ -170,8 +171,8 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
         idx1[l] = (T)I.idx1[l];
         idx2[l] = (T)I.idx2[l];
         i6dx[l] = (T)I.i6dx[l];
-        mu[l] = (T)p.st[wk.x].mu[l];
-        nu[l] = (T)p.st[wk.x].nu[l];
+        mu[l] = (T)p.st[wk.x].mu[l] * p.dts;
+        nu[l] = (T)p.st[wk.x].nu[l] * p.dts;
     }
     const T K = T(4);
 
@@ -205,8 +206,8 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
     T unv[2][4];
 #pragma unroll
     for (int z = 0; z < 4; z++) {
-        unv[0][z] = (!residual && p.stage >= 2 && own0) ? un[z * kst + g0] : T(0);
-        unv[1][z] = (!residual && p.stage >= 2 && own1) ? un[z * kst + g1] : T(0);
+        unv[0][z] = (!residual && p.mode != kCombFE && own0) ? un[z * kst + g0] : T(0);
+        unv[1][z] = (!residual && p.mode != kCombFE && own1) ? un[z * kst + g1] : T(0);
     }
 
     // ---- A: tile + halo -> LDS, with the pointwise tables
@@ -308,10 +309,11 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
                     out[z * kst + gi] = R[k];
                     continue;
                 }
-                T v = Hu(px[k], py[k]) + dt * R[k];
+                const T vin = Hu(px[k], py[k]);
+                T v = vin + dt * R[k];
                 if (!isfinite(v)) bad = true;
                 if constexpr (LIM) v = clampb(v, umin, umax);
-                v = rk_combine(p.stage, v, unv[c][z]);
+                v = stage_combine(p, v, unv[c][z], x1 ? x1[z * kst + gi] : T(0), vin);
                 if constexpr (LIM) v = clampb(v, umin, umax);
                 out[z * kst + gi] = v;
             }
@@ -449,7 +451,7 @@ __global__ void __launch_bounds__(NT) stage2d_kernel(StageParams<T> p)
             clamp_mag = fmax(clamp_mag, (double)fabs(cl - v));
             v = cl;
         }
-        v = rk_combine(p.stage, v, unv[c][0]);
+        v = stage_combine(p, v, unv[c][0], x1 ? x1[gi] : T(0), u);
         if constexpr (LIM) {
             const T cl = clampb(v, umin, umax);
             clamp_mag = fmax(clamp_mag, (double)fabs(cl - v));

@@ -100,8 +100,8 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     const int n0 = Ic->n[0], n1 = Ic->n[1];
     const int tx0 = wk.y, ty0 = wk.z;
     const int ox = tx0 * TX, oy = ty0 * TY;
-    // the right-hand side (stage 4) is evaluated by the unlimited instantiation
-    const bool residual = !LIM && p.stage == 4;
+    // the right-hand side is evaluated by the unlimited instantiation
+    const bool residual = !LIM && p.stage == kStageRHS;
     const double dtd = Sc->dt;
     const int tid = (int)threadIdx.x;
     // the instance's DoF blocks of the three state buffers as buffer
@@ -112,6 +112,10 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     const auto rin = __builtin_amdgcn_make_buffer_rsrc((void *)(p.in + Ic->off), 0, (int)blk, kBufWord3);
     const auto run = __builtin_amdgcn_make_buffer_rsrc((void *)(p.un + Ic->off), 0, (int)blk, kBufWord3);
     const auto rout = __builtin_amdgcn_make_buffer_rsrc((void *)(p.out + Ic->off), 0, (int)blk, kBufWord3);
+    // X1 of a kCombSum stage; otherwise an empty range (loads read 0 and
+    // touch no memory, which keeps the load sequence free of branches)
+    const auto rx1 = __builtin_amdgcn_make_buffer_rsrc((void *)(p.x1 ? p.x1 + Ic->off : p.in + Ic->off), 0,
+                                                       p.x1 ? (int)blk : 0, kBufWord3);
     auto ld = [&](const __amdgpu_buffer_rsrc_t &r, int z, unsigned gi) -> T {
         return buf_load<T>(r, gi * (unsigned)sizeof(T), (unsigned)z * kb);
     };
@@ -169,7 +173,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         c2[l] = Ic->fk[l] == kFQuad ? c : T(0);
         c2x2[l] = T(2) * c2[l];
     }
-    const T dt = prm(dtd, Sc->f_dt);
+    const T dt = prm(dtd, Sc->f_dt) * p.dts;
     const T umin = prm(Ic->umin, Ic->f_umin), umax = prm(Ic->umax, Ic->f_umax);
     const T pc1 = prm(Ic->pc1, Ic->f_pc[0]), pc2 = prm(Ic->pc2, Ic->f_pc[1]), pc3 = prm(Ic->pc3, Ic->f_pc[2]);
     T idx1[2], idx2[2], i6dx[2], mu[2], nu[2];
@@ -178,8 +182,8 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         idx1[l] = prm(Ic->idx1[l], Ic->f_idx1[l]);
         idx2[l] = prm(Ic->idx2[l], Ic->f_idx2[l]);
         i6dx[l] = prm(Ic->i6dx[l], Ic->f_i6dx[l]);
-        mu[l] = prm(Sc->mu[l], Sc->f_mu[l]);
-        nu[l] = prm(Sc->nu[l], Sc->f_nu[l]);
+        mu[l] = prm(Sc->mu[l], Sc->f_mu[l]) * p.dts;
+        nu[l] = prm(Sc->nu[l], Sc->f_nu[l]) * p.dts;
     }
     // K = 2 d = 4: the LLF states use K mu, theta^c and theta^d 3 K mu and 3 K nu
     T kmu[2], k3mu[2], k3nu[2];
@@ -244,14 +248,20 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
 #pragma unroll
         for (int z = 0; z < 4; z++) halo[k][z] = ld(rin, z, gi);
     }
-    // U^n of the own cells (the RK combination of stages 2 and 3; the other
-    // stages read it too, from cache, which keeps the load sequence free of
-    // branches so that the waits above stay exact)
-    T unv[2][4];
+    // X0 (U^n) and X1 of the own cells for the stage's combination (a stage
+    // that does not combine reads X0 too, from cache, and X1 from an empty
+    // range: the load sequence stays free of branches, so the waits above
+    // stay exact)
+    T unv[2][4], x1v[2][4];
 #pragma unroll
     for (int z = 0; z < 4; z++) {
         unv[0][z] = ld(run, z, g0);
         unv[1][z] = ld(run, z, g1);
+    }
+#pragma unroll
+    for (int z = 0; z < 4; z++) {
+        x1v[0][z] = ld(rx1, z, g0);
+        x1v[1][z] = ld(rx1, z, g1);
     }
     auto put_cell = [&](int xx, int yy, const T *u) {
         cg[cgi(xx, yy)] = V2<T>{u[0], pot(u[0])};
@@ -361,7 +371,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
                 T v = R[c][z - 1];
                 if (!isfinite(v)) bad = true;
                 if constexpr (LIM) v = clampb(v, umin, umax);
-                v = rk_combine(p.stage, v, unv[c][z]);
+                v = stage_combine(p, v, unv[c][z], x1v[c][z], Su(z == 1 ? SXF : (z == 2 ? SYF : SK), x, y + c));
                 if constexpr (LIM) v = clampb(v, umin, umax);
                 st(z, gi, v);
             }
@@ -519,7 +529,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
             clamp_mag = fmax(clamp_mag, (T)fabs(cl - v));
             v = cl;
         }
-        v = rk_combine(p.stage, v, unv[c][0]);
+        v = stage_combine(p, v, unv[c][0], x1v[c][0], u);
         if constexpr (LIM) {
             const T cl = clampb(v, umin, umax);
             clamp_mag = fmax(clamp_mag, (T)fabs(cl - v));

@@ -211,14 +211,15 @@ __device__ __forceinline__ constexpr int zeta_mask(int z)
     return D == 3 ? (z == 3 ? 4 : (z == 4 ? 3 : z)) : z;
 }
 
+// The stage's combination of its forward-Euler result v with X0, X1 and the
+// stage input vin (kComb*); the blend is written so that its weights sum to
+// one exactly.
 template <class T>
-__device__ __forceinline__ T rk_combine(int stage, T fe, T un)
+__device__ __forceinline__ T stage_combine(const StageParams<T> &p, T v, T x0, T x1, T vin)
 {
-    // U2 = 3/4 U^n + 1/4 FE(U1), U^{n+1} = 1/3 U^n + 2/3 FE(U2), written so
-    // that the weights sum to one exactly
-    if (stage == 2) return un + T(0.25) * (fe - un);
-    if (stage == 3) return un + T(2.0 / 3.0) * (fe - un);
-    return fe;
+    if (p.mode == kCombBlend) return x0 + p.w * (v - x0);
+    if (p.mode == kCombSum) return ((p.c0 * x0 + p.c1 * x1) + p.cin * vin) + p.w * v;
+    return v;
 }
 
 // Wave-wide maximum of an unsigned value in six DPP steps (shifts within rows
@@ -328,8 +329,9 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
     const long long kst = I.kstride;
     const T *__restrict__ in = p.in + I.off;
     const T *__restrict__ un = p.un + I.off;
+    const T *__restrict__ x1 = p.x1 ? p.x1 + I.off : nullptr;
     T *__restrict__ out = p.out + I.off;
-    const bool residual = p.stage == 4;
+    const bool residual = p.stage == kStageRHS;
     const double dtd = p.st[wk.x].dt;
 
     const T inf = __builtin_huge_val();
@@ -349,7 +351,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
 
     Phys<T> P;
     P.load(I, D);
-    const T dt = (T)dtd;
+    const T dt = (T)dtd * p.dts;
     const T K = T(2 * D);
     T idx1[3], idx2[3], i6dx[3], mu[3], nu[3];
 #pragma unroll
@@ -357,8 +359,8 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
         idx1[l] = (T)I.idx1[l];
         idx2[l] = (T)I.idx2[l];
         i6dx[l] = (T)I.i6dx[l];
-        mu[l] = (T)p.st[wk.x].mu[l];
-        nu[l] = (T)p.st[wk.x].nu[l];
+        mu[l] = (T)p.st[wk.x].mu[l] * p.dts;
+        nu[l] = (T)p.st[wk.x].nu[l] * p.dts;
     }
 
     // ---- A: stage tile + halo (averages -> ub, point values -> half grid)
@@ -503,7 +505,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
             T v = u0 + dt * R;
             if (!isfinite(v)) bad = true;
             if constexpr (LIM) v = clampb(v, P.umin, P.umax);
-            v = rk_combine(p.stage, v, un[zk * kst + gi]);
+            v = stage_combine(p, v, un[zk * kst + gi], x1 ? x1[zk * kst + gi] : T(0), u0);
             if constexpr (LIM) v = clampb(v, P.umin, P.umax);
             out[zk * kst + gi] = v;
         }
@@ -664,7 +666,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
             clamp_mag = fmax(clamp_mag, (double)fabs(c - v));
             v = c;
         }
-        v = rk_combine(p.stage, v, un[gi]);
+        v = stage_combine(p, v, un[gi], x1 ? x1[gi] : T(0), u);
         if constexpr (LIM) {
             T c = clampb(v, P.umin, P.umax);
             clamp_mag = fmax(clamp_mag, (double)fabs(c - v));

@@ -117,6 +117,37 @@ def test_ssprk3_steps_match_oracle(name):
         assert nrm["max_clamp"] <= 4 * ulp * max(1.0, abs(s["umax"]), abs(s["umin"]))
 
 
+@pytest.mark.parametrize("name", ["c1", "c2", "c3_64", "c3_32", "c4", "c5"])
+def test_ssprk54_steps_match_oracle(name):
+    """Ten SSP-RK(5,4) steps (the paper's integrator) with the oracle's CFL
+    steps prescribed to both sides; exact bounds with the limiter."""
+    spec, U = _steps_case(name)
+    prec = spec["precision"]
+    s, U = prepare(spec, U, prec)
+    P = oracle.problem(s)
+    Uo, t, dts = oracle.run(P, U, nsteps=10, cfl=s["cfl"], integrator="ssprk54")
+    note("ssprk54 %s prec=%d n=%s dt0=%.3e" % (name, prec, s["n"], dts[0]))
+    V, tg, used, nrm = gpu_run(s, U, dts=dts, integrator="ssprk54")
+    err = rel_l1(V, Uo)
+    assert err <= TOL[prec], err
+    assert abs(tg - t) <= 1e-15 * max(1.0, t) + 1e-300
+    if s.get("limiter"):
+        assert min(v.min() for v in V) >= s["umin"] and max(v.max() for v in V) <= s["umax"]
+        ulp = np.spacing(np.float32(1.0)) if prec == 32 else np.spacing(1.0)
+        assert nrm["max_clamp"] <= 4 * ulp * max(1.0, abs(s["umax"]), abs(s["umin"]))
+
+
+def test_ssprk54_cfl_bound():
+    """With the limiter every forward-Euler stage must satisfy C s <= 1/(2d);
+    the largest SSP-RK(5,4) stage step is s = b21/a21 = 0.66305 dt."""
+    spec, U = W.config2(n=16)
+    ok = dict(spec, cfl=0.25 / 0.6630508078509)
+    af.Context(ok, integrator="ssprk54").close()
+    with pytest.raises(af.AFError) as e:
+        af.Context(dict(spec, cfl=0.25 / 0.66), integrator="ssprk54")
+    assert e.value.status == af.AF_ERR_CFL
+
+
 @pytest.mark.parametrize("name", ["c1", "c2", "c3_32", "c5"])
 def test_cfl_time_step_matches_oracle(name):
     spec, U = _steps_case(name)
@@ -146,6 +177,24 @@ def test_config1_full_run_matches_exact_and_oracle():
     assert rel_l1(V, Uo) <= 1e-12
     ex = W.rescale_free_fourier_1d(spec, spec["phi"], 1.0)
     assert max(np.abs(a - b).mean() for a, b in zip(V, ex)) < 5e-6
+
+
+def test_config1_stated_cfl_with_ssprk54_matches_oracle():
+    """The 1D workload at its stated C = 0.4 with SSP-RK(5,4) to T = 1:
+    GPU vs oracle and vs the exact solution."""
+    spec, U = W.config1(cfl=0.4)
+    P = oracle.problem(spec)
+    Uo, t, dts = oracle.run(P, U, cfl=0.4, t_end=1.0, integrator="ssprk54")
+    ctx = af.Context(spec, integrator="ssprk54")
+    ctx.set_state(0, U)
+    ctx.step(len(dts) + 2, t_end=1.0)
+    V, tg = ctx.get_state(0)
+    nrm = ctx.norms(0)
+    ctx.close()
+    assert abs(tg - 1.0) < 1e-13 and nrm["steps"] == len(dts)
+    assert rel_l1(V, Uo) <= 1e-12
+    ex = W.rescale_free_fourier_1d(spec, spec["phi"], 1.0)
+    assert max(np.abs(a - b).mean() for a, b in zip(V, ex)) < 2e-7
 
 
 def test_divergence_is_reported():
@@ -270,7 +319,7 @@ def test_conservation_and_bounds_long_run():
 
 
 @pytest.mark.parametrize("name,integ", [("c2", "ssprk3"), ("c4", "ssprk3"), ("c5", "ssprk3"), ("c1", "ssprk3"),
-                                        ("c2", "euler")])
+                                        ("c2", "euler"), ("c4", "ssprk54")])
 def test_cfl_from_last_stage_minmax_equals_wave_speed_pass(name, integ):
     """For convex |f'| the last stage of a step reduces the min / max average
     and the next step's CFL step comes from them; it must equal, to the bit,
