@@ -56,37 +56,50 @@ __global__ void __launch_bounds__(256) wavespeed_kernel(const InstDev *inst, con
 // max(|f_l'(min)|, |f_l'(max)|), evaluated in FP64 exactly as the wave-speed
 // kernel evaluates it per face, so the time step is the same to the bit.
 __global__ void __launch_bounds__(256) finalize_kernel(const InstDev *inst, const StepCtl *ctl, const double *dtp,
-                                                       InstState *st, int dim, const unsigned long long *mm,
-                                                       int waves_per_block)
+                                                      InstState *st, int dim, const unsigned long long *mm,
+                                                      int waves_per_block)
 {
     const int i = blockIdx.x;
     const InstDev &I = inst[i];
-    __shared__ unsigned long long klo[256], khi[256];
+    // what the first lane needs, requested before the reduction so that the
+    // load latencies overlap
+    const double te = ctl->t_end, dpre = dtp[i], t0 = st[i].t, cfl = I.cfl;
+    const int prescribed = ctl->prescribed;
     double w = __longlong_as_double((long long)st[i].wmax);
     double lo = 0.0, hi = 0.0;
     if (mm) {
+        // slot pairs of the instance: four independent loads in flight per
+        // thread, then a wave and a block reduction
+        __shared__ unsigned long long ka[4], kb[4];
         unsigned long long a = ~0ull, b = 0ull;
         const int n = I.wcount * waves_per_block;
-        const unsigned long long *m = mm + 2 * (long long)I.wstart * waves_per_block;
-        for (int k = threadIdx.x; k < n; k += blockDim.x) {
-            a = min(a, m[2 * k]);
-            b = max(b, m[2 * k + 1]);
-        }
-        klo[threadIdx.x] = a;
-        khi[threadIdx.x] = b;
-        __syncthreads();
-        for (int o = 128; o >= 1; o >>= 1) {
-            if ((int)threadIdx.x < o) {
-                klo[threadIdx.x] = min(klo[threadIdx.x], klo[threadIdx.x + o]);
-                khi[threadIdx.x] = max(khi[threadIdx.x], khi[threadIdx.x + o]);
+        const ulonglong2 *m = (const ulonglong2 *)(mm + 2 * (long long)I.wstart * waves_per_block);
+        for (int k0 = threadIdx.x; k0 < n; k0 += 4 * 256) {
+            ulonglong2 v[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) v[j] = k0 + 256 * j < n ? m[k0 + 256 * j] : make_ulonglong2(~0ull, 0ull);
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                a = min(a, v[j].x);
+                b = max(b, v[j].y);
             }
-            __syncthreads();
         }
-        lo = ordered_value(klo[0]);
-        hi = ordered_value(khi[0]);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            a = min(a, (unsigned long long)__shfl_xor((long long)a, o));
+            b = max(b, (unsigned long long)__shfl_xor((long long)b, o));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            ka[threadIdx.x >> 6] = a;
+            kb[threadIdx.x >> 6] = b;
+        }
+        __syncthreads();
+        a = min(min(ka[0], ka[1]), min(ka[2], ka[3]));
+        b = max(max(kb[0], kb[1]), max(kb[2], kb[3]));
+        lo = ordered_value(a);
+        hi = ordered_value(b);
     }
     if (threadIdx.x != 0) return;
-    const double te = ctl->t_end;
     if (mm) {
         const double big = 1e6 * fmax(fmax(fabs(I.umin), fabs(I.umax)), 1.0);
         if (!(fabs(lo) <= big && fabs(hi) <= big)) st[i].flags |= 1u;  // divergent or non-finite
@@ -96,26 +109,27 @@ __global__ void __launch_bounds__(256) finalize_kernel(const InstDev *inst, cons
         for (int l = 0; l < dim; l++) w = fmax(w, P.alpha_int(l, lo, hi) * I.idx1[l] + I.kmax * I.idx2[l]);
     }
     double dt;
-    if (ctl->prescribed) {
-        dt = dtp[i];
+    if (prescribed) {
+        dt = dpre;
     } else {
-        dt = w > 0.0 ? I.cfl / w : (te > 0.0 ? te - st[i].t : 0.0);
+        dt = w > 0.0 ? cfl / w : (te > 0.0 ? te - t0 : 0.0);
     }
     st[i].wmax = 0ull;
     if (te > 0.0) {
-        const double rem = te - st[i].t;
+        const double rem = te - t0;
         if (rem <= 1e-12 * te) dt = 0.0;  // remainder is rounding, not a step
         else if (dt > rem) dt = rem;
     }
     st[i].dt = dt;
-    st[i].t += dt;
+    st[i].t = t0 + dt;
     if (dt > 0.0) st[i].steps++;
     st[i].f_dt = (float)dt;
     for (int l = 0; l < 3; l++) {
-        st[i].mu[l] = dt * I.idx1[l];
-        st[i].nu[l] = dt * I.idx2[l];
-        st[i].f_mu[l] = (float)st[i].mu[l];
-        st[i].f_nu[l] = (float)st[i].nu[l];
+        const double mu = dt * I.idx1[l], nu = dt * I.idx2[l];
+        st[i].mu[l] = mu;
+        st[i].nu[l] = nu;
+        st[i].f_mu[l] = (float)mu;
+        st[i].f_nu[l] = (float)nu;
     }
 }
 

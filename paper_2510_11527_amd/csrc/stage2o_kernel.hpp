@@ -112,8 +112,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     const auto rin = __builtin_amdgcn_make_buffer_rsrc((void *)(p.in + Ic->off), 0, (int)blk, kBufWord3);
     const auto run = __builtin_amdgcn_make_buffer_rsrc((void *)(p.un + Ic->off), 0, (int)blk, kBufWord3);
     const auto rout = __builtin_amdgcn_make_buffer_rsrc((void *)(p.out + Ic->off), 0, (int)blk, kBufWord3);
-    // X1 of a kCombSum stage; otherwise an empty range (loads read 0 and
-    // touch no memory, which keeps the load sequence free of branches)
+    // X1 of a kCombSum stage (an empty range otherwise)
     const auto rx1 = __builtin_amdgcn_make_buffer_rsrc((void *)(p.x1 ? p.x1 + Ic->off : p.in + Ic->off), 0,
                                                        p.x1 ? (int)blk : 0, kBufWord3);
     auto ld = [&](const __amdgpu_buffer_rsrc_t &r, int z, unsigned gi) -> T {
@@ -249,19 +248,24 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         for (int z = 0; z < 4; z++) halo[k][z] = ld(rin, z, gi);
     }
     // X0 (U^n) and X1 of the own cells for the stage's combination (a stage
-    // that does not combine reads X0 too, from cache, and X1 from an empty
-    // range: the load sequence stays free of branches, so the waits above
-    // stay exact)
+    // that does not combine reads X0 too, from cache: the load sequence up to
+    // here stays free of branches, so the waits above stay exact; X1, needed
+    // by summing stages only, comes last)
     T unv[2][4], x1v[2][4];
 #pragma unroll
     for (int z = 0; z < 4; z++) {
         unv[0][z] = ld(run, z, g0);
         unv[1][z] = ld(run, z, g1);
     }
+    if (p.x1) {
 #pragma unroll
-    for (int z = 0; z < 4; z++) {
-        x1v[0][z] = ld(rx1, z, g0);
-        x1v[1][z] = ld(rx1, z, g1);
+        for (int z = 0; z < 4; z++) {
+            x1v[0][z] = ld(rx1, z, g0);
+            x1v[1][z] = ld(rx1, z, g1);
+        }
+    } else {
+#pragma unroll
+        for (int z = 0; z < 4; z++) x1v[0][z] = x1v[1][z] = T(0);
     }
     auto put_cell = [&](int xx, int yy, const T *u) {
         cg[cgi(xx, yy)] = V2<T>{u[0], pot(u[0])};
