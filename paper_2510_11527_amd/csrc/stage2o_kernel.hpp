@@ -9,20 +9,23 @@
 //   * each thread owns a vertical pair of cells and does every per-cell item
 //     of them itself -- loads, centres, the six point values, the two x- and
 //     two y-faces to their right/top, the four cell-centred potentials and the
-//     two average updates -- with all LDS addresses fixed offsets of one base;
+//     two average updates;
 //   * the items of the halo (cells, centres, faces and potentials outside the
 //     tile that the tile's items read) are short wave-aligned extra passes;
+//   * every LDS array shares one row stride, so each item (own or halo)
+//     reaches all its operands at constant offsets of one cell index;
 //   * the half grid is split by parity into four cell-indexed sub-grids of
 //     {u, a(u)}: centres C (x_i, y_j), x-faces X (x_{i+1/2}, y_j), y-faces
 //     Y (x_i, y_{j+1/2}) and corners K (x_{i+1/2}, y_{j+1/2}); every 5-point
 //     half-grid stencil alternates between two of them;
 //   * f is recomputed from u (two instructions) instead of stored, which keeps
-//     the LDS footprint at three workgroups per CU;
+//     the LDS footprint at four workgroups per CU;
 //   * the polynomial potentials without clamps (linear, u^2, u^3) take a
 //     three-instruction path (flag kOwnPP);
 //   * for pure quadratic fluxes f_l = c2 u^2 (flag kOwnBQ) the point-value
 //     stencil works on u^2 and max|u|: |f_l'| = 2|c2| |u|, and the constant
-//     c2 moves into the per-direction scale;
+//     c2 moves into the per-direction scale; the LLF face states use the
+//     factored differences f(a) - f^L and f^L - f(b);
 //   * the scales 1/(6 dx), 1/dx^2 and dt are folded into one multiply-add
 //     per term of the point-value update;
 //   * global memory is addressed with 32-bit byte offsets from per-DoF-kind
@@ -56,15 +59,26 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
 // kernel variant flags
 enum : int { kOwnPP = 1, kOwnBQ = 2 };
 
-// Layout of the face and potential arrays: x-faces (TX + 3 per tile row) and
-// x-potentials (TX + 2) row by row; y-faces (TY + 3 rows) and y-potentials
-// (TY + 2 rows) row by row with TX entries.
+// LDS geometry.  Every array is indexed by the same cell index b = xx + SX yy
+// of the tile region (RX x RY cells: the tile and a halo of 2), so that all
+// accesses of one work item are constant offsets of one base:
+//   * five {u, a} grids of RX x RY cells (row stride SX = RX + 1): the cells
+//     {ubar, a(ubar)}, then the half-grid sub-grids C, X, Y, K;
+//   * face values: x-face (xx, yy) (between cells (xx, yy) and (xx+1, yy);
+//     xx in [0, TX+2], yy in [2, TY+2)) at b - 2 SX; y-face (xx, yy) (between
+//     (xx, yy) and (xx, yy+1); xx in [2, TX+2), yy in [0, TY+2]) at
+//     NXF + b - 2;
+//   * potentials: x (xx in [1, TX+2], yy in [2, TY+2)) at b - 1 - 2 SX, y (xx
+//     in [2, TX+2), yy in [1, TY+2]) at NXC + b - 2 - SX.
 template <int TX, int TY>
 struct Own2Geo {
-    static constexpr int FXS = TX + 3, CXS = TX + 2;
-    static constexpr int NXF = FXS * TY, NYF = TX * (TY + 3), NF = NXF + NYF;
-    static constexpr int NXC = CXS * TY, NYC = TX * (TY + 2), NC = NXC + NYC;
-    __device__ static __forceinline__ int yslot(int r) { return r; }
+    static constexpr int RX = TX + 4, RY = TY + 4, SX = RX + 1, SG = SX * RY;
+    static constexpr int NXF = (TY - 1) * SX + TX + 3, NYF = (TY + 2) * SX + TX, NF = NXF + NYF;
+    static constexpr int NXC = (TY - 1) * SX + TX + 2, NYC = (TY + 1) * SX + TX, NC = NXC + NYC;
+    __device__ static __forceinline__ int fx(int b) { return b - 2 * SX; }
+    __device__ static __forceinline__ int fy(int b) { return NXF + b - 2; }
+    __device__ static __forceinline__ int px(int b) { return b - 1 - 2 * SX; }
+    __device__ static __forceinline__ int py(int b) { return NXC + b - 2 - SX; }
 };
 
 template <class T, bool LIM, int FL, int TX, int TY, int NT>
@@ -73,20 +87,19 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     constexpr bool PP = (FL & kOwnPP) != 0, BQ = (FL & kOwnBQ) != 0;
     static_assert(TX * TY == 2 * NT && TY % 2 == 0, "two cells per thread");
     static_assert(NT % TX == 0 && NT % 64 == 0, "threads cover whole columns and waves");
-    constexpr int RX = TX + 4, RY = TY + 4;     // tile + halo 2
-    constexpr int SX = RX + 1, SG = SX * RY;    // sub-grid row stride (padded) and size
     using FG = Own2Geo<TX, TY>;
-    constexpr int NXF = FG::NXF, NXC = FG::NXC;
-    constexpr int SC = 0, SXF = 1, SYF = 2, SK = 3;  // sub-grids
+    constexpr int RX = FG::RX, SX = FG::SX, SG = FG::SG;
+    constexpr int SC = 1, SXF = 2, SYF = 3, SK = 4;  // grids 1..4: the half-grid sub-grids
 
-    __shared__ V2<T> hs[4 * SG];                // {u, a} of the four sub-grids
-    __shared__ V2<T> cg[RX * RY];               // {ubar, a(ubar)} of the cells
-    // Face and potential arrays.  With the limiter, u^{L,+} (of the left cell
-    // of a face) and u^{L,-} (of the right cell) live there until the
-    // potentials have read them; the flux and the potential used in the
-    // update are kept in registers until then and take their place.
+    // One LDS block: the five {u, a} grids (grid 0: the cells), then the face
+    // and potential arrays.  With the limiter, u^{L,+} (of the left cell of a
+    // face) and u^{L,-} (of the right cell) live there until the potentials
+    // have read them; the flux and the potential used in the update are kept
+    // in registers until then and take their place.
     static_assert(FG::NC <= FG::NF, "potentials fit in a face array");
-    __shared__ T fbuf[LIM ? 2 * FG::NF : FG::NF + FG::NC];
+    constexpr int NFB = LIM ? 2 * FG::NF : FG::NF + FG::NC;
+    __shared__ V2<T> smem[5 * SG + (NFB + 1) / 2];
+    T *const fbuf = (T *)(smem + 5 * SG);
     T *const ulp = fbuf, *const ulm = fbuf + FG::NF;
     T *const fl = fbuf, *const pc = fbuf + FG::NF;
 
@@ -172,8 +185,20 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         c2[l] = Ic->fk[l] == kFQuad ? c : T(0);
         c2x2[l] = T(2) * c2[l];
     }
+    // pure quadratic fluxes: |c2|, c2 / 2 and c2 / 6 for the faces
+    T cabs[2], chalf[2], csix[2];
+#pragma unroll
+    for (int l = 0; l < 2; l++) {
+        cabs[l] = fabs(c2[l]);
+        chalf[l] = T(0.5) * c2[l];
+        csix[l] = c2[l] * T(1.0 / 6.0);
+    }
     const T dt = prm(dtd, Sc->f_dt) * p.dts;
     const T umin = prm(Ic->umin, Ic->f_umin), umax = prm(Ic->umax, Ic->f_umax);
+    // umax once in a vector register for the FP32 clamps: a median of three
+    // reads at most one scalar register, so umin (scalar) and umax (vector)
+    T umaxv = umax;
+    if constexpr (sizeof(T) == 4) asm volatile("" : "+v"(umaxv));
     const T pc1 = prm(Ic->pc1, Ic->f_pc[0]), pc2 = prm(Ic->pc2, Ic->f_pc[1]), pc3 = prm(Ic->pc3, Ic->f_pc[2]);
     T idx1[2], idx2[2], i6dx[2], mu[2], nu[2];
 #pragma unroll
@@ -199,17 +224,11 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     };
     auto fq = [&](int l, T u) -> T { return u * (c1[l] + c2[l] * u); };
     auto gq = [&](int l, T u) -> T { return fabs(c1[l] + c2x2[l] * u); };
-    auto sg = [&](int s, int xx, int yy) -> int { return s * SG + xx + SX * yy; };
-    auto S = [&](int s, int xx, int yy) -> V2<T> { return hs[sg(s, xx, yy)]; };
-    auto Su = [&](int s, int xx, int yy) -> T { return hs[sg(s, xx, yy)].x; };
-    auto Sa = [&](int s, int xx, int yy) -> T { return hs[sg(s, xx, yy)].y; };
-    auto cgi = [&](int xx, int yy) -> int { return xx + RX * yy; };
-    // face and potential slots: x-face between cells (xx, yy) and (xx+1, yy);
-    // y-face between (xx, yy) and (xx, yy+1); potentials of cell (xx, yy)
-    auto fxi = [&](int xx, int yy) -> int { return xx + FG::FXS * (yy - 2); };
-    auto fyi = [&](int xx, int yy) -> int { return NXF + (xx - 2) + TX * FG::yslot(yy); };
-    auto pxi = [&](int xx, int yy) -> int { return (xx - 1) + FG::CXS * (yy - 2); };
-    auto pyi = [&](int xx, int yy) -> int { return NXC + (xx - 2) + TX * FG::yslot(yy - 1); };
+    // grid s at cell index b (the neighbours of b are b +- 1 and b +- SX)
+    auto S = [&](int s, int b) -> V2<T> { return smem[s * SG + b]; };
+    auto Su = [&](int s, int b) -> T { return smem[s * SG + b].x; };
+    auto Sa = [&](int s, int b) -> T { return smem[s * SG + b].y; };
+    auto bix = [](int xx, int yy) -> int { return xx + SX * yy; };
 
     // ---- A: cells of the tile and its halo -> LDS with their potentials.
     // Loads are issued in the order they are consumed (own cells, halo cells,
@@ -218,7 +237,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     constexpr int NHR = 4 * RX, NH = NHR + 4 * TY;   // halo: 4 rows, then 4 columns
     constexpr int NHI = (NH + NT - 1) / NT;          // halo cells per thread
     T own[2][4], halo[NHI][4];
-    int hx[NHI], hy[NHI];
+    int hb[NHI];
 #pragma unroll
     for (int z = 0; z < 4; z++) {
         own[0][z] = ld(rin, z, g0);
@@ -241,8 +260,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
             yy = 2 + (h2 >> 2);
             xx = q < 2 ? q : q + TX;
         }
-        hx[k] = xx;
-        hy[k] = yy;
+        hb[k] = bix(xx, yy);
         const unsigned gi = (unsigned)(wrap(ox + xx - 2, n0, fold0) + n0 * wrap(oy + yy - 2, n1, fold1));
 #pragma unroll
         for (int z = 0; z < 4; z++) halo[k][z] = ld(rin, z, gi);
@@ -267,27 +285,28 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
 #pragma unroll
         for (int z = 0; z < 4; z++) x1v[0][z] = x1v[1][z] = T(0);
     }
-    auto put_cell = [&](int xx, int yy, const T *u) {
-        cg[cgi(xx, yy)] = V2<T>{u[0], pot(u[0])};
-        hs[sg(SXF, xx, yy)] = V2<T>{u[1], pot(u[1])};
-        hs[sg(SYF, xx, yy)] = V2<T>{u[2], pot(u[2])};
-        hs[sg(SK, xx, yy)] = V2<T>{u[3], pot(u[3])};
+    auto put_cell = [&](int b, const T *u) {
+        smem[b] = V2<T>{u[0], pot(u[0])};
+        smem[SXF * SG + b] = V2<T>{u[1], pot(u[1])};
+        smem[SYF * SG + b] = V2<T>{u[2], pot(u[2])};
+        smem[SK * SG + b] = V2<T>{u[3], pot(u[3])};
     };
-    put_cell(x, y, own[0]);
-    put_cell(x, y + 1, own[1]);
+    const int b0 = bix(x, y), b1 = b0 + SX;  // the own cells
+    put_cell(b0, own[0]);
+    put_cell(b1, own[1]);
 #pragma unroll
-    for (int k = 0; k < NHI; k++) put_cell(hx[k], hy[k], halo[k]);
+    for (int k = 0; k < NHI; k++) put_cell(hb[k], halo[k]);
     __syncthreads();
 
     // ---- B: cell centres by inverting the tensor Simpson rule
-    auto centre = [&](int xx, int yy) {
-        const T faces = Su(SXF, xx - 1, yy) + Su(SXF, xx, yy) + Su(SYF, xx, yy - 1) + Su(SYF, xx, yy);
-        const T corners = Su(SK, xx - 1, yy - 1) + Su(SK, xx, yy - 1) + Su(SK, xx - 1, yy) + Su(SK, xx, yy);
-        const T u = (T(36) * cg[cgi(xx, yy)].x - T(4) * faces - corners) * T(0.0625);
-        hs[sg(SC, xx, yy)] = V2<T>{u, pot(u)};
+    auto centre = [&](int b) {
+        const T faces = Su(SXF, b - 1) + Su(SXF, b) + Su(SYF, b - SX) + Su(SYF, b);
+        const T corners = Su(SK, b - 1 - SX) + Su(SK, b - SX) + Su(SK, b - 1) + Su(SK, b);
+        const T u = (T(36) * Su(0, b) - T(4) * faces - corners) * T(0.0625);
+        smem[SC * SG + b] = V2<T>{u, pot(u)};
     };
-    centre(x, y);
-    centre(x, y + 1);
+    centre(b0);
+    centre(b1);
     {
         // halo centres: rows 1 and TY+2 over columns [1, TX+3), columns 1
         // and TX+2 over rows [2, TY+2)
@@ -303,7 +322,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
                 yy = 2 + (h2 >> 1);
                 xx = (h2 & 1) ? TX + 2 : 1;
             }
-            centre(xx, yy);
+            centre(bix(xx, yy));
         }
     }
     __syncthreads();
@@ -346,20 +365,20 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         T R[2][3];  // per own cell: x-face, y-face, corner point value (or du/dt)
 #pragma unroll
         for (int c = 0; c < 2; c++) {
-            const int yy = y + c;
+            const int b = c == 0 ? b0 : b1;
             const bool z0 = residual;
-            // x-face point (x+1/2, yy)
-            T r = z0 ? T(0) : Su(SXF, x, yy);
-            r = pv_dir(0, S(SXF, x - 1, yy), S(SC, x, yy), S(SXF, x, yy), S(SC, x + 1, yy), S(SXF, x + 1, yy), r);
-            R[c][0] = pv_dir(1, S(SXF, x, yy - 1), S(SK, x, yy - 1), S(SXF, x, yy), S(SK, x, yy), S(SXF, x, yy + 1), r);
-            // y-face point (x, yy+1/2)
-            r = z0 ? T(0) : Su(SYF, x, yy);
-            r = pv_dir(0, S(SYF, x - 1, yy), S(SK, x - 1, yy), S(SYF, x, yy), S(SK, x, yy), S(SYF, x + 1, yy), r);
-            R[c][1] = pv_dir(1, S(SYF, x, yy - 1), S(SC, x, yy), S(SYF, x, yy), S(SC, x, yy + 1), S(SYF, x, yy + 1), r);
-            // corner point (x+1/2, yy+1/2)
-            r = z0 ? T(0) : Su(SK, x, yy);
-            r = pv_dir(0, S(SK, x - 1, yy), S(SYF, x, yy), S(SK, x, yy), S(SYF, x + 1, yy), S(SK, x + 1, yy), r);
-            R[c][2] = pv_dir(1, S(SK, x, yy - 1), S(SXF, x, yy), S(SK, x, yy), S(SXF, x, yy + 1), S(SK, x, yy + 1), r);
+            // x-face point (x+1/2, y)
+            T r = z0 ? T(0) : Su(SXF, b);
+            r = pv_dir(0, S(SXF, b - 1), S(SC, b), S(SXF, b), S(SC, b + 1), S(SXF, b + 1), r);
+            R[c][0] = pv_dir(1, S(SXF, b - SX), S(SK, b - SX), S(SXF, b), S(SK, b), S(SXF, b + SX), r);
+            // y-face point (x, y+1/2)
+            r = z0 ? T(0) : Su(SYF, b);
+            r = pv_dir(0, S(SYF, b - 1), S(SK, b - 1), S(SYF, b), S(SK, b), S(SYF, b + 1), r);
+            R[c][1] = pv_dir(1, S(SYF, b - SX), S(SC, b), S(SYF, b), S(SC, b + SX), S(SYF, b + SX), r);
+            // corner point (x+1/2, y+1/2)
+            r = z0 ? T(0) : Su(SK, b);
+            r = pv_dir(0, S(SK, b - 1), S(SYF, b), S(SK, b), S(SYF, b + 1), S(SK, b + 1), r);
+            R[c][2] = pv_dir(1, S(SK, b - SX), S(SXF, b), S(SK, b), S(SXF, b + SX), S(SK, b + SX), r);
         }
 #pragma unroll
         for (int c = 0; c < 2; c++) {
@@ -374,9 +393,9 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
                 }
                 T v = R[c][z - 1];
                 if (!isfinite(v)) bad = true;
-                if constexpr (LIM) v = clampb(v, umin, umax);
-                v = stage_combine(p, v, unv[c][z], x1v[c][z], Su(z == 1 ? SXF : (z == 2 ? SYF : SK), x, y + c));
-                if constexpr (LIM) v = clampb(v, umin, umax);
+                if constexpr (LIM) v = clampb(v, umin, umaxv);
+                v = stage_combine(p, v, unv[c][z], x1v[c][z], Su(z == 1 ? SXF : (z == 2 ? SYF : SK), c == 0 ? b0 : b1));
+                if constexpr (LIM) v = clampb(v, umin, umaxv);
                 st(z, gi, v);
             }
         }
@@ -389,32 +408,47 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         T v;
         int id;
     };
-    auto face = [&](int l, int xx, int yy, bool hi) -> Item {
-        const V2<T> A = cg[cgi(xx, yy)];
-        const V2<T> B = l == 0 ? cg[cgi(xx + 1, yy)] : cg[cgi(xx, yy + 1)];
-        const int id = l == 0 ? fxi(xx, yy) : fyi(xx, yy);
-        const T fa = fq(l, A.x), fb = fq(l, B.x);
-        T fL = T(0), up = T(0), um = T(0);
+    auto face = [&](int l, int b, bool hi) -> Item {
+        const V2<T> A = S(0, b);
+        const V2<T> B = S(0, l == 0 ? b + 1 : b + SX);
+        const int id = l == 0 ? FG::fx(b) : FG::fy(b);
+        T fL = T(0), up = T(0), um = T(0), D = T(0), gmh = T(0);
         if constexpr (LIM) {
-            const T al = fmax(gq(l, A.x), gq(l, B.x));
-            fL = T(0.5) * (fa + fb) - T(0.5) * al * (B.x - A.x);
             const T Km = kmu[l];
             const T dA = (B.y - A.y) * idx1[l];
-            up = A.x + Km * (dA - fL + fa);
-            um = B.x + Km * (fL - fb - dA);
+            if constexpr (BQ) {
+                // f_l = c2 u^2: with D = b - a, g = |c2| max(|a|, |b|) (half the
+                // LLF speed) and h = c2 (a + b) / 2, f(a) - f^L = D (g - h) and
+                // f^L - f(b) = -D (g + h)
+                D = B.x - A.x;
+                const T g = cabs[l] * vmax(T(fabs(A.x)), T(fabs(B.x))), s2 = A.x + B.x;
+                gmh = g - chalf[l] * s2;
+                const T gph = g + chalf[l] * s2;
+                up = A.x + Km * (dA + D * gmh);
+                um = B.x - Km * (dA + D * gph);
+            } else {
+                const T fa = fq(l, A.x), fb = fq(l, B.x);
+                const T al = fmax(gq(l, A.x), gq(l, B.x));
+                fL = T(0.5) * (fa + fb) - T(0.5) * al * (B.x - A.x);
+                up = A.x + Km * (dA - fL + fa);
+                um = B.x + Km * (fL - fb - dA);
+            }
             ulp[id] = up;
             ulm[id] = um;
         }
         if (!hi) return Item{T(0), -1};
         // Simpson average of f_l over the three points of the face
         T fH;
-        if (l == 0)
-            fH = (fq(0, Su(SK, xx, yy - 1)) + T(4) * fq(0, Su(SXF, xx, yy)) + fq(0, Su(SK, xx, yy))) * T(1.0 / 6.0);
-        else
-            fH = (fq(1, Su(SK, xx - 1, yy)) + T(4) * fq(1, Su(SYF, xx, yy)) + fq(1, Su(SK, xx, yy))) * T(1.0 / 6.0);
+        {
+            const T k1 = l == 0 ? Su(SK, b - SX) : Su(SK, b - 1), k2 = Su(SK, b);
+            const T m = l == 0 ? Su(SXF, b) : Su(SYF, b);
+            if constexpr (BQ) fH = csix[l] * ((k1 * k1 + k2 * k2) + T(4) * (m * m));
+            else fH = (fq(l, k1) + T(4) * fq(l, m) + fq(l, k2)) * T(1.0 / 6.0);
+        }
         T F = fH;
         if constexpr (LIM) {
             if (!residual) {
+                if constexpr (BQ) fL = c2[l] * (A.x * A.x) - D * gmh;
                 const T df = fH - fL;
                 const T s3 = k3mu[l] * df;
                 // up moves by -s3, um by +s3
@@ -425,7 +459,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         if constexpr (!LIM) fl[id] = F;
         return Item{F, id};
     };
-    Item fo[4] = {face(0, x, y, true), face(0, x, y + 1, true), face(1, x, y, true), face(1, x, y + 1, true)};
+    Item fo[4] = {face(0, b0, true), face(0, b1, true), face(1, b0, true), face(1, b1, true)};
     // halo faces: x-faces at columns 0, 1 (HI), TX+2 over the tile rows;
     // y-faces at rows 0, 1 (HI), TY+2 over the tile columns (from the next
     // wave boundary on, so no wave mixes the two)
@@ -437,33 +471,33 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         fh[k] = Item{T(0), -1};
         if (h < NXHF) {
             const int q = h / TY;
-            fh[k] = face(0, q < 2 ? q : TX + 2, 2 + h - q * TY, q == 1);
+            fh[k] = face(0, bix(q < 2 ? q : TX + 2, 2 + h - q * TY), q == 1);
         } else if (h >= Y0F && h < NHF) {
             const int h2 = h - Y0F, q = h2 / TX;
-            fh[k] = face(1, 2 + h2 - q * TX, q < 2 ? q : TY + 2, q == 1);
+            fh[k] = face(1, bix(2 + h2 - q * TX, q < 2 ? q : TY + 2), q == 1);
         }
     }
     __syncthreads();
 
     // ---- D2: cell-centred potentials a^H of Prop. 2.1 and their limited blend
-    auto potential = [&](int l, int xx, int yy) -> Item {
-        const T corners = Sa(SK, xx - 1, yy - 1) + Sa(SK, xx, yy - 1) + Sa(SK, xx - 1, yy) + Sa(SK, xx, yy);
+    auto potential = [&](int l, int b) -> Item {
+        const T corners = Sa(SK, b - 1 - SX) + Sa(SK, b - SX) + Sa(SK, b - 1) + Sa(SK, b);
         T aH;
         if (l == 0)
-            aH = (T(8) * (Sa(SYF, xx, yy - 1) + Sa(SYF, xx, yy)) + T(32) * Sa(SC, xx, yy) - corners -
-                  T(4) * (Sa(SXF, xx - 1, yy) + Sa(SXF, xx, yy))) *
+            aH = (T(8) * (Sa(SYF, b - SX) + Sa(SYF, b)) + T(32) * Sa(SC, b) - corners -
+                  T(4) * (Sa(SXF, b - 1) + Sa(SXF, b))) *
                  T(1.0 / 36.0);
         else
-            aH = (T(8) * (Sa(SXF, xx - 1, yy) + Sa(SXF, xx, yy)) + T(32) * Sa(SC, xx, yy) - corners -
-                  T(4) * (Sa(SYF, xx, yy - 1) + Sa(SYF, xx, yy))) *
+            aH = (T(8) * (Sa(SXF, b - 1) + Sa(SXF, b)) + T(32) * Sa(SC, b) - corners -
+                  T(4) * (Sa(SYF, b - SX) + Sa(SYF, b))) *
                  T(1.0 / 36.0);
         T Pv = aH;
         if constexpr (LIM) {
             if (!residual) {
-                const T aL = cg[cgi(xx, yy)].y;
+                const T aL = Sa(0, b);
                 // faces c-1/2 (f0) and c+1/2 (f1) of the cell
-                const int f0 = l == 0 ? fxi(xx - 1, yy) : fyi(xx, yy - 1);
-                const int f1 = l == 0 ? fxi(xx, yy) : fyi(xx, yy);
+                const int f0 = l == 0 ? FG::fx(b - 1) : FG::fy(b - SX);
+                const int f1 = l == 0 ? FG::fx(b) : FG::fy(b);
                 const T pL = ulp[f0], mC = ulm[f0], pC = ulp[f1], mR = ulm[f1];
                 const T da = aH - aL;
                 const T s = k3nu[l] * da;
@@ -472,11 +506,11 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
                 Pv = aL + theta_from_gap<T>(gap, (T)fabs(s)) * da;
             }
         }
-        const int id = l == 0 ? pxi(xx, yy) : pyi(xx, yy);
+        const int id = l == 0 ? FG::px(b) : FG::py(b);
         if constexpr (!LIM) pc[id] = Pv;
         return Item{Pv, id};
     };
-    Item po[4] = {potential(0, x, y), potential(0, x, y + 1), potential(1, x, y), potential(1, x, y + 1)};
+    Item po[4] = {potential(0, b0), potential(0, b1), potential(1, b0), potential(1, b1)};
     // halo potentials: x at columns 1, TX+2; y at rows 1, TY+2
     constexpr int NXHP = 2 * TY, Y0P = (NXHP + 63) / 64 * 64, NHP = Y0P + 2 * TX, NHPI = (NHP + NT - 1) / NT;
     Item ph[NHPI];
@@ -486,10 +520,10 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         ph[k] = Item{T(0), -1};
         if (h < NXHP) {
             const int q = h / TY;
-            ph[k] = potential(0, q ? TX + 2 : 1, 2 + h - q * TY);
+            ph[k] = potential(0, bix(q ? TX + 2 : 1, 2 + h - q * TY));
         } else if (h >= Y0P && h < NHP) {
             const int h2 = h - Y0P, q = h2 / TX;
-            ph[k] = potential(1, 2 + h2 - q * TX, q ? TY + 2 : 1);
+            ph[k] = potential(1, bix(2 + h2 - q * TX, q ? TY + 2 : 1));
         }
     }
     if constexpr (LIM) {
@@ -516,26 +550,26 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         const bool own = c == 0 ? own0 : own1;
         if (!own) continue;
         const unsigned gi = c == 0 ? g0 : g1;
-        const int yy = y + c;
-        const T dFx = fl[fxi(x, yy)] - fl[fxi(x - 1, yy)];
-        const T dFy = fl[fyi(x, yy)] - fl[fyi(x, yy - 1)];
-        const T dPx = pc[pxi(x + 1, yy)] - T(2) * pc[pxi(x, yy)] + pc[pxi(x - 1, yy)];
-        const T dPy = pc[pyi(x, yy + 1)] - T(2) * pc[pyi(x, yy)] + pc[pyi(x, yy - 1)];
+        const int b = c == 0 ? b0 : b1;
+        const T dFx = fl[FG::fx(b)] - fl[FG::fx(b - 1)];
+        const T dFy = fl[FG::fy(b)] - fl[FG::fy(b - SX)];
+        const T dPx = pc[FG::px(b + 1)] - T(2) * pc[FG::px(b)] + pc[FG::px(b - 1)];
+        const T dPy = pc[FG::py(b + SX)] - T(2) * pc[FG::py(b)] + pc[FG::py(b - SX)];
         if (residual) {
             st(0, gi, (dPx * idx2[0] + dPy * idx2[1]) - (dFx * idx1[0] + dFy * idx1[1]));
             continue;
         }
-        const T u = cg[cgi(x, yy)].x;
+        const T u = Su(0, b);
         T v = u - (mu[0] * dFx + mu[1] * dFy) + (nu[0] * dPx + nu[1] * dPy);
         if (!isfinite(v)) bad = true;
         if constexpr (LIM) {
-            const T cl = clampb(v, umin, umax);
+            const T cl = clampb(v, umin, umaxv);
             clamp_mag = fmax(clamp_mag, (T)fabs(cl - v));
             v = cl;
         }
         v = stage_combine(p, v, unv[c][0], x1v[c][0], u);
         if constexpr (LIM) {
-            const T cl = clampb(v, umin, umax);
+            const T cl = clampb(v, umin, umaxv);
             clamp_mag = fmax(clamp_mag, (T)fabs(cl - v));
             v = cl;
         }
@@ -553,9 +587,9 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
 template <class T, bool LIM, int TX, int TY>
 constexpr long stage2o_lds_bytes()
 {
-    constexpr long RX = TX + 4, RY = TY + 4;
     using FG = Own2Geo<TX, TY>;
-    return (long)sizeof(T) * (8 * (RX + 1) * RY + 2 * RX * RY + (LIM ? 2L * FG::NF : (long)FG::NF + FG::NC));
+    constexpr long NFB = LIM ? 2L * FG::NF : (long)FG::NF + FG::NC;
+    return (long)sizeof(T) * (10L * FG::SG + 2 * ((NFB + 1) / 2));
 }
 
 }  // namespace af4
