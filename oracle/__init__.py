@@ -15,7 +15,8 @@ A problem is described by a plain dict (see
      "flux": [("quad", 0.5), ("quad", 0.5)],      # per axis: kind, params
      "diff": ("deadzone", eps, u0),                  # kind, params
      "umin": 0.0, "umax": 1.0, "limiter": True,
-     "si": False, "si_gamma": 1.0, "cfl": 0.075}
+     "si": False, "si_gamma": 1.0, "cfl": 0.075,
+     "diffusion_form": "dc"}                         # or "nodc" (App. A, 1D)
 
 DoFs are a list of 2^d numpy float64 arrays in the zeta order of Sec. 4
 (average first), each of prod(n) values with x fastest.
@@ -51,6 +52,7 @@ class OrcProblem(ctypes.Structure):
         ("si", ctypes.c_int),
         ("si_gamma", ctypes.c_double),
         ("theta_mode", ctypes.c_int),
+        ("nodc", ctypes.c_int),
         ("dx", ctypes.c_double * 3),
         ("kappa_max", ctypes.c_double),
         ("ncrit", ctypes.c_int * 3),
@@ -151,6 +153,7 @@ def problem(spec, theta_mode="computed"):
     P.si = int(bool(spec.get("si", False)))
     P.si_gamma = float(spec.get("si_gamma", 1.0))
     P.theta_mode = THETA_MODES[theta_mode]
+    P.nodc = int(spec.get("diffusion_form", "dc") == "nodc")
     if lib().orc_setup(ctypes.byref(P)) != 0:
         raise ValueError("oracle: invalid problem")
     return P

@@ -18,6 +18,11 @@
  * state; the point is that a reader can check each function against the
  * paper by eye.  It is deliberately slow.
  *
+ * With nodc set (1D only) the diffusion follows the variant of App. A without
+ * double conservation: kappa(u) D_c(u) face fluxes in the average, the
+ * compact B-matrix operator in the point value; its limiting is a reading
+ * (see F_nodc_lim).
+ *
  * Half-grid reading (used by the paper's "half-index shifts", Sec. 4): along
  * axis l, the points x_{i-1/2}, x_i, x_{i+1/2}, x_{i+1}, ... form a uniform
  * grid of spacing dx_l/2.  A half-grid point has integer coordinates p; an
@@ -63,6 +68,7 @@ typedef struct {
     int si;           /* smoothness-indicator blending */
     double si_gamma;
     int theta_mode;   /* ORC_THETA_*: computed, forced to 1, forced to 0 */
+    int nodc;         /* 1: the variant of App. A without double conservation (1D) */
     /* derived (filled by orc_setup) */
     double dx[3];
     double kappa_max;
@@ -222,6 +228,7 @@ static int find_crit(const orc_problem *P, int l, double a, double b, double *ou
 int orc_setup(orc_problem *P)
 {
     if (P->dim < 1 || P->dim > 3) return -1;
+    if (P->nodc && (P->dim != 1 || P->si)) return -1;  /* App. A is a 1D scheme */
     for (int l = 0; l < 3; l++) {
         if (l >= P->dim) { P->n[l] = 1; P->dx[l] = 1; P->ncrit[l] = 0; continue; }
         if (P->n[l] < 4) return -1;
@@ -340,6 +347,34 @@ static double llf(const orc_problem *P, int l, double a, double b, double alpha)
     return 0.5 * (flux(P, l, a) + flux(P, l, b)) - 0.5 * alpha * (b - a);
 }
 
+/* App. A: the compact fourth-order operator for (kappa(u) u_x)_x at a point
+ * value (Eq. 1d_diff_compact_kappa_u),
+ *   (4/dx^2) sum_{m,n=-2..2} b_mn kappa(z_m) z_n,
+ * on the 5-point half-grid line z_{-2..2} = u_{i-1/2}, u_i, u_{i+1/2},
+ * u_{i+1}, u_{i+3/2}, where the 5x5 matrix B is the 4x4 matrix M printed
+ * there placed in the lower-right corner minus M placed in the upper-left
+ * corner. */
+static const double M_nodc[4][4] = {
+    {1.0 / 8, -1.0 / 6, 1.0 / 24, 0.0},
+    {-1.0 / 6, -3.0 / 8, 2.0 / 3, -1.0 / 8},
+    {1.0 / 8, -2.0 / 3, 3.0 / 8, 1.0 / 6},
+    {0.0, -1.0 / 24, 1.0 / 6, -1.0 / 8},
+};
+static double b_nodc(int m, int n)  /* m, n in 0..4 for -2..2 */
+{
+    double b = 0;
+    if (m >= 1 && n >= 1) b += M_nodc[m - 1][n - 1];
+    if (m <= 3 && n <= 3) b -= M_nodc[m][n];
+    return b;
+}
+static double dtilde2(const orc_problem *P, const double z[5], double dx)
+{
+    double s = 0;
+    for (int m = 0; m < 5; m++)
+        for (int n = 0; n < 5; n++) s += b_nodc(m, n) * kappa(P, z[m]) * z[n];
+    return 4 * s / (dx * dx);
+}
+
 /* contribution of direction l to du/dt at the point value p:
  *   -( D+^{4th} f^+ + D-^{4th} f^- ) + D^{2,4th} a(u)
  * with D+ (Eq. 1d_upwind_ops_4p), D- (Eq. 1d_upwind_ops_4m), the local LF
@@ -367,7 +402,8 @@ static double pv_rhs_dir(const orc_problem *P, const double *const *U, const int
     double dx = P->dx[l];
     double Dp = (fp[0] - 6 * fp[1] + 3 * fp[2] + 2 * fp[3]) / (3 * dx);
     double Dm = (-2 * fm[1] - 3 * fm[2] + 6 * fm[3] - fm[4]) / (3 * dx);
-    double D2 = (-a[0] / 3 + 16 * a[1] / 3 - 10 * a[2] + 16 * a[3] / 3 - a[4] / 3) / (dx * dx);
+    double D2 = P->nodc ? dtilde2(P, z, dx)
+                        : (-a[0] / 3 + 16 * a[1] / 3 - 10 * a[2] + 16 * a[3] / 3 - a[4] / 3) / (dx * dx);
     double conv = -(Dp + Dm);
     if (P->si) {
         /* low-order LLF right-hand side: neighbours at +-dx/2, a cell
@@ -533,6 +569,24 @@ static double ahat_L_face(const orc_problem *P, const double *const *U, int l, c
     return (pot(P, avg(P, U, cp)) - pot(P, avg(P, U, c))) / P->dx[l];
 }
 
+/* App. A: the diffusion flux at the face c + e_l/2 of the variant without
+ * double conservation (Eqs. 1d_diff_nodc_av_u, 1d_diff_nodc_pnt_p):
+ * kappa(u_{i+1/2}) times the central difference D_c^{4th}(u)_{i+1/2}
+ * (Eq. 1d_diff_central_4th) on the 5-point half-grid line around the face */
+static double g_nodc(const orc_problem *P, const double *const *U, int l, const int c[3])
+{
+    int p[3] = {2 * c[0], 2 * c[1], 2 * c[2]};
+    p[l] += 1;
+    double z[5];
+    for (int m = -2; m <= 2; m++) {
+        int q[3] = {p[0], p[1], p[2]};
+        q[l] += m;
+        z[m + 2] = H(P, U, q);
+    }
+    double Dc = (z[0] - 8 * z[1] + 8 * z[3] - z[4]) / (6 * P->dx[l]);
+    return kappa(P, z[2]) * Dc;
+}
+
 /* directional low-order intermediate states
  * (Eqs. 1d_low_directional_plus/minus, multid_low_directional_plus/minus)
  * with the factor K = 2d (2 in 1D, 6 in 3D; 4 in 2D by the same argument) */
@@ -640,6 +694,36 @@ static double P_lim(const orc_problem *P, const double *const *U, int l, const i
     return aL + theta_d(P, U, l, c, dt, dg) * (ahat_H_used(P, U, l, c) - aL);
 }
 
+/* App. A with limiting.  The paper limits this variant too but gives no
+ * formula; the reading taken here: the diffusion flux g joins the convective
+ * flux, F = fhat - g, whose low-order part F^L = fhat^L - (a(ubar_{i+1}) -
+ * a(ubar_i))/dx is the one the low-order states u^{L,+-} of Sec. 5.1 are
+ * built from.  The limited average is ubar - mu (F^Lim_{i+1/2} -
+ * F^Lim_{i-1/2}) = (u^{Lim,+} + u^{Lim,-})/2 with u^{Lim,+}_i = u^{L,+}_i -
+ * K mu theta_{i+1/2} dF_{i+1/2} and u^{Lim,-}_{i+1} = u^{L,-}_{i+1} + K mu
+ * theta_{i+1/2} dF_{i+1/2} (one correction per state, so the factor is K,
+ * not 3K); theta is the largest value keeping both in the bounds. */
+static double F_nodc_lim(const orc_problem *P, const double *const *U, int l, const int c[3], double dt, orc_diag *dg)
+{
+    double FL = fhat_L(P, U, l, c) - ahat_L_face(P, U, l, c);
+    double dF = (fhat_H(P, U, l, c) - g_nodc(P, U, l, c)) - FL;
+    double t;
+    if (P->theta_mode == ORC_THETA_ONE) t = 1;
+    else if (P->theta_mode == ORC_THETA_ZERO) t = 0;
+    else {
+        double K = 2.0 * P->dim, mu = dt / P->dx[l];
+        int cp[3];
+        shift(c, l, 1, cp);
+        double up = uL_plus(P, U, l, c, dt), um = uL_minus(P, U, l, cp, dt);
+        t = min2(Theta(P, up, up - K * mu * dF), Theta(P, um, um + K * mu * dF));
+        if (dg) {
+            dg->n_theta++;
+            if (t < 1) dg->n_theta_lt1++;
+        }
+    }
+    return FL + t * dF;
+}
+
 /* ------------------------------------------------------------------ */
 /* Public per-cell evaluations.                                       */
 /* ------------------------------------------------------------------ */
@@ -660,7 +744,8 @@ static void rhs_cell(const orc_problem *P, const double *const *U, const int c[3
         int cm[3];
         shift(c, l, -1, cm);
         r -= (fhat_H(P, U, l, c) - fhat_H(P, U, l, cm)) / P->dx[l];
-        r += (dca_face(P, U, l, c) - dca_face(P, U, l, cm)) / P->dx[l];
+        if (P->nodc) r += (g_nodc(P, U, l, c) - g_nodc(P, U, l, cm)) / P->dx[l];
+        else r += (dca_face(P, U, l, c) - dca_face(P, U, l, cm)) / P->dx[l];
     }
     out[0] = r;
     int nb = 1 << P->dim;
@@ -685,6 +770,10 @@ static void fe_cell(const orc_problem *P, const double *const *U, double dt, con
             int cm[3], cp[3];
             shift(c, l, -1, cm);
             shift(c, l, 1, cp);
+            if (P->nodc) {
+                un -= mu * (F_nodc_lim(P, U, l, c, dt, dg) - F_nodc_lim(P, U, l, cm, dt, dg));
+                continue;
+            }
             un -= mu * (F_lim(P, U, l, c, dt, dg) - F_lim(P, U, l, cm, dt, dg));
             un += nu * (P_lim(P, U, l, cp, dt, dg) - 2 * P_lim(P, U, l, c, dt, dg) + P_lim(P, U, l, cm, dt, dg));
         }

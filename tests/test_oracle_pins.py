@@ -663,3 +663,118 @@ def test_cfl_time_step_closed_form():
     spec, U = W.config1()
     P = oracle.problem(spec)
     assert abs(oracle.dt_cfl(P, U, 0.3) - 1.0 / 480.0) < 1e-17
+
+
+# ---------------------------------------------------------------------------
+# App. A: the variant without double conservation
+# ---------------------------------------------------------------------------
+
+def test_nodc_constant_kappa_reduces_to_printed_operator():
+    """For a = k0 u the compact operator of App. A reduces to the printed
+    five-point formula (Eq. 1d_diff_nodc_constant), and the average's
+    diffusion flux k0 D_c(u) to the central difference of Eq. 1d_diff_central_4th."""
+    N, dx, k0 = 13, 0.29, 0.8
+    P = oracle.problem(spec1d(N, N * dx, ("linear", 0.0, 0.0), ("linear", k0, 0.0), diffusion_form="nodc"))
+    rng = np.random.default_rng(11)
+    ub, up = rng.normal(size=N), rng.normal(size=N)
+    R = oracle.rhs(P, [ub, up])
+    ctr = (6 * ub - np.roll(up, 1) - up) / 4  # Simpson's rule for u_i (Sec. 2.1)
+    # PV at i+1/2: -1/12 u_{i-1/2} + 4/3 u_i - 5/2 u_{i+1/2} + 4/3 u_{i+1} - 1/12 u_{i+3/2}
+    pv = 4 * k0 / dx ** 2 * (-np.roll(up, 1) / 12 + 4 * ctr / 3 - 5 * up / 2 + 4 * np.roll(ctr, -1) / 3
+                             - np.roll(up, -1) / 12)
+    # face flux at i+1/2: k0 (u_{i-1/2} - 8 u_i + 8 u_{i+1} - u_{i+3/2}) / (6 dx)
+    g = k0 * (np.roll(up, 1) - 8 * ctr + 8 * np.roll(ctr, -1) - np.roll(up, -1)) / (6 * dx)
+    avg = (g - np.roll(g, 1)) / dx
+    np.testing.assert_allclose(R[1], pv, rtol=0, atol=1e-12 * np.abs(pv).max())
+    np.testing.assert_allclose(R[0], avg, rtol=0, atol=1e-12 * np.abs(avg).max())
+
+
+@pytest.mark.parametrize("flux", [("linear", 0.7, 0.0), ("quad", 0.5)])
+def test_nodc_equals_dc_for_linear_diffusion(flux):
+    """For a = k0 u the variant of App. A coincides with the doubly conservative
+    scheme (stated at the end of App. A): right-hand side, and the limited
+    stage with theta forced to one (the high-order updates)."""
+    N = 24
+    base = spec1d(N, 1.0, flux, ("linear", 0.05, 0.0), umin=0.0, umax=1.0, limiter=True)
+    rng = np.random.default_rng(3)
+    U = [rng.uniform(0.1, 0.9, N) for _ in range(2)]
+    Pd = oracle.problem(base)
+    Pn = oracle.problem(dict(base, diffusion_form="nodc"))
+    for a, b in zip(oracle.rhs(Pd, U), oracle.rhs(Pn, U)):
+        np.testing.assert_allclose(b, a, rtol=0, atol=1e-11 * (1 + np.abs(a).max()))
+    dt = 0.2 * oracle.dt_cfl(Pd, U, 0.2)
+    Pd1 = oracle.problem(base, theta_mode="one")
+    Pn1 = oracle.problem(dict(base, diffusion_form="nodc"), theta_mode="one")
+    for a, b in zip(oracle.fe(Pd1, U, dt)[0], oracle.fe(Pn1, U, dt)[0]):
+        np.testing.assert_allclose(b, a, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("diff", [("power", 0.1, 3.0), ("bl", 0.01), ("deadzone", 0.05, 0.4)])
+def test_nodc_theta_zero_is_the_dc_low_order_scheme(diff):
+    """With every theta forced to zero both variants reduce to the same
+    first-order scheme: the low-order flux F^L = f^L - (a(u_{i+1}) - a(u_i))/dx
+    of the App. A reading is exactly the DC scheme's low-order update."""
+    N = 20
+    base = spec1d(N, 1.0, ("quad", 0.5), diff, umin=0.0, umax=1.0, limiter=True)
+    rng = np.random.default_rng(5)
+    U = [rng.uniform(0.0, 1.0, N) for _ in range(2)]
+    dt = oracle.dt_cfl(oracle.problem(base), U, 0.25)
+    Pd = oracle.problem(base, theta_mode="zero")
+    Pn = oracle.problem(dict(base, diffusion_form="nodc"), theta_mode="zero")
+    (a, _), (b, _) = oracle.fe(Pd, U, dt), oracle.fe(Pn, U, dt)
+    np.testing.assert_allclose(b[0], a[0], rtol=0, atol=1e-14)  # averages (the PV operators differ)
+
+
+def _nodc_errors(N, c=0.1, m=3.0):
+    """Errors of the App. A right-hand side against (a(u))_xx for a smooth
+    periodic u on [0, 1] with a = c u^m (zero flux).  The averages are the
+    Simpson averages of the exact point values, so that the reconstructed
+    centres are exact and the errors are those of the operators alone."""
+    dx = 1.0 / N
+    x = (np.arange(N) + 0.5) * dx  # centres
+    modes = [(1, 0.25, 0.0), (2, 0.1, 0.3 + np.pi / 2)]  # k, amplitude, phase of sin(2 pi k x + phase)
+
+    def u(x, d=0):
+        r = 0.5 if d == 0 else 0.0
+        for k, A, ph in modes:
+            w = 2 * np.pi * k
+            r = r + A * w ** d * np.sin(w * x + ph + d * np.pi / 2)
+        return r
+
+    xf = x + dx / 2
+    ub = (u(x - dx / 2) + 4 * u(x) + u(xf)) / 6
+    U = [ub, u(xf)]
+    P = oracle.problem(spec1d(N, 1.0, ("linear", 0.0, 0.0), ("power", c, m), diffusion_form="nodc"))
+    R = oracle.rhs(P, U)
+    kap = lambda v: c * m * v ** (m - 1)
+    dkap = lambda v: c * m * (m - 1) * v ** (m - 2)
+    axx = dkap(u(xf)) * u(xf, 1) ** 2 + kap(u(xf)) * u(xf, 2)
+    ax = kap(u(xf)) * u(xf, 1)
+    avg = (ax - np.roll(ax, 1)) / dx
+    return np.abs(R[1] - axx).max(), np.abs(R[0] - avg).max()
+
+
+def test_nodc_operators_are_fourth_order():
+    """App. A's point-value operator and average flux are fourth-order
+    accurate for a nonlinear kappa (the order conditions behind B)."""
+    e = np.array([_nodc_errors(N) for N in (16, 32, 64)])
+    rates = np.log2(e[:-1] / e[1:])
+    assert (rates > 3.7).all(), rates
+
+
+@pytest.mark.parametrize("trial", range(4))
+def test_nodc_limited_stage_is_bound_preserving(trial):
+    """The App. A reading with limiting keeps the averages in the bounds by
+    itself (the safeguard clamp stays unused) under the CFL condition, on
+    blocky data that activates the limiter."""
+    rng = np.random.default_rng(400 + trial)
+    fl, df = FLUXES[trial % 4], DIFFS[(trial + 1) % 4]
+    spec, U = _random_problem(rng, 1, fl, df)
+    spec = dict(spec, n=[24], diffusion_form="nodc")
+    U = [np.resize(u, 24) for u in U]
+    P = oracle.problem(spec)
+    dt = oracle.dt_cfl(P, U, 0.5 * rng.uniform(0.5, 1.0))
+    V, dg = oracle.fe(P, U, dt)
+    assert dg["n_theta_lt1"] > 0
+    assert dg["max_avg_clamp"] <= 1e-14
+    assert (V[0] >= 0).all() and (V[0] <= 1).all()
