@@ -6,7 +6,7 @@ projection on, FP32, SSP-RK3, all K steps in one HIP graph launch.  Prints one
 JSON line.  ``value`` is cell-DoF updates per second per RK stage (all
 instances, inputs resident in HBM before the timed region).
 
-    python bench.py [--steps K] [--warmup W] [--workload c4|c2|c3|c3f32|c5]
+    python bench.py [--steps K] [--warmup W] [--workload c4|c2|c3|c3f32|c5|nodc]
 """
 import argparse
 import glob
@@ -73,6 +73,8 @@ def workload(name):
         return "c3_buckley_leverett_gravity_1024x1024_fp32", [W.config3(precision=32)]
     if name == "c5":
         return "c5_degenerate_3d_256cubed_fp32_si", [W.config5()]
+    if name == "nodc":
+        return "nodc_ek_batched_1024x8192_1d_fp64", W.config_nodc()
     raise SystemExit("unknown workload " + name)
 
 

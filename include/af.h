@@ -68,6 +68,17 @@ typedef enum {
                          five stages, two more state buffers */
 } af_integrator;
 
+/* Form of the diffusion discretization. */
+typedef enum {
+    AF_DIFF_DC = 0,   /* doubly conservative (Secs. 2.2, 4): the paper's method */
+    AF_DIFF_NODC = 1  /* App. A, 1D only: averages with the face fluxes
+                         kappa(u_{i+1/2}) D_c(u)_{i+1/2}, point values with the
+                         compact operator of Eq. (1d_diff_compact_kappa_u).  With
+                         the limiter, the diffusion flux joins the convective
+                         one in the face correction (one limited correction per
+                         low-order state; the paper states no formula for it) */
+} af_diffusion_form;
+
 typedef struct {
     int dim;                 /* 1, 2 or 3 */
     int n[3];                /* cells per axis (>= 4 on used axes) */
@@ -87,6 +98,8 @@ typedef struct {
     double si_gamma;         /* gamma of the blending */
     int precision;           /* 32 or 64: storage and stencil arithmetic */
     int integrator;          /* af_integrator */
+    int diffusion_form;      /* af_diffusion_form; AF_DIFF_NODC needs dim = 1 and no
+                                blending (else AF_ERR_UNSUPPORTED) */
 } af_problem;
 
 typedef struct {

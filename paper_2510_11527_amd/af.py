@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "AF_OK", -1: "AF_ERR_ARG", -2: "AF_ERR_ALLOC", -3: "AF_ERR_DE
                 -5: "AF_ERR_NONFINITE", -6: "AF_ERR_CFL", -7: "AF_ERR_STATE", -8: "AF_ERR_UNSUPPORTED"}
 FLUX = {"linear": 0, "quad": 1, "bl": 2, "bl_grav": 3}
 DIFF = {"linear": 0, "power": 1, "deadzone": 2, "bl": 3, "ramp2": 4}
+DIFFUSION_FORMS = {"dc": 0, "nodc": 1}
 INTEGRATORS = {"ssprk3": 0, "euler": 1, "ssprk54": 2}
 
 EXPORTS = ["af_create", "af_destroy", "af_set_state", "af_get_state", "af_step", "af_residual", "af_norms",
@@ -44,6 +45,7 @@ class AfProblem(ctypes.Structure):
         ("si_gamma", ctypes.c_double),
         ("precision", ctypes.c_int),
         ("integrator", ctypes.c_int),
+        ("diffusion_form", ctypes.c_int),
     ]
 
 
@@ -129,6 +131,7 @@ def make_problem(spec, precision=None, integrator="ssprk3"):
     P.si_gamma = float(spec.get("si_gamma", 1.0))
     P.precision = int(precision or spec.get("precision", 64))
     P.integrator = INTEGRATORS[integrator]
+    P.diffusion_form = DIFFUSION_FORMS[spec.get("diffusion_form", "dc")]
     return P
 
 

@@ -34,6 +34,7 @@ struct InstDev {
     double pu0, plo, phi, pc1, pc2, pc3;
     int pabs, ppow;
     int wstart, wcount;  // the instance's range in the work list of the stage kernels
+    int nodc, pad0;      // 1: diffusion in the form of App. A (no double conservation; 1D)
     double idx1[3];      // 1 / dx_l
     double idx2[3];      // 1 / dx_l^2
     double i6dx[3];      // 1 / (6 dx_l)

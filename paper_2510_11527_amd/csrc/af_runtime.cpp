@@ -295,6 +295,10 @@ af_status validate(const af_problem &P, int idx)
         return bad(AF_ERR_CFL, "with the limiter cfl times the largest stage step must not exceed 1/(2 dim)");
     if (!std::isnan(P.umin) && !std::isnan(P.umax) && !(P.umax >= P.umin)) return bad(AF_ERR_ARG, "umax < umin");
     if (P.si_blend && !(P.si_gamma >= 0)) return bad(AF_ERR_ARG, "si_gamma must be >= 0");
+    if (P.diffusion_form != AF_DIFF_DC && P.diffusion_form != AF_DIFF_NODC)
+        return bad(AF_ERR_ARG, "unknown diffusion form");
+    if (P.diffusion_form == AF_DIFF_NODC && (P.dim != 1 || P.si_blend))
+        return bad(AF_ERR_UNSUPPORTED, "the diffusion form of App. A is one-dimensional and unblended");
     return AF_OK;
 }
 
@@ -523,6 +527,7 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
         I.umax = P.umax;
         I.cfl = P.cfl;
         I.si_gamma = P.si_blend ? P.si_gamma : 0.0;
+        I.nodc = P.diffusion_form == AF_DIFF_NODC;
         if (!std::isnan(P.umin) && !std::isnan(P.umax)) derive_bounds_params(I, P, P.dim);
         set_f32_params(I);
     }

@@ -116,6 +116,16 @@ struct Phys {
         return pabs ? copysign(g, u) : g;
     }
 
+    // kappa(u) = a'(u) of the same forms (the pow branch: p0 p u^(p-1)); zero
+    // where the clamp of the unified form is active
+    __device__ __forceinline__ T kappa(T u) const
+    {
+        if (ppow) return a0 * a1 * power_potential<T>(T(1), a1 - T(1), am - 1, u);
+        const T w = (pabs ? fabs(u) : u) - pu0;
+        if (!(w > plo && w < phi)) return T(0);
+        return pc1 + w * (T(2) * pc2 + w * (T(3) * pc3));
+    }
+
     // max of |f_l'| over [min(x,y), max(x,y)]: end points and interior local
     // maxima of |f_l'|
     __device__ __forceinline__ T alpha_int(int l, T x, T y) const
@@ -333,6 +343,8 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
     T *__restrict__ out = p.out + I.off;
     const bool residual = p.stage == kStageRHS;
     const double dtd = p.st[wk.x].dt;
+    // the 1D variant without double conservation (App. A)
+    const bool nodc = D == 1 && I.nodc != 0;
 
     const T inf = __builtin_huge_val();
     T vlo = inf, vhi = -inf;  // min / max of the averages written
@@ -494,7 +506,21 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                         conv = th * conv + (T(1) - th) * convL;
                     }
                 }
-                const T d2 = (-(aa[0] + aa[4]) * T(1.0 / 3.0) + (aa[1] + aa[3]) * T(16.0 / 3.0) - T(10) * aa[2]) * idx2[l];
+                T d2;
+                if (nodc) {
+                    // App. A: (4/dx^2) sum_m kappa(z_m) (B z)_m, B = [0 0; 0 M] - [M 0; 0 0]
+                    // with the 4x4 matrix M printed there (rows of B below)
+                    const T b0 = T(-1.0 / 8.0) * zz[0] + T(1.0 / 6.0) * zz[1] - T(1.0 / 24.0) * zz[2];
+                    const T b1 = T(1.0 / 6.0) * (zz[0] + zz[3]) + T(0.5) * zz[1] - T(5.0 / 6.0) * zz[2];
+                    const T b2 = T(-1.0 / 8.0) * (zz[0] + zz[4]) + T(0.5) * (zz[1] + zz[3]) - T(0.75) * zz[2];
+                    const T b3 = T(1.0 / 6.0) * (zz[1] + zz[4]) + T(0.5) * zz[3] - T(5.0 / 6.0) * zz[2];
+                    const T b4 = T(-1.0 / 24.0) * zz[2] + T(1.0 / 6.0) * zz[3] - T(1.0 / 8.0) * zz[4];
+                    d2 = T(4) * idx2[l] *
+                         (((P.kappa(zz[0]) * b0 + P.kappa(zz[1]) * b1) + P.kappa(zz[2]) * b2) +
+                          (P.kappa(zz[3]) * b3 + P.kappa(zz[4]) * b4));
+                } else {
+                    d2 = (-(aa[0] + aa[4]) * T(1.0 / 3.0) + (aa[1] + aa[3]) * T(16.0 / 3.0) - T(10) * aa[2]) * idx2[l];
+                }
                 R += conv + d2;
             }
             if (!own) continue;
@@ -529,13 +555,13 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
             const bool need_hi = fidx >= 1 && fidx < G::t(l) + 2;
             if (!LIM && !need_hi) continue;
             const T ua = ub[G::cidx(x, y, z)], ubb = ub[G::cidx(x + sx, y + sy, z + sz)];
-            T fL = T(0), up = T(0), um = T(0);
+            T fL = T(0), up = T(0), um = T(0), dA = T(0);
             if (LIM || use_si) {
                 const T fa = P.f(l, ua), fb = P.f(l, ubb);
                 const T al = P.alpha_int(l, ua, ubb);
                 fL = T(0.5) * (fa + fb) - T(0.5) * al * (ubb - ua);
                 if constexpr (LIM) {
-                    const T dA = (P.a(ubb) - P.a(ua)) * idx1[l];
+                    dA = (P.a(ubb) - P.a(ua)) * idx1[l];
                     const T Km = K * mu[l];
                     up = ua - Km * (fL - fa) + Km * dA;   // u^{L,+} of the left cell
                     um = ubb - Km * (fb - fL) - Km * dA;  // u^{L,-} of the right cell
@@ -565,11 +591,23 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                 const T th = exp(-gam * T(0.5) * (s_at(l, x, y, z) + s_at(l, x + sx, y + sy, z + sz)));
                 fH = th * fH + (T(1) - th) * fL;
             }
+            if (nodc) {
+                // App. A: the diffusion flux kappa(u_{i+1/2}) D_c(u)_{i+1/2} joins
+                // the convective one, F = fhat - g, with low-order part
+                // fhat^L - (a(u_{i+1}) - a(u_i))/dx (the one the u^{L,+-} use)
+                const int bx = 2 * x + 1;
+                const T z0 = hg[G::hidx(bx - 2, 0, 0)], z1 = hg[G::hidx(bx - 1, 0, 0)], z2 = hg[G::hidx(bx, 0, 0)];
+                const T z3 = hg[G::hidx(bx + 1, 0, 0)], z4 = hg[G::hidx(bx + 2, 0, 0)];
+                fH -= P.kappa(z2) * ((z0 - z4) + T(8) * (z3 - z1)) * i6dx[l];
+                fL -= dA;
+            }
             T F = fH;
             if constexpr (LIM) {
                 if (!residual) {
+                    // each u^{L,+-} carries three corrections (factor 3K); with
+                    // the App. A flux it carries one (factor K)
                     const T df = fH - fL;
-                    const T s3 = T(3) * K * mu[l] * df;
+                    const T s3 = (nodc ? T(1) : T(3)) * K * mu[l] * df;
                     const T tc = fmin(Theta(up, up - s3, P.umin, P.umax), Theta(um, um + s3, P.umin, P.umax));
                     F = fL + tc * df;
                 }
@@ -587,7 +625,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
         const int E0 = l == 0 ? G::T0 + 2 : G::T0, E1 = l == 1 ? G::T1 + 2 : G::T1, E2 = l == 2 ? G::T2 + 2 : G::T2;
         const int FE0 = l == 0 ? G::T0 + 3 : G::T0, FE1 = l == 1 ? G::T1 + 3 : G::T1;
         const int NC = E0 * E1 * E2;
-        for (int id = (int)threadIdx.x; id < NC; id += NT) {
+        for (int id = (int)threadIdx.x; id < NC && !nodc; id += NT) {
             const int i = id % E0, r = id / E0, j = r % E1, k = r / E1;
             const int x = i + G::H0 - sx, y = j + G::H1 - sy, z = k + G::H2 - sz;
             T aH = T(0);
@@ -649,10 +687,11 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
             const int fo = G::face_off(l) + fi + FE0 * (fj + FE1 * fk);
             const int co = G::cell_off(l) + ci + CE0 * (cj + CE1 * ck);
             const T Fp = fl[fo], Fm = fl[fo - fstep];
-            const T Pm = pc[co - cstep], P0 = pc[co], Pp = pc[co + cstep];
             dF += mu[l] * (Fp - Fm);
-            dP += nu[l] * (Pp - T(2) * P0 + Pm);
             rF += idx1[l] * (Fp - Fm);
+            if (nodc) continue;  // the diffusion is part of the face flux
+            const T Pm = pc[co - cstep], P0 = pc[co], Pp = pc[co + cstep];
+            dP += nu[l] * (Pp - T(2) * P0 + Pm);
             rP += idx2[l] * (Pp - T(2) * P0 + Pm);
         }
         if (residual) {

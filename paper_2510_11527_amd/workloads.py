@@ -271,6 +271,44 @@ def config5(seed=SEED_BASE + 5, n=256, cfl=0.05, steps=100):
     return spec, dofs
 
 
+def _ek_profile_antiderivative(x):
+    """Antiderivative from -1 of the initial profile of the Evje-Karlsen
+    example (1 on [-1, -0.4), -2.5 x on [-0.4, 0), 0 on [0, 1)), extended
+    periodically with period 2 (the profile's integral over a period is 0.8)."""
+    k = np.floor((x + 1.0) / 2.0)
+    y = x - 2.0 * k
+    g = np.where(y < -0.4, y + 1.0, np.where(y < 0.0, 0.8 - 1.25 * y * y, 0.8))
+    return 0.8 * k + g
+
+
+def config_nodc(seed=SEED_BASE + 6, n_inst=1024, n=8192, cfl=0.075, precision=64, diffusion_form="nodc",
+                limiter=True):
+    """Batch of 1D strongly degenerate problems for the diffusion form of
+    App. A: a periodic stand-in of the Evje-Karlsen example (the paper's runs
+    use Dirichlet data on [-1, 1]).  f = u^2/4, a = max(0, u - 1/2) (kappa
+    jumps from 0 to 1 at u = 1/2: zero on a set of positive measure), initial
+    profile of that example shifted by a uniform random offset in [-1, 1);
+    averages exact, point values sampled; bounds [0, 1].  Returns a list of
+    (spec, dofs)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    dx = 2.0 / n
+    edges = -1.0 + dx * np.arange(n + 1)
+    for i in range(n_inst):
+        sh = rng.uniform(-1.0, 1.0)
+        G = _ek_profile_antiderivative(edges - sh)
+        avg = (G[1:] - G[:-1]) / dx
+        xf = edges[1:] - sh
+        yf = xf - 2.0 * np.floor((xf + 1.0) / 2.0)
+        pv = np.where(yf < -0.4, 1.0, np.where(yf < 0.0, -2.5 * yf, 0.0))
+        dofs = round_to([np.clip(avg, 0.0, 1.0), pv], precision)
+        spec = dict(name="nodc_ek_1d[%d]" % i, dim=1, n=[n], lo=[-1.0], hi=[1.0], flux=[("quad", 0.25, 0.0)],
+                    diff=("deadzone", 1.0, 0.5), umin=0.0, umax=1.0, cfl=cfl, limiter=limiter, si=False,
+                    si_gamma=1.0, precision=precision, t_end=None, steps=None, diffusion_form=diffusion_form)
+        out.append((spec, dofs))
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Small problems of the paper's examples, used by tests
 # ---------------------------------------------------------------------------
