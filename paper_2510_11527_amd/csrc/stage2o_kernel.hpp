@@ -123,7 +123,11 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     const unsigned kb = (unsigned)Ic->kstride * (unsigned)sizeof(T);
     const unsigned blk = 4u * kb;
     const auto rin = __builtin_amdgcn_make_buffer_rsrc((void *)(p.in + Ic->off), 0, (int)blk, kBufWord3);
-    const auto run = __builtin_amdgcn_make_buffer_rsrc((void *)(p.un + Ic->off), 0, (int)blk, kBufWord3);
+    // X0 (U^n) of the combination; a forward-Euler stage reads it from an
+    // empty range (zeros), so that one blend X0 + w (v - X0) with w = 1 serves
+    // every stage but the summing ones
+    const auto run = __builtin_amdgcn_make_buffer_rsrc((void *)(p.un + Ic->off), 0,
+                                                       p.mode == kCombFE ? 0 : (int)blk, kBufWord3);
     const auto rout = __builtin_amdgcn_make_buffer_rsrc((void *)(p.out + Ic->off), 0, (int)blk, kBufWord3);
     // X1 of a kCombSum stage (an empty range otherwise)
     const auto rx1 = __builtin_amdgcn_make_buffer_rsrc((void *)(p.x1 ? p.x1 + Ic->off : p.in + Ic->off), 0,
@@ -217,6 +221,15 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         k3mu[l] = T(12) * mu[l];
         k3nu[l] = T(12) * nu[l];
     }
+
+    // the stage's combination (stage_combine): a forward-Euler stage is the
+    // blend with X0 = 0 (empty range above) and w = 1, exactly v
+    const T wb = p.mode == kCombFE ? T(1) : p.w;
+    const bool summing = p.mode == kCombSum;
+    auto combine = [&](T v, T x0, T x1, T vin) -> T {
+        if (summing) return ((p.c0 * x0 + p.c1 * x1) + p.cin * vin) + p.w * v;
+        return x0 + wb * (v - x0);
+    };
 
     auto pot = [&](T u) -> T {
         if constexpr (PP) return u * (pc1 + u * (pc2 + u * pc3));
@@ -339,11 +352,12 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         // the residual); for pure quadratic fluxes t is c2 times
         //   (u_{-2}^2 - 8 u_{-1}^2 + 8 u_1^2 - u_2^2) + 2 sgn(c2) max|u| d4.
         const T sc = residual ? T(1) : dt;
-        T kc[2], kd[2], sg2[2];
+        T kc[2], kd[2], sg2[2], kd30 = T(0);
 #pragma unroll
         for (int l = 0; l < 2; l++) {
             kc[l] = -(BQ ? c2[l] : T(1)) * i6dx[l] * sc;
             kd[l] = idx2[l] * T(1.0 / 3.0) * sc;
+            kd30 -= T(30) * kd[l];
             sg2[l] = c2[l] > T(0) ? T(2) : (c2[l] < T(0) ? T(-2) : T(0));
         }
         auto pv_dir = [&](int l, V2<T> w0, V2<T> w1, V2<T> w2, V2<T> w3, V2<T> w4, T acc) -> T {
@@ -359,7 +373,8 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
                 const T dcf = (fq(l, w0.x) - fq(l, w4.x)) + T(8) * (fq(l, w3.x) - fq(l, w1.x));
                 t = dcf + al * d4;
             }
-            const T d = (T(16) * (w1.y + w3.y) - (w0.y + w4.y)) - T(30) * w2.y;
+            // the centre term -30 a_0 of both directions is added once per point
+            const T d = T(16) * (w1.y + w3.y) - (w0.y + w4.y);
             return (acc + kc[l] * t) + kd[l] * d;
         };
         T R[2][3];  // per own cell: x-face, y-face, corner point value (or du/dt)
@@ -368,15 +383,15 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
             const int b = c == 0 ? b0 : b1;
             const bool z0 = residual;
             // x-face point (x+1/2, y)
-            T r = z0 ? T(0) : Su(SXF, b);
+            T r = kd30 * Sa(SXF, b) + (z0 ? T(0) : Su(SXF, b));
             r = pv_dir(0, S(SXF, b - 1), S(SC, b), S(SXF, b), S(SC, b + 1), S(SXF, b + 1), r);
             R[c][0] = pv_dir(1, S(SXF, b - SX), S(SK, b - SX), S(SXF, b), S(SK, b), S(SXF, b + SX), r);
             // y-face point (x, y+1/2)
-            r = z0 ? T(0) : Su(SYF, b);
+            r = kd30 * Sa(SYF, b) + (z0 ? T(0) : Su(SYF, b));
             r = pv_dir(0, S(SYF, b - 1), S(SK, b - 1), S(SYF, b), S(SK, b), S(SYF, b + 1), r);
             R[c][1] = pv_dir(1, S(SYF, b - SX), S(SC, b), S(SYF, b), S(SC, b + SX), S(SYF, b + SX), r);
             // corner point (x+1/2, y+1/2)
-            r = z0 ? T(0) : Su(SK, b);
+            r = kd30 * Sa(SK, b) + (z0 ? T(0) : Su(SK, b));
             r = pv_dir(0, S(SK, b - 1), S(SYF, b), S(SK, b), S(SYF, b + 1), S(SK, b + 1), r);
             R[c][2] = pv_dir(1, S(SK, b - SX), S(SXF, b), S(SK, b), S(SXF, b + SX), S(SK, b + SX), r);
         }
@@ -394,7 +409,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
                 T v = R[c][z - 1];
                 if (!isfinite(v)) bad = true;
                 if constexpr (LIM) v = clampb(v, umin, umaxv);
-                v = stage_combine(p, v, unv[c][z], x1v[c][z], Su(z == 1 ? SXF : (z == 2 ? SYF : SK), c == 0 ? b0 : b1));
+                v = combine(v, unv[c][z], x1v[c][z], Su(z == 1 ? SXF : (z == 2 ? SYF : SK), c == 0 ? b0 : b1));
                 if constexpr (LIM) v = clampb(v, umin, umaxv);
                 st(z, gi, v);
             }
@@ -567,7 +582,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
             clamp_mag = fmax(clamp_mag, (T)fabs(cl - v));
             v = cl;
         }
-        v = stage_combine(p, v, unv[c][0], x1v[c][0], u);
+        v = combine(v, unv[c][0], x1v[c][0], u);
         if constexpr (LIM) {
             const T cl = clampb(v, umin, umaxv);
             clamp_mag = fmax(clamp_mag, (T)fabs(cl - v));
