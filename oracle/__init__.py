@@ -16,7 +16,8 @@ A problem is described by a plain dict (see
      "diff": ("deadzone", eps, u0),                  # kind, params
      "umin": 0.0, "umax": 1.0, "limiter": True,
      "si": False, "si_gamma": 1.0, "cfl": 0.075,
-     "diffusion_form": "dc"}                         # or "nodc" (App. A, 1D)
+     "diffusion_form": "dc",                         # or "nodc" (App. A, 1D)
+     "bc": ("periodic", "periodic")}                 # 1D ends: "outflow" or ("dirichlet", g)
 
 DoFs are a list of 2^d numpy float64 arrays in the zeta order of Sec. 4
 (average first), each of prod(n) values with x fastest.
@@ -34,6 +35,7 @@ _LIB = os.path.join(_HERE, "liborc.so")
 FLUX_KINDS = {"linear": 0, "quad": 1, "bl": 2, "bl_grav": 3}
 DIFF_KINDS = {"linear": 0, "power": 1, "deadzone": 2, "bl": 3, "ramp2": 4}
 THETA_MODES = {"computed": 0, "one": 1, "zero": 2}
+BC_KINDS = {"periodic": 0, "dirichlet": 1, "outflow": 2}
 
 
 class OrcProblem(ctypes.Structure):
@@ -53,6 +55,8 @@ class OrcProblem(ctypes.Structure):
         ("si_gamma", ctypes.c_double),
         ("theta_mode", ctypes.c_int),
         ("nodc", ctypes.c_int),
+        ("bc", ctypes.c_int * 2),
+        ("bcval", ctypes.c_double * 2),
         ("dx", ctypes.c_double * 3),
         ("kappa_max", ctypes.c_double),
         ("ncrit", ctypes.c_int * 3),
@@ -154,6 +158,11 @@ def problem(spec, theta_mode="computed"):
     P.si_gamma = float(spec.get("si_gamma", 1.0))
     P.theta_mode = THETA_MODES[theta_mode]
     P.nodc = int(spec.get("diffusion_form", "dc") == "nodc")
+    bc = spec.get("bc", ("periodic", "periodic"))
+    for s in range(2):
+        kind = bc[s] if isinstance(bc[s], str) else bc[s][0]
+        P.bc[s] = BC_KINDS[kind]
+        P.bcval[s] = 0.0 if isinstance(bc[s], str) else float(bc[s][1])
     if lib().orc_setup(ctypes.byref(P)) != 0:
         raise ValueError("oracle: invalid problem")
     return P

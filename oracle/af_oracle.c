@@ -53,6 +53,7 @@
 enum { ORC_F_LINEAR = 0, ORC_F_QUAD = 1, ORC_F_BL = 2, ORC_F_BL_GRAV = 3 };
 enum { ORC_A_LINEAR = 0, ORC_A_POWER = 1, ORC_A_DEADZONE = 2, ORC_A_BL = 3, ORC_A_RAMP2 = 4 };
 enum { ORC_THETA_COMPUTED = 0, ORC_THETA_ONE = 1, ORC_THETA_ZERO = 2 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_DIRICHLET = 1, ORC_BC_OUTFLOW = 2 };
 
 typedef struct {
     /* problem (filled by the caller) */
@@ -69,6 +70,8 @@ typedef struct {
     double si_gamma;
     int theta_mode;   /* ORC_THETA_*: computed, forced to 1, forced to 0 */
     int nodc;         /* 1: the variant of App. A without double conservation (1D) */
+    int bc[2];        /* ORC_BC_* of the low and high end of axis 0 (1D; both periodic or neither) */
+    double bcval[2];  /* Dirichlet values */
     /* derived (filled by orc_setup) */
     double dx[3];
     double kappa_max;
@@ -229,6 +232,10 @@ int orc_setup(orc_problem *P)
 {
     if (P->dim < 1 || P->dim > 3) return -1;
     if (P->nodc && (P->dim != 1 || P->si)) return -1;  /* App. A is a 1D scheme */
+    for (int s = 0; s < 2; s++)
+        if (P->bc[s] < ORC_BC_PERIODIC || P->bc[s] > ORC_BC_OUTFLOW) return -1;
+    if ((P->bc[0] == ORC_BC_PERIODIC) != (P->bc[1] == ORC_BC_PERIODIC)) return -1;
+    if (P->bc[0] != ORC_BC_PERIODIC && (P->dim != 1 || P->si)) return -1;
     for (int l = 0; l < 3; l++) {
         if (l >= P->dim) { P->n[l] = 1; P->dx[l] = 1; P->ncrit[l] = 0; continue; }
         if (P->n[l] < 4) return -1;
@@ -272,8 +279,24 @@ static long cell_index(const orc_problem *P, const int c[3])
     return (long)i + (long)P->n[0] * ((long)j + (long)P->n[1] * k);
 }
 
+/* Non-periodic ends (1D).  The paper runs Examples 6.5-6.8 with Dirichlet
+ * or outflow boundaries but states no ghost treatment; the reading taken
+ * here: every half-grid point beyond the domain, the boundary points
+ * x_{-1/2} and x_{N-1/2} included, and every ghost cell average takes one
+ * boundary value -- the Dirichlet value, or for outflow the average of the
+ * adjacent boundary cell.  The stored boundary point value x_{N-1/2} is not
+ * evolved: a stage writes the boundary value into it. */
+static int bc_open(const orc_problem *P) { return P->bc[0] != ORC_BC_PERIODIC; }
+static double bc_value(const orc_problem *P, const double *const *U, int side)
+{
+    if (P->bc[side] == ORC_BC_DIRICHLET) return P->bcval[side];
+    return U[0][side == 0 ? 0 : P->n[0] - 1];
+}
+
 static double avg(const orc_problem *P, const double *const *U, const int c[3])
 {
+    if (bc_open(P) && c[0] < 0) return bc_value(P, U, 0);
+    if (bc_open(P) && c[0] >= P->n[0]) return bc_value(P, U, 1);
     return U[0][cell_index(P, c)];
 }
 
@@ -305,6 +328,8 @@ static double centre(const orc_problem *P, const double *const *U, const int c[3
 /* value at half-grid point p: a point-value DoF, or a reconstructed centre */
 static double H(const orc_problem *P, const double *const *U, const int p[3])
 {
+    if (bc_open(P) && p[0] <= -1) return bc_value(P, U, 0);
+    if (bc_open(P) && p[0] >= 2 * P->n[0] - 1) return bc_value(P, U, 1);
     int q[3], c[3], b = 0;
     for (int l = 0; l < 3; l++) {
         q[l] = wrapi(p[l], 2 * P->n[l]);
@@ -755,6 +780,7 @@ static void rhs_cell(const orc_problem *P, const double *const *U, const int c[3
         int p[3] = {2 * c[0] + (b & 1), 2 * c[1] + ((b >> 1) & 1), 2 * c[2] + ((b >> 2) & 1)};
         out[zeta_of_mask(P->dim, b)] = pv_rhs(&Q, U, p);
     }
+    if (bc_open(P) && c[0] == P->n[0] - 1) out[1] = 0;  /* the boundary point is not an unknown */
 }
 
 /* one forward-Euler stage of the (limited) scheme for one cell */
@@ -814,6 +840,7 @@ static void fe_cell(const orc_problem *P, const double *const *U, double dt, con
         }
         out[zeta_of_mask(P->dim, b)] = v;
     }
+    if (bc_open(P) && c[0] == P->n[0] - 1) out[1] = P->bc[1] == ORC_BC_DIRICHLET ? P->bcval[1] : out[0];
 }
 
 static long ncells(const orc_problem *P) { return (long)P->n[0] * P->n[1] * P->n[2]; }
@@ -1001,6 +1028,12 @@ double orc_dt(const orc_problem *P, const double *const *U, double cfl)
             shift(c, l, 1, cp);
             double v = alpha_L(P, l, avg(P, U, c), avg(P, U, cp)) / P->dx[l] + P->kappa_max / (P->dx[l] * P->dx[l]);
             if (v > m) m = v;
+            if (bc_open(P) && c[0] == 0) {  /* the face x_{-1/2} with the ghost cell */
+                int cm[3];
+                shift(c, l, -1, cm);
+                v = alpha_L(P, l, avg(P, U, cm), avg(P, U, c)) / P->dx[l] + P->kappa_max / (P->dx[l] * P->dx[l]);
+                if (v > m) m = v;
+            }
         }
     }
     return cfl / m;

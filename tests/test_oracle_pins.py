@@ -778,3 +778,117 @@ def test_nodc_limited_stage_is_bound_preserving(trial):
     assert dg["n_theta_lt1"] > 0
     assert dg["max_avg_clamp"] <= 1e-14
     assert (V[0] >= 0).all() and (V[0] <= 1).all()
+
+
+# ---------------------------------------------------------------------------
+# Dirichlet and outflow ends (1D; the ghost rule is a reading, see af_oracle.c)
+# ---------------------------------------------------------------------------
+
+def _bump_state(N, L, centre=0.5, width=0.15, base=0.0, amp=1.0):
+    """Averages and point values of base + amp * cos^4 bump (compact support),
+    averages by 64-point midpoint sub-sampling."""
+    dx = L / N
+    def f(x):
+        r = np.clip(np.abs(x - centre) / width, 0, 1)
+        return base + amp * np.where(r < 1, np.cos(0.5 * np.pi * r) ** 4, 0.0)
+    xs = (np.arange(N)[:, None] + (np.arange(64) + 0.5)[None, :] / 64) * dx
+    return [f(xs).mean(axis=1), f((np.arange(N) + 1.0) * dx)]
+
+
+@pytest.mark.parametrize("bc", [("outflow", "outflow"), (("dirichlet", 0.0), ("dirichlet", 0.0)),
+                                (("dirichlet", 0.0), "outflow")])
+@pytest.mark.parametrize("lim", [False, True])
+def test_open_ends_leave_interior_solutions_alone(bc, lim):
+    """While a solution equals the boundary value near both ends, every
+    boundary rule gives exactly the periodic result: the ghost values agree
+    with what the periodic wrap-around would supply."""
+    N = 96
+    base = spec1d(N, 1.0, ("quad", 0.5, 0.0), ("deadzone", 0.02, 0.3), umin=0.0, umax=1.0, limiter=lim)
+    U = _bump_state(N, 1.0)
+    Pp = oracle.problem(base)
+    Pb = oracle.problem(dict(base, bc=bc))
+    dts = [0.3 * oracle.dt_cfl(Pp, U, 0.3)] * 8
+    Up, _, _ = oracle.run(Pp, U, dts=dts)
+    Ub, _, _ = oracle.run(Pb, U, dts=dts)
+    for a, b in zip(Up, Ub):
+        np.testing.assert_array_equal(b, a)
+
+
+@pytest.mark.parametrize("bc", [("outflow", "outflow"), (("dirichlet", 0.3), ("dirichlet", 0.3))])
+def test_constant_boundary_state_is_a_fixed_point(bc):
+    """The constant state equal to the boundary value (outflow: any constant)
+    is kept exactly by every stage, with and without limiting."""
+    N = 40
+    for lim in (False, True):
+        base = spec1d(N, 1.0, ("bl_grav", 0.0, 5.0), ("bl", 0.01, 0.0), umin=0.0, umax=1.0, limiter=lim, bc=bc)
+        U = [np.full(N, 0.3), np.full(N, 0.3)]
+        P = oracle.problem(base)
+        V, _, _ = oracle.run(P, U, nsteps=5, cfl=0.3)
+        for v in V:
+            np.testing.assert_allclose(v, 0.3, rtol=0, atol=1e-15)
+
+
+def test_outflow_lets_a_bump_leave():
+    """Linear advection to the right with outflow ends: after the bump has
+    crossed the right end the domain is back at the background value (small
+    reflection), and the mass decreased by the bump's mass."""
+    N, L = 200, 2.0
+    base = spec1d(N, L, ("linear", 1.0, 0.0), ("linear", 1e-4, 0.0), umin=0.0, umax=1.0, limiter=True,
+                  bc=("outflow", "outflow"))
+    U = _bump_state(N, L, centre=1.5, width=0.2)
+    m0 = U[0].sum() * (L / N)
+    P = oracle.problem(base)
+    V, t, _ = oracle.run(P, U, t_end=0.9, cfl=0.4)
+    assert abs(V[0]).max() < 2e-3 and abs(V[1]).max() < 2e-3
+    assert abs(V[0].sum() * (L / N)) < 1e-3 * m0
+    assert V[0].min() >= 0.0 and V[0].max() <= 1.0
+
+
+def test_dirichlet_inflow_fills_the_domain():
+    """Linear advection to the right from a Dirichlet inflow value 1 into a
+    zero background: behind the front the state is the inflow value, ahead of
+    it the background; bounds hold throughout."""
+    N, L = 200, 2.0
+    base = spec1d(N, L, ("linear", 1.0, 0.0), ("linear", 1e-3, 0.0), umin=0.0, umax=1.0, limiter=True,
+                  bc=(("dirichlet", 1.0), ("dirichlet", 0.0)))
+    U = [np.zeros(N), np.zeros(N)]
+    P = oracle.problem(base)
+    V, t, _ = oracle.run(P, U, t_end=1.0, cfl=0.4)
+    x = (np.arange(N) + 0.5) * (L / N)
+    assert np.allclose(V[0][x < 0.7], 1.0, atol=1e-3)
+    assert np.allclose(V[0][x > 1.3], 0.0, atol=1e-3)
+    assert V[0].min() >= 0.0 and V[0].max() <= 1.0 and V[1].min() >= 0.0 and V[1].max() <= 1.0
+    assert V[1][-1] == 0.0  # the stored boundary point value is the Dirichlet value
+
+
+@pytest.mark.parametrize("bc", [(("dirichlet", 0.7), ("dirichlet", -0.4)), ("outflow", "outflow"),
+                                (("dirichlet", 1.3), "outflow")])
+@pytest.mark.parametrize("c,k0", [(1.3, 0.7), (0.4, 0.05)])  # the printed stencils are for c > 0
+def test_open_ends_match_printed_stencils_on_ghost_filled_grid(bc, c, k0):
+    """For f = c u, a = k0 u the right-hand side at every cell, boundary cells
+    included, is the printed linear AF stencil (Eq. 1d_af_constant) applied
+    to the grid extended by the ghost rule: ghost averages, ghost point
+    values and both boundary points x_{-1/2}, x_{N-1/2} take the boundary
+    value (Dirichlet value, or the boundary cell's average); ghost centres
+    too.  The stored boundary point is not an unknown: its right-hand side
+    is zero."""
+    g = golden("linear_af_stencils.json")
+    N, dx, G = 13, 0.37, 3
+    P = oracle.problem(spec1d(N, N * dx, ("linear", c, 0.0), ("linear", k0, 0.0), bc=bc))
+    rng = np.random.default_rng(17)
+    ub, up = rng.normal(size=N), rng.normal(size=N)
+    R = oracle.rhs(P, [ub, up])
+    val = [s[1] if not isinstance(s, str) else (ub[0] if side == 0 else ub[-1]) for side, s in enumerate(bc)]
+    UB = np.concatenate([np.full(G, val[0]), ub, np.full(G, val[1])])
+    UP = np.concatenate([np.full(G, val[0]), up, np.full(G, val[1])])
+    UP[G + N - 1] = val[1]  # x_{N-1/2} is the boundary point
+    ctr = (6 * UB - np.roll(UP, 1) - UP) / 4
+    ctr[:G], ctr[G + N:] = val[0], val[1]
+    avg = c / dx * _apply_stencil(g["avg_convection_over_c_dx"], UB, UP, ctr, 0) \
+        + k0 / dx ** 2 * _apply_stencil(g["avg_diffusion_over_k0_dx2"], UB, UP, ctr, 0)
+    pv = c / dx * _apply_stencil(g["pv_convection_over_c_dx"], UB, UP, ctr, 1) \
+        + k0 / dx ** 2 * _apply_stencil(g["pv_diffusion_over_k0_dx2"], UB, UP, ctr, 1)
+    avg, pv = avg[G:G + N], pv[G:G + N]
+    pv[-1] = 0.0
+    np.testing.assert_allclose(R[0], avg, rtol=0, atol=1e-12 * (1 + np.abs(avg).max()))
+    np.testing.assert_allclose(R[1], pv, rtol=0, atol=1e-12 * (1 + np.abs(pv).max()))
