@@ -6,7 +6,7 @@ projection on, FP32, SSP-RK3, all K steps in one HIP graph launch.  Prints one
 JSON line.  ``value`` is cell-DoF updates per second per RK stage (all
 instances, inputs resident in HBM before the timed region).
 
-    python bench.py [--steps K] [--warmup W] [--workload c4|c2|c3|c3f32|c5|nodc]
+    python bench.py [--steps K] [--warmup W] [--workload c4|c2|c3|c3f32|c5|nodc|ek]
 """
 import argparse
 import glob
@@ -75,6 +75,8 @@ def workload(name):
         return "c5_degenerate_3d_256cubed_fp32_si", [W.config5()]
     if name == "nodc":
         return "nodc_ek_batched_1024x8192_1d_fp64", W.config_nodc()
+    if name == "ek":
+        return "ek_dirichlet_batched_1024x8192_1d_fp64", W.config_ek()
     raise SystemExit("unknown workload " + name)
 
 

@@ -68,6 +68,21 @@ typedef enum {
                          five stages, two more state buffers */
 } af_integrator;
 
+/* Ends of axis 0 (1D problems).  The paper runs its Examples 6.5-6.8 with
+ * Dirichlet or outflow ends but states no ghost treatment; the one used:
+ * every value beyond the domain -- ghost cell averages, ghost point values
+ * and both boundary points x_{-1/2}, x_{N-1/2} -- is the end's boundary
+ * value: the Dirichlet value, or for outflow the average of the adjacent
+ * boundary cell.  The stored point value at x_{N-1/2} (index N-1) is not
+ * evolved: a stage writes the boundary value into it (its input value is
+ * ignored; its right-hand side is 0).  The mass changes by the boundary
+ * fluxes. */
+typedef enum {
+    AF_BC_PERIODIC = 0,
+    AF_BC_DIRICHLET = 1,  /* u = bc_value at the end */
+    AF_BC_OUTFLOW = 2     /* zero-order extrapolation of the boundary cell's average */
+} af_bc;
+
 /* Form of the diffusion discretization. */
 typedef enum {
     AF_DIFF_DC = 0,   /* doubly conservative (Secs. 2.2, 4): the paper's method */
@@ -100,6 +115,11 @@ typedef struct {
     int integrator;          /* af_integrator */
     int diffusion_form;      /* af_diffusion_form; AF_DIFF_NODC needs dim = 1 and no
                                 blending (else AF_ERR_UNSUPPORTED) */
+    int bc[2];               /* af_bc of the low and high end of axis 0: both periodic or
+                                neither (AF_ERR_ARG); non-periodic ends need dim = 1 and no
+                                blending (AF_ERR_UNSUPPORTED) */
+    double bc_value[2];      /* Dirichlet values; with the limiter inside [umin, umax]
+                                (AF_ERR_BOUNDS, checked when the bounds are known) */
 } af_problem;
 
 typedef struct {

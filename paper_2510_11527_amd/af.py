@@ -20,6 +20,7 @@ STATUS_NAMES = {0: "AF_OK", -1: "AF_ERR_ARG", -2: "AF_ERR_ALLOC", -3: "AF_ERR_DE
 FLUX = {"linear": 0, "quad": 1, "bl": 2, "bl_grav": 3}
 DIFF = {"linear": 0, "power": 1, "deadzone": 2, "bl": 3, "ramp2": 4}
 DIFFUSION_FORMS = {"dc": 0, "nodc": 1}
+BC_KINDS = {"periodic": 0, "dirichlet": 1, "outflow": 2}
 INTEGRATORS = {"ssprk3": 0, "euler": 1, "ssprk54": 2}
 
 EXPORTS = ["af_create", "af_destroy", "af_set_state", "af_get_state", "af_step", "af_residual", "af_norms",
@@ -46,6 +47,8 @@ class AfProblem(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("integrator", ctypes.c_int),
         ("diffusion_form", ctypes.c_int),
+        ("bc", ctypes.c_int * 2),
+        ("bc_value", ctypes.c_double * 2),
     ]
 
 
@@ -132,6 +135,11 @@ def make_problem(spec, precision=None, integrator="ssprk3"):
     P.precision = int(precision or spec.get("precision", 64))
     P.integrator = INTEGRATORS[integrator]
     P.diffusion_form = DIFFUSION_FORMS[spec.get("diffusion_form", "dc")]
+    bc = spec.get("bc", ("periodic", "periodic"))
+    for e in range(2):  # each end: "periodic", "outflow" or ("dirichlet", value)
+        kind = bc[e] if isinstance(bc[e], str) else bc[e][0]
+        P.bc[e] = BC_KINDS[kind]
+        P.bc_value[e] = 0.0 if isinstance(bc[e], str) else float(bc[e][1])
     return P
 
 

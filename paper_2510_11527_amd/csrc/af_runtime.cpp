@@ -49,6 +49,7 @@ struct af_ctx {
     // the last stage of the previous step reduced the min / max averages of
     // every instance, so the next step's CFL needs no wave-speed pass
     bool keys_fresh = false;
+    bool open = false;   // some instance has non-periodic ends
     std::string err;
 };
 
@@ -299,6 +300,19 @@ af_status validate(const af_problem &P, int idx)
         return bad(AF_ERR_ARG, "unknown diffusion form");
     if (P.diffusion_form == AF_DIFF_NODC && (P.dim != 1 || P.si_blend))
         return bad(AF_ERR_UNSUPPORTED, "the diffusion form of App. A is one-dimensional and unblended");
+    for (int e = 0; e < 2; e++)
+        if (P.bc[e] < AF_BC_PERIODIC || P.bc[e] > AF_BC_OUTFLOW) return bad(AF_ERR_ARG, "unknown boundary kind");
+    if ((P.bc[0] == AF_BC_PERIODIC) != (P.bc[1] == AF_BC_PERIODIC))
+        return bad(AF_ERR_ARG, "both ends periodic or neither");
+    if (P.bc[0] != AF_BC_PERIODIC && (P.dim != 1 || P.si_blend))
+        return bad(AF_ERR_UNSUPPORTED, "non-periodic ends are supported for unblended 1D problems");
+    for (int e = 0; e < 2; e++) {
+        if (P.bc[e] != AF_BC_DIRICHLET) continue;
+        if (!std::isfinite(P.bc_value[e])) return bad(AF_ERR_ARG, "Dirichlet value must be finite");
+        if (P.limiter && !std::isnan(P.umin) && !std::isnan(P.umax) &&
+            !(P.bc_value[e] >= P.umin && P.bc_value[e] <= P.umax))
+            return bad(AF_ERR_BOUNDS, "Dirichlet value outside [umin, umax]");
+    }
     return AF_OK;
 }
 
@@ -316,7 +330,7 @@ void drop_graph(af_ctx *c)
 
 // Fluxes with convex |f'| (linear, quadratic): the CFL wave speed is a
 // function of the min / max average, which the last stage of a step reduces.
-bool cfl_from_keys(const af_ctx *c) { return (c->caps & af4::kCapQF) != 0; }
+bool cfl_from_keys(const af_ctx *c) { return (c->caps & af4::kCapQF) != 0 && !c->open; }
 
 // Work list (instance, tile) for the current variant; instances are kept
 // contiguous so that one instance can be launched alone.
@@ -492,6 +506,8 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
     c->prec = probs[0].precision;
     c->lim = !!probs[0].limiter;
     c->si = !!probs[0].si_blend;
+    for (int i = 0; i < n_inst; i++)
+        if (probs[i].bc[0] != AF_BC_PERIODIC) c->open = true;
     c->integ = probs[0].integrator;
     c->prob.assign(probs, probs + n_inst);
     c->ih.resize(n_inst);
@@ -528,6 +544,10 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
         I.cfl = P.cfl;
         I.si_gamma = P.si_blend ? P.si_gamma : 0.0;
         I.nodc = P.diffusion_form == AF_DIFF_NODC;
+        for (int e = 0; e < 2; e++) {
+            I.bc[e] = P.bc[e];
+            I.bcv[e] = P.bc[e] == AF_BC_DIRICHLET ? P.bc_value[e] : 0.0;
+        }
         if (!std::isnan(P.umin) && !std::isnan(P.umax)) derive_bounds_params(I, P, P.dim);
         set_f32_params(I);
     }
@@ -685,10 +705,22 @@ af_status af_set_state(af_ctx *c, int inst, const double *const *dofs, double t)
     if (derive && !c->have_state[inst]) {
         umin = *std::min_element(r.begin(), r.end());
         umax = *std::max_element(r.begin(), r.end());
+        for (int e = 0; e < 2; e++)  // Dirichlet data bound the solution too
+            if (P.bc[e] == AF_BC_DIRICHLET) {
+                const double g = c->prec == 32 ? (double)(float)P.bc_value[e] : P.bc_value[e];
+                umin = std::min(umin, g);
+                umax = std::max(umax, g);
+            }
     }
-    if (c->lim)
+    if (c->lim) {
         for (double v : r)
             if (v < umin || v > umax) return fail(c, AF_ERR_BOUNDS, "af_set_state: DoF outside [umin, umax]");
+        for (int e = 0; e < 2; e++) {
+            const double g = c->prec == 32 ? (double)(float)P.bc_value[e] : P.bc_value[e];
+            if (P.bc[e] == AF_BC_DIRICHLET && !(g >= umin && g <= umax))
+                return fail(c, AF_ERR_BOUNDS, "af_set_state: Dirichlet value outside [umin, umax]");
+        }
+    }
     if (derive && !c->have_state[inst]) {
         I.umin = umin;
         I.umax = umax;

@@ -28,6 +28,7 @@ __global__ void __launch_bounds__(256) wavespeed_kernel(const InstDev *inst, con
         kdx2[l] = I.kmax * I.idx2[l];
     }
     const double big = 1e6 * fmax(fmax(fabs(I.umin), fabs(I.umax)), 1.0);
+    const bool open = dim == 1 && I.bc[0] != 0;  // non-periodic ends: ghost values at both end faces
     double w = 0.0;
     bool bad = false;
     for (int r = r0; r < r1; r++) {
@@ -38,7 +39,12 @@ __global__ void __launch_bounds__(256) wavespeed_kernel(const InstDev *inst, con
         for (int i = threadIdx.x; i < n0; i += blockDim.x) {
             const double uc = (double)u[row + i];
             if (!(fabs(uc) <= big)) bad = true;  // also catches NaN
-            const double ux = (double)u[row + (i + 1 == n0 ? 0 : i + 1)];
+            double ux = (double)u[row + (i + 1 == n0 ? 0 : i + 1)];
+            if (open && i + 1 == n0) ux = I.bc[1] == 1 ? (double)(T)I.bcv[1] : uc;  // the face x_{N-1/2}
+            if (open && i == 0) {  // the face x_{-1/2}
+                const double ug = I.bc[0] == 1 ? (double)(T)I.bcv[0] : uc;
+                w = fmax(w, P.alpha_int(0, ug, uc) * idx[0] + kdx2[0]);
+            }
             w = fmax(w, P.alpha_int(0, uc, ux) * idx[0] + kdx2[0]);
             if (dim >= 2) w = fmax(w, P.alpha_int(1, uc, (double)u[rowy + i]) * idx[1] + kdx2[1]);
             if (dim >= 3) w = fmax(w, P.alpha_int(2, uc, (double)u[rowz + i]) * idx[2] + kdx2[2]);

@@ -345,6 +345,16 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
     const double dtd = p.st[wk.x].dt;
     // the 1D variant without double conservation (App. A)
     const bool nodc = D == 1 && I.nodc != 0;
+    // Non-periodic ends (1D): every value beyond the domain and both boundary
+    // points take the end's boundary value (Dirichlet value, or for outflow
+    // the boundary cell's average); the stored point value at x_{N-1/2} is
+    // not evolved but set to the boundary value by every stage.
+    const bool open = D == 1 && I.bc[0] != 0;
+    T bv0 = T(0), bv1 = T(0);
+    if (open) {
+        bv0 = I.bc[0] == 1 ? (T)I.bcv[0] : in[0];
+        bv1 = I.bc[1] == 1 ? (T)I.bcv[1] : in[n0 - 1];
+    }
 
     const T inf = __builtin_huge_val();
     T vlo = inf, vhi = -inf;  // min / max of the averages written
@@ -377,6 +387,18 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
 
     // ---- A: stage tile + halo (averages -> ub, point values -> half grid)
     box_loop<G::R0, G::R1, G::R2, NT>([&](int x, int y, int z) {
+        if (open) {
+            const int gr = ox + x - G::H0;
+            if (gr < 0 || gr >= n0) {
+                const T g = gr < 0 ? bv0 : bv1;
+                ub[G::cidx(x, 0, 0)] = g;
+                hg[G::hidx(2 * x + 1, 0, 0)] = g;
+                return;
+            }
+            ub[G::cidx(x, 0, 0)] = in[gr];
+            hg[G::hidx(2 * x + 1, 0, 0)] = gr == n0 - 1 ? bv1 : in[kst + gr];
+            return;
+        }
         int gx = wrap_index(ox + x - G::H0, n0);
         int gy = D >= 2 ? wrap_index(oy + y - G::H1, n1) : 0;
         int gz = D >= 3 ? wrap_index(oz + z - G::H2, n2) : 0;
@@ -398,6 +420,10 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
         constexpr T iW = D == 1 ? T(0.25) : (D == 2 ? T(0.0625) : T(0.015625));
         box_loop<E0, E1, E2, NT>([&](int i, int j, int k) {
             const int x = i + L0, y = j + L1, z = k + L2;
+            if (open && (ox + x - G::H0 < 0 || ox + x - G::H0 >= n0)) {
+                hg[G::hidx(2 * x, 0, 0)] = ox + x - G::H0 < 0 ? bv0 : bv1;  // ghost centre
+                return;
+            }
             T acc = S * ub[G::cidx(x, y, z)];
 #pragma unroll
             for (int oz = (D >= 3 ? -1 : 0); oz <= (D >= 3 ? 1 : 0); oz++)
@@ -524,11 +550,16 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                 R += conv + d2;
             }
             if (!own) continue;
+            // the boundary point x_{N-1/2} of non-periodic ends: right-hand
+            // side 0; a stage gives it the boundary value (outflow: the new
+            // average, written with the average below)
+            const bool bpt = open && gi == n0 - 1;
             if (residual) {
-                out[zk * kst + gi] = R;
+                out[zk * kst + gi] = bpt ? T(0) : R;
                 continue;
             }
-            T v = u0 + dt * R;
+            if (bpt && I.bc[1] != 1) continue;
+            T v = bpt ? bv1 : u0 + dt * R;
             if (!isfinite(v)) bad = true;
             if constexpr (LIM) v = clampb(v, P.umin, P.umax);
             v = stage_combine(p, v, un[zk * kst + gi], x1 ? x1[zk * kst + gi] : T(0), u0);
@@ -704,6 +735,13 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
             T c = clampb(v, P.umin, P.umax);
             clamp_mag = fmax(clamp_mag, (double)fabs(c - v));
             v = c;
+        }
+        if (open && gi == n0 - 1 && I.bc[1] != 1) {
+            // outflow: the boundary point takes the stage's average, combined
+            // like every point value
+            T b = stage_combine(p, v, un[kst + gi], x1 ? x1[kst + gi] : T(0), in[kst + gi]);
+            if constexpr (LIM) b = clampb(b, P.umin, P.umax);
+            out[kst + gi] = b;
         }
         v = stage_combine(p, v, un[gi], x1 ? x1[gi] : T(0), u);
         if constexpr (LIM) {

@@ -309,6 +309,37 @@ def config_nodc(seed=SEED_BASE + 6, n_inst=1024, n=8192, cfl=0.075, precision=64
     return out
 
 
+def config_ek(seed=SEED_BASE + 7, n_inst=1024, n=8192, cfl=0.075, precision=64, diffusion_form="dc",
+              limiter=True):
+    """Batch of 1D problems of the Evje-Karlsen example as the paper runs it
+    (Example 6.5): [-1, 1] with Dirichlet ends u(-1) = 1, u(1) = 0, f = u^2/4;
+    the example's C^1 potential is replaced by a = max(0, u - 1/2) (kappa
+    jumps from 0 to 1 at u = 1/2 instead of ramping over [0.5, 0.6]).  The
+    initial profile (1, then -2.5 (x - s) on [s - 0.4, s), then 0) has its
+    ramp shifted by s ~ U[-0.3, 0.3] per instance; averages exact, point
+    values sampled, the boundary point x_{N-1/2} holding the Dirichlet value;
+    bounds [0, 1].  Returns a list of (spec, dofs)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    dx = 2.0 / n
+    edges = -1.0 + dx * np.arange(n + 1)
+    for i in range(n_inst):
+        sh = rng.uniform(-0.3, 0.3)
+        y = edges - sh  # the unshifted profile's coordinate; y in [-1.3, 1.3]
+        G = np.where(y < -0.4, y + 1.0, np.where(y < 0.0, 0.8 - 1.25 * y * y, 0.8))
+        avg = (G[1:] - G[:-1]) / dx
+        yf = y[1:]
+        pv = np.where(yf < -0.4, 1.0, np.where(yf < 0.0, -2.5 * yf, 0.0))
+        pv[-1] = 0.0
+        dofs = round_to([np.clip(avg, 0.0, 1.0), pv], precision)
+        spec = dict(name="ek_dirichlet_1d[%d]" % i, dim=1, n=[n], lo=[-1.0], hi=[1.0], flux=[("quad", 0.25, 0.0)],
+                    diff=("deadzone", 1.0, 0.5), umin=0.0, umax=1.0, cfl=cfl, limiter=limiter, si=False,
+                    si_gamma=1.0, precision=precision, t_end=None, steps=None, diffusion_form=diffusion_form,
+                    bc=(("dirichlet", 1.0), ("dirichlet", 0.0)))
+        out.append((spec, dofs))
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Small problems of the paper's examples, used by tests
 # ---------------------------------------------------------------------------

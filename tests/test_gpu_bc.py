@@ -1,0 +1,150 @@
+"""GPU parity of the non-periodic ends (1D Dirichlet and outflow), called
+through the C ABI, against the FP64 CPU oracle on identical seeded inputs:
+right-hand side, limited and unlimited forward-Euler stages, SSP-RK3 and
+SSP-RK(5,4) steps of the Dirichlet Evje-Karlsen workload in both diffusion
+forms, the CFL step with the end faces, a batch mixing periodic and open
+instances, and argument validation."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_11527_amd import af
+from paper_2510_11527_amd import workloads as W
+from gpu_common import TOL, gpu_run, prepare, rel_l1
+
+pytestmark = pytest.mark.gpu
+
+BCS = [(("dirichlet", 0.8), ("dirichlet", 0.1)), ("outflow", "outflow"), (("dirichlet", 1.0), "outflow"),
+       ("outflow", ("dirichlet", 0.0))]
+CASES = [(("quad", 0.5, 0.0), ("deadzone", 0.05, 0.25)), (("bl", 0.0, 0.0), ("power", 0.05, 2.0)),
+         (("linear", -0.7, 0.0), ("bl", 0.01, 0.0)), (("bl_grav", 0.0, 5.0), ("ramp2", 0.1, 0.3))]
+
+
+def note(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def spec1(n, fl, df, bc, limiter=False, precision=64, form="dc"):
+    return dict(name="t", dim=1, n=[n], lo=[0.0], hi=[1.3], flux=[fl], diff=df, umin=0.0, umax=1.0,
+                limiter=limiter, si=False, si_gamma=1.0, precision=precision, cfl=0.15, diffusion_form=form, bc=bc)
+
+
+def state1(n, rng, bc):
+    U = [rng.uniform(0, 1, size=n) for _ in range(2)]
+    U[0] = np.where(rng.uniform(size=n) < 0.6, U[0], rng.choice([0.0, 1.0], size=n))
+    if not isinstance(bc[1], str):
+        U[1][-1] = bc[1][1]  # the boundary point holds the Dirichlet value
+    else:
+        U[1][-1] = U[0][-1]
+    return U
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("form", ["dc", "nodc"])
+def test_open_ends_residual_matches_oracle(prec, form):
+    rng = np.random.default_rng(800 + prec + (form == "nodc"))
+    for k, bc in enumerate(BCS):
+        fl, df = CASES[k]
+        spec = spec1(47, fl, df, bc, precision=prec, form=form)
+        s, U = prepare(spec, state1(47, rng, bc), prec)
+        note("bc residual prec=%d form=%s bc=%s flux=%s" % (prec, form, bc, fl[0]))
+        ctx = af.Context(s)
+        ctx.set_state(0, U)
+        R = ctx.residual(0)
+        ctx.close()
+        Ro = oracle.rhs(oracle.problem(s), U)
+        err = rel_l1(R, Ro)
+        assert err <= TOL[prec] * (10 if prec == 32 else 1), err
+        assert R[1][-1] == 0.0
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("lim", [False, True])
+def test_open_ends_forward_euler_stage_matches_oracle(prec, lim):
+    rng = np.random.default_rng(900 + prec + 3 * lim)
+    for k, bc in enumerate(BCS):
+        for form in ("dc", "nodc"):
+            fl, df = CASES[(k + (form == "nodc")) % 4]
+            spec = spec1(53, fl, df, bc, limiter=lim, precision=prec, form=form)
+            s, U = prepare(spec, state1(53, rng, bc), prec)
+            P = oracle.problem(s)
+            dt = oracle.dt_cfl(P, U, s["cfl"])
+            note("bc fe prec=%d lim=%d form=%s bc=%s flux=%s dt=%.3e" % (prec, lim, form, bc, fl[0], dt))
+            V, t, used, nrm = gpu_run(s, U, dts=[dt], integrator="euler")
+            Vo, dg = oracle.fe(P, U, dt)
+            err = rel_l1(V, Vo)
+            assert err <= TOL[prec], err
+            if lim:
+                assert min(v.min() for v in V) >= s["umin"] and max(v.max() for v in V) <= s["umax"]
+
+
+@pytest.mark.parametrize("integ", ["ssprk3", "ssprk54"])
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("form", ["dc", "nodc"])
+def test_dirichlet_evje_karlsen_steps_match_oracle(integ, prec, form):
+    """Ten steps of the Evje-Karlsen workload with its Dirichlet ends (reduced
+    size), the oracle's CFL steps prescribed to both sides."""
+    spec, U = W.config_ek(n_inst=1, n=120, precision=prec, diffusion_form=form)[0]
+    s, U = prepare(spec, U, prec)
+    P = oracle.problem(s)
+    Uo, t, dts = oracle.run(P, U, nsteps=10, cfl=s["cfl"], integrator=integ)
+    note("ek steps %s prec=%d form=%s dt0=%.3e" % (integ, prec, form, dts[0]))
+    V, tg, used, nrm = gpu_run(s, U, dts=dts, integrator=integ)
+    err = rel_l1(V, Uo)
+    assert err <= TOL[prec], err
+    assert min(v.min() for v in V) >= s["umin"] and max(v.max() for v in V) <= s["umax"]
+    assert V[1][-1] == 0.0
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_open_ends_cfl_step_matches_oracle(prec):
+    """The CFL step includes the two end faces with their ghost values: a
+    Dirichlet value far from the data sets the wave speed."""
+    rng = np.random.default_rng(1000 + prec)
+    for bc in [(("dirichlet", 0.95), ("dirichlet", 0.0)), ("outflow", "outflow")]:
+        spec = spec1(64, ("quad", 2.0, 0.0), ("power", 0.001, 2.0), bc, limiter=True, precision=prec)
+        U = [rng.uniform(0.2, 0.4, size=64) for _ in range(2)]
+        U[1][-1] = bc[1][1] if not isinstance(bc[1], str) else U[0][-1]
+        s, U = prepare(spec, U, prec)
+        s["umin"], s["umax"] = 0.0, 1.0
+        P = oracle.problem(s)
+        dto = oracle.dt_cfl(P, U, s["cfl"])
+        V, t, used, nrm = gpu_run(s, U, nsteps=1)
+        note("bc cfl prec=%d bc=%s dt %.17g vs %.17g" % (prec, bc, used[0], dto))
+        assert abs(used[0] - dto) <= (1e-15 if prec == 64 else 1e-6) * dto
+
+
+def test_open_and_periodic_instances_batched():
+    """A batch mixing periodic App. A instances and Dirichlet instances of
+    both diffusion forms, each with its own CFL step, against the oracle."""
+    items = W.config_nodc(n_inst=2, n=80)
+    items += W.config_ek(n_inst=2, n=96)
+    items += [(dict(s, diffusion_form="nodc", name="ek_nodc"), U) for s, U in W.config_ek(n_inst=1, n=64, seed=9)]
+    ctx = af.Context([s for s, _ in items])
+    for i, (_, U) in enumerate(items):
+        ctx.set_state(i, U)
+    ctx.step(6)
+    for i, (s, U) in enumerate(items):
+        V, t = ctx.get_state(i)
+        Uo, to, _ = oracle.run(oracle.problem(s), U, nsteps=6, cfl=s["cfl"])
+        note("bc batch instance %d %s" % (i, s["name"]))
+        assert rel_l1(V, Uo) <= TOL[64]
+        assert abs(t - to) <= 1e-15 * max(1.0, to)
+    ctx.close()
+
+
+def test_open_end_validation():
+    spec, U = W.config_ek(n_inst=1, n=32)[0]
+    with pytest.raises(af.AFError) as e:
+        af.Context(dict(spec, bc=("periodic", "outflow")))
+    assert e.value.status == af.AF_ERR_ARG
+    with pytest.raises(af.AFError) as e:
+        af.Context(dict(spec, bc=(("dirichlet", 1.5), "outflow")))
+    assert e.value.status == af.AF_ERR_BOUNDS
+    s2, _ = W.config2(n=16)
+    with pytest.raises(af.AFError) as e:
+        af.Context(dict(s2, bc=("outflow", "outflow")))
+    assert e.value.status == af.AF_ERR_UNSUPPORTED
