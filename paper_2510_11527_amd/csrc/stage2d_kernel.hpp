@@ -28,64 +28,6 @@ struct V2 {
     T x, y;
 };
 
-template <class T>
-__device__ __forceinline__ T fast_rcp(T v)
-{
-    return T(1) / v;
-}
-template <>
-__device__ __forceinline__ float fast_rcp<float>(float v)
-{
-    return __builtin_amdgcn_rcpf(v);
-}
-
-// max / min that propagate NaN (IEEE maximum / minimum): for FP32 they map to
-// v_maximum3 / v_minimum3 and, unlike fmax / fmin, need no quieting of
-// operands loaded from memory; a NaN operand makes the result NaN, which the
-// non-finite check of the update then reports
-template <class T>
-__device__ __forceinline__ T vmax(T a, T b)
-{
-    if constexpr (sizeof(T) == 4) return __builtin_elementwise_maximum(a, b);
-    else return fmax(a, b);
-}
-template <class T>
-__device__ __forceinline__ T vmin(T a, T b)
-{
-    if constexpr (sizeof(T) == 4) return __builtin_elementwise_minimum(a, b);
-    else return fmin(a, b);
-}
-
-// largest t in [0,1] with every low-order state + t * correction in bounds,
-// given the common correction magnitude s and the smallest gap to the bound
-// the states move towards (selects only; s == 0 gives 0 * inf -> NaN, which
-// fmin turns into 1; a gap of s or more may give 1 - ulp, which only
-// shortens the correction)
-template <class T>
-__device__ __forceinline__ T theta_from_gap(T gap, T s)
-{
-    return fmin(fmax(gap, T(0)) * fast_rcp(s), T(1));
-}
-
-// smallest distance to the bound that a correction of sign(s) moves the
-// states z+ (moved by +s) and z- (moved by -s) towards
-template <class T>
-__device__ __forceinline__ T gap2(T s, T zp, T zm, T umin, T umax)
-{
-    const bool pos = s > T(0);
-    const T up = pos ? zp : zm, down = pos ? zm : zp;  // the state moving up, the one moving down
-    return fmin(umax - up, down - umin);
-}
-
-// same for two states moved by +s (a1, a2) and two moved by -s (b1, b2)
-template <class T>
-__device__ __forceinline__ T gap4(T s, T a1, T a2, T b1, T b2, T umin, T umax)
-{
-    const bool pos = s > T(0);
-    const T top = pos ? vmax(a1, a2) : vmax(b1, b2), bottom = pos ? vmin(b1, b2) : vmin(a1, a2);
-    return fmin(umax - top, bottom - umin);
-}
-
 // FT: keep f_x, f_y in the half-grid table (else recomputed from u; only
 // for quadratic fluxes)
 template <class T, bool LIM, bool QF, bool FT, int TX, int TY, int NT>

@@ -29,6 +29,19 @@ namespace af4 {
 enum : int { kFLinear = 0, kFQuad = 1, kFBL = 2, kFBLGrav = 3 };
 enum : int { kALinear = 0, kAPower = 1, kADeadzone = 2, kABL = 3, kARamp2 = 4 };
 
+// 1/v: an IEEE division in FP64; in FP32 the hardware reciprocal (within
+// 1 ulp), which spares the ten-instruction correctly rounded division
+template <class T>
+__device__ __forceinline__ T fast_rcp(T v)
+{
+    return T(1) / v;
+}
+template <>
+__device__ __forceinline__ float fast_rcp<float>(float v)
+{
+    return __builtin_amdgcn_rcpf(v);
+}
+
 // p0 * u^p (powers other than 1, 2, 3): kept out of line so that the
 // stage kernels do not carry a pow expansion at every evaluation site
 template <class T>
@@ -86,7 +99,7 @@ struct Phys {
         if (k == kFQuad) return fc[l] * u * u;
         if (k == kFLinear) return fc[l] * u;
         T v = T(1) - u;
-        T q = u * u / (u * u + v * v);
+        T q = u * u * fast_rcp(u * u + v * v);
         if (k == kFBL) return q;
         return q * (T(1) - fg[l] * v * v);
     }
@@ -99,9 +112,10 @@ struct Phys {
         if (k == kFLinear) return fabs(fc[l]);
         T v = T(1) - u;
         T den = u * u + v * v;
-        T d1 = T(2) * u * v / (den * den);
+        const T r = fast_rcp(den);
+        T d1 = T(2) * u * v * (r * r);
         if (k == kFBL) return fabs(d1);
-        T q = u * u / den;
+        T q = u * u * r;
         return fabs(d1 * (T(1) - fg[l] * v * v) + q * T(2) * fg[l] * v);
     }
 
@@ -141,15 +155,51 @@ struct Phys {
     }
 };
 
-// Theta(zL, zH) of Sec. 5.1.1: largest t in [0,1] with (1-t) zL + t zH in bounds
+// max / min that propagate NaN (IEEE maximum / minimum): for FP32 they map to
+// v_maximum3 / v_minimum3 and, unlike fmax / fmin, need no quieting of
+// operands loaded from memory; a NaN operand makes the result NaN, which the
+// non-finite check of the update then reports
 template <class T>
-__device__ __forceinline__ T Theta(T zL, T zH, T umin, T umax)
+__device__ __forceinline__ T vmax(T a, T b)
 {
-    T t;
-    if (zH < umin) t = (zL - umin) / (zL - zH);
-    else if (zH > umax) t = (zL - umax) / (zL - zH);
-    else return T(1);
-    return t > T(0) ? fmin(t, T(1)) : T(0);
+    if constexpr (sizeof(T) == 4) return __builtin_elementwise_maximum(a, b);
+    else return fmax(a, b);
+}
+template <class T>
+__device__ __forceinline__ T vmin(T a, T b)
+{
+    if constexpr (sizeof(T) == 4) return __builtin_elementwise_minimum(a, b);
+    else return fmin(a, b);
+}
+
+// largest t in [0,1] with every low-order state + t * correction in bounds,
+// given the common correction magnitude s and the smallest gap to the bound
+// the states move towards (selects only; s == 0 gives 0 * inf -> NaN, which
+// fmin turns into 1; a gap of s or more may give 1 - ulp, which only
+// shortens the correction)
+template <class T>
+__device__ __forceinline__ T theta_from_gap(T gap, T s)
+{
+    return fmin(fmax(gap, T(0)) * fast_rcp(s), T(1));
+}
+
+// smallest distance to the bound that a correction of sign(s) moves the
+// states z+ (moved by +s) and z- (moved by -s) towards
+template <class T>
+__device__ __forceinline__ T gap2(T s, T zp, T zm, T umin, T umax)
+{
+    const bool pos = s > T(0);
+    const T up = pos ? zp : zm, down = pos ? zm : zp;  // the state moving up, the one moving down
+    return fmin(umax - up, down - umin);
+}
+
+// same for two states moved by +s (a1, a2) and two moved by -s (b1, b2)
+template <class T>
+__device__ __forceinline__ T gap4(T s, T a1, T a2, T b1, T b2, T umin, T umax)
+{
+    const bool pos = s > T(0);
+    const T top = pos ? vmax(a1, a2) : vmax(b1, b2), bottom = pos ? vmin(b1, b2) : vmin(a1, a2);
+    return fmin(umax - top, bottom - umin);
 }
 
 // v clamped to [lo, hi] (lo <= hi); FP32 uses the median of three, one
@@ -639,8 +689,9 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                     // the App. A flux it carries one (factor K)
                     const T df = fH - fL;
                     const T s3 = (nodc ? T(1) : T(3)) * K * mu[l] * df;
-                    const T tc = fmin(Theta(up, up - s3, P.umin, P.umax), Theta(um, um + s3, P.umin, P.umax));
-                    F = fL + tc * df;
+                    // min(Theta(up, up - s3), Theta(um, um + s3)) with one reciprocal
+                    const T gap = gap2<T>(s3, um, up, P.umin, P.umax);
+                    F = fL + theta_from_gap<T>(gap, (T)fabs(s3)) * df;
                 }
             }
             fl[G::face_off(l) + id] = F;
@@ -689,9 +740,9 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                     const T pC = ulp[f0 + step], mR = ulm[f0 + step];    // u^{L,+}_c, u^{L,-}_{c+1}
                     const T da = aH - aL;
                     const T s3 = T(3) * K * nu[l] * da;
-                    const T td = fmin(fmin(Theta(pL, pL + s3, P.umin, P.umax), Theta(pC, pC - s3, P.umin, P.umax)),
-                                      fmin(Theta(mC, mC - s3, P.umin, P.umax), Theta(mR, mR + s3, P.umin, P.umax)));
-                    Pv = aL + td * da;
+                    // min of the four Theta's (pL, mR move by +s3; pC, mC by -s3)
+                    const T gap = gap4<T>(s3, pL, mR, pC, mC, P.umin, P.umax);
+                    Pv = aL + theta_from_gap<T>(gap, (T)fabs(s3)) * da;
                 }
             }
             pc[G::cell_off(l) + id] = Pv;
