@@ -892,3 +892,67 @@ def test_open_ends_match_printed_stencils_on_ghost_filled_grid(bc, c, k0):
     pv[-1] = 0.0
     np.testing.assert_allclose(R[0], avg, rtol=0, atol=1e-12 * (1 + np.abs(avg).max()))
     np.testing.assert_allclose(R[1], pv, rtol=0, atol=1e-12 * (1 + np.abs(pv).max()))
+
+
+# ---------------------------------------------------------------------------
+# Smoothness-indicator blending (Sec. 5.1.3)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d", [1, 2])
+@pytest.mark.parametrize("lim", [False, True])
+def test_si_with_gamma_zero_is_unblended(d, lim):
+    """gamma = 0 makes every blending coefficient exp(0) = 1."""
+    rng = np.random.default_rng(300 + d + 7 * lim)
+    spec, U = _random_problem(rng, d, ("quad", 0.5, 0.0), ("deadzone", 0.05, 0.25))
+    spec["limiter"] = lim
+    dt = oracle.dt_cfl(oracle.problem(spec), U, 0.2 / d)
+    V0, _ = oracle.fe(oracle.problem(spec), U, dt)
+    V1, _ = oracle.fe(oracle.problem(dict(spec, si=True, si_gamma=0.0)), U, dt)
+    for a, b in zip(V0, V1):
+        np.testing.assert_allclose(b, a, rtol=0, atol=1e-15)
+
+
+def test_si_large_gamma_gives_the_low_order_averages():
+    """On data with no locally linear stretch (s > 0 everywhere), gamma -> inf
+    blends every flux and potential fully to its low-order value, so the
+    limited average update is the theta = 0 scheme (itself pinned to the
+    textbook LLF + central scheme)."""
+    rng = np.random.default_rng(44)
+    for d in (1, 2):
+        n = {1: 40, 2: 12}[d]
+        spec = dict(dim=d, n=[n] * d, lo=[0.0] * d, hi=[1.0] * d, flux=[("bl_grav", 0.0, 5.0)] * d,
+                    diff=("ramp2", 0.1, 0.3), umin=0.0, umax=1.0, limiter=True)
+        U = [rng.uniform(0.05, 0.95, size=n ** d) for _ in range(2 ** d)]
+        dt = oracle.dt_cfl(oracle.problem(spec), U, 0.2 / d)
+        Vs, _ = oracle.fe(oracle.problem(dict(spec, si=True, si_gamma=1e7)), U, dt)
+        V0, _ = oracle.fe(oracle.problem(spec, theta_mode="zero"), U, dt)
+        np.testing.assert_allclose(Vs[0], V0[0], rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("gamma", [0.7, 5.0])
+def test_si_blended_average_matches_printed_formulas(gamma):
+    """Unlimited 1D update with f = c u, a = k0 u: the blended flux and
+    potential written out from the printed definitions -- s~ and its (1,4,1)/6
+    smoothing, theta^{c,s} = exp(-gamma (s_i + s_{i+1})/2), theta^{d,s} =
+    exp(-gamma s_i), the AF flux f(u_{i+1/2}) against the LLF flux, the
+    potential of Prop. 2.1 against a(ubar) -- give the oracle's averages."""
+    N, dx, c, k0 = 17, 0.23, 0.9, 0.4
+    P = oracle.problem(spec1d(N, N * dx, ("linear", c, 0.0), ("linear", k0, 0.0), si=True, si_gamma=gamma))
+    rng = np.random.default_rng(8)
+    ub, up = rng.uniform(0.1, 1.0, N), rng.uniform(0.1, 1.0, N)
+    dt = 0.01
+    V, _ = oracle.fe(P, [ub, up], dt)
+    um, upp = np.roll(ub, 1), np.roll(ub, -1)
+    st = np.abs(um - 2 * ub + upp) / (np.abs(um) + 2 * np.abs(ub) + np.abs(upp) + 1e-13)
+    s = (np.roll(st, 1) + 4 * st + np.roll(st, -1)) / 6
+    thc = np.exp(-gamma * 0.5 * (s + np.roll(s, -1)))         # face i+1/2
+    thd = np.exp(-gamma * s)
+    fH = c * up                                                # f(u_{i+1/2})
+    fL = 0.5 * c * (ub + upp) - 0.5 * abs(c) * (upp - ub)
+    F = thc * fH + (1 - thc) * fL
+    ctr = (6 * ub - np.roll(up, 1) - up) / 4
+    aH = k0 * (-np.roll(up, 1) + 8 * ctr - up) / 6             # Prop. 2.1
+    A = thd * aH + (1 - thd) * k0 * ub
+    mu, nu = dt / dx, dt / dx ** 2
+    avg = ub - mu * (F - np.roll(F, 1)) + nu * (np.roll(A, -1) - 2 * A + np.roll(A, 1))
+    np.testing.assert_allclose(V[0], avg, rtol=0, atol=1e-14)
