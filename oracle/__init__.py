@@ -17,7 +17,8 @@ A problem is described by a plain dict (see
      "umin": 0.0, "umax": 1.0, "limiter": True,
      "si": False, "si_gamma": 1.0, "cfl": 0.075,
      "diffusion_form": "dc",                         # or "nodc" (App. A, 1D)
-     "bc": ("periodic", "periodic")}                 # 1D ends: "outflow" or ("dirichlet", g)
+     "bc": ("periodic", "periodic")}                 # ends of axis 0: "outflow" or ("dirichlet", g);
+                                                     # "bcs": [(lo, hi) per axis] for 2D
 
 DoFs are a list of 2^d numpy float64 arrays in the zeta order of Sec. 4
 (average first), each of prod(n) values with x fastest.
@@ -55,8 +56,8 @@ class OrcProblem(ctypes.Structure):
         ("si_gamma", ctypes.c_double),
         ("theta_mode", ctypes.c_int),
         ("nodc", ctypes.c_int),
-        ("bc", ctypes.c_int * 2),
-        ("bcval", ctypes.c_double * 2),
+        ("bc", (ctypes.c_int * 2) * 3),
+        ("bcval", (ctypes.c_double * 2) * 3),
         ("dx", ctypes.c_double * 3),
         ("kappa_max", ctypes.c_double),
         ("ncrit", ctypes.c_int * 3),
@@ -158,14 +159,23 @@ def problem(spec, theta_mode="computed"):
     P.si_gamma = float(spec.get("si_gamma", 1.0))
     P.theta_mode = THETA_MODES[theta_mode]
     P.nodc = int(spec.get("diffusion_form", "dc") == "nodc")
-    bc = spec.get("bc", ("periodic", "periodic"))
-    for s in range(2):
-        kind = bc[s] if isinstance(bc[s], str) else bc[s][0]
-        P.bc[s] = BC_KINDS[kind]
-        P.bcval[s] = 0.0 if isinstance(bc[s], str) else float(bc[s][1])
+    for l, ends in enumerate(boundary_ends(spec)):
+        for s in range(2):
+            kind = ends[s] if isinstance(ends[s], str) else ends[s][0]
+            P.bc[l][s] = BC_KINDS[kind]
+            P.bcval[l][s] = 0.0 if isinstance(ends[s], str) else float(ends[s][1])
     if lib().orc_setup(ctypes.byref(P)) != 0:
         raise ValueError("oracle: invalid problem")
     return P
+
+
+def boundary_ends(spec):
+    """Per axis, the (low, high) ends of a problem dict: "bcs" lists them per
+    axis; "bc" gives those of axis 0; absent axes are periodic."""
+    ends = list(spec.get("bcs", []))
+    if "bc" in spec and not ends:
+        ends = [spec["bc"]]
+    return ends + [("periodic", "periodic")] * (3 - len(ends))
 
 
 def ncells(P):

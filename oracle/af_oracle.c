@@ -70,8 +70,8 @@ typedef struct {
     double si_gamma;
     int theta_mode;   /* ORC_THETA_*: computed, forced to 1, forced to 0 */
     int nodc;         /* 1: the variant of App. A without double conservation (1D) */
-    int bc[2];        /* ORC_BC_* of the low and high end of axis 0 (1D; both periodic or neither) */
-    double bcval[2];  /* Dirichlet values */
+    int bc[3][2];        /* ORC_BC_* of the low and high end of each axis (both periodic or neither) */
+    double bcval[3][2];  /* Dirichlet values */
     /* derived (filled by orc_setup) */
     double dx[3];
     double kappa_max;
@@ -232,10 +232,12 @@ int orc_setup(orc_problem *P)
 {
     if (P->dim < 1 || P->dim > 3) return -1;
     if (P->nodc && (P->dim != 1 || P->si)) return -1;  /* App. A is a 1D scheme */
-    for (int s = 0; s < 2; s++)
-        if (P->bc[s] < ORC_BC_PERIODIC || P->bc[s] > ORC_BC_OUTFLOW) return -1;
-    if ((P->bc[0] == ORC_BC_PERIODIC) != (P->bc[1] == ORC_BC_PERIODIC)) return -1;
-    if (P->bc[0] != ORC_BC_PERIODIC && (P->dim != 1 || P->si)) return -1;
+    for (int l = 0; l < 3; l++) {
+        for (int s = 0; s < 2; s++)
+            if (P->bc[l][s] < ORC_BC_PERIODIC || P->bc[l][s] > ORC_BC_OUTFLOW) return -1;
+        if ((P->bc[l][0] == ORC_BC_PERIODIC) != (P->bc[l][1] == ORC_BC_PERIODIC)) return -1;
+        if (P->bc[l][0] != ORC_BC_PERIODIC && (l >= P->dim || P->dim == 3 || P->si)) return -1;
+    }
     for (int l = 0; l < 3; l++) {
         if (l >= P->dim) { P->n[l] = 1; P->dx[l] = 1; P->ncrit[l] = 0; continue; }
         if (P->n[l] < 4) return -1;
@@ -279,24 +281,65 @@ static long cell_index(const orc_problem *P, const int c[3])
     return (long)i + (long)P->n[0] * ((long)j + (long)P->n[1] * k);
 }
 
-/* Non-periodic ends (1D).  The paper runs Examples 6.5-6.8 with Dirichlet
- * or outflow boundaries but states no ghost treatment; the reading taken
- * here: every half-grid point beyond the domain, the boundary points
- * x_{-1/2} and x_{N-1/2} included, and every ghost cell average takes one
- * boundary value -- the Dirichlet value, or for outflow the average of the
- * adjacent boundary cell.  The stored boundary point value x_{N-1/2} is not
- * evolved: a stage writes the boundary value into it. */
-static int bc_open(const orc_problem *P) { return P->bc[0] != ORC_BC_PERIODIC; }
-static double bc_value(const orc_problem *P, const double *const *U, int side)
+/* Non-periodic ends (1D and 2D).  The paper runs Examples 6.5-6.9 with
+ * Dirichlet or outflow boundaries but states no ghost treatment; the reading
+ * taken here: a half-grid point on or beyond an open end -- the boundary
+ * points x_{-1/2}, x_{N-1/2} included -- takes a boundary value, and so does
+ * a ghost cell's average (the value at its centre):
+ *   * if one of the ends it lies on or beyond is Dirichlet, the Dirichlet
+ *     value (the lowest such axis first);
+ *   * else (outflow) the mean average of the domain cells whose closure
+ *     contains the point moved onto the boundary (the point clamped to the
+ *     domain along the axes it leaves): one cell in 1D, one or two along an
+ *     edge in 2D, the corner cell at a corner.
+ * The stored point values on the high ends are not unknowns: their input is
+ * ignored, a stage writes the Dirichlet value (Dirichlet) or passes the
+ * input through (outflow), and the right-hand side there is 0. */
+static int axis_open(const orc_problem *P, int l) { return l < P->dim && P->bc[l][0] != ORC_BC_PERIODIC; }
+static int bc_open(const orc_problem *P) { return axis_open(P, 0) || axis_open(P, 1) || axis_open(P, 2); }
+
+/* bit l set: p lies on or beyond an open end of axis l */
+static int ends_of(const orc_problem *P, const int p[3])
 {
-    if (P->bc[side] == ORC_BC_DIRICHLET) return P->bcval[side];
-    return U[0][side == 0 ? 0 : P->n[0] - 1];
+    int m = 0;
+    for (int l = 0; l < 3; l++)
+        if (axis_open(P, l) && (p[l] <= -1 || p[l] >= 2 * P->n[l] - 1)) m |= 1 << l;
+    return m;
+}
+
+static double bc_point(const orc_problem *P, const double *const *U, const int p[3], int m)
+{
+    for (int l = 0; l < 3; l++)
+        if ((m >> l & 1) && P->bc[l][p[l] <= -1 ? 0 : 1] == ORC_BC_DIRICHLET) return P->bcval[l][p[l] <= -1 ? 0 : 1];
+    /* outflow: mean over the cells containing the clamped point */
+    int lo[3], hi[3];
+    for (int l = 0; l < 3; l++) {
+        if (m >> l & 1) {
+            lo[l] = hi[l] = p[l] <= -1 ? 0 : P->n[l] - 1;
+        } else if (p[l] & 1) {
+            lo[l] = (p[l] - 1) >> 1;  /* floor, also for negative (periodic) indices */
+            hi[l] = lo[l] + 1;
+        } else {
+            lo[l] = hi[l] = p[l] >> 1;
+        }
+    }
+    double sum = 0;
+    int cnt = 0;
+    for (int k = lo[2]; k <= hi[2]; k++)
+        for (int j = lo[1]; j <= hi[1]; j++)
+            for (int i = lo[0]; i <= hi[0]; i++) {
+                const int c[3] = {i, j, k};
+                sum += U[0][cell_index(P, c)];
+                cnt++;
+            }
+    return sum / cnt;
 }
 
 static double avg(const orc_problem *P, const double *const *U, const int c[3])
 {
-    if (bc_open(P) && c[0] < 0) return bc_value(P, U, 0);
-    if (bc_open(P) && c[0] >= P->n[0]) return bc_value(P, U, 1);
+    const int p[3] = {2 * c[0], 2 * c[1], 2 * c[2]};
+    const int m = ends_of(P, p);
+    if (m) return bc_point(P, U, p, m);
     return U[0][cell_index(P, c)];
 }
 
@@ -328,8 +371,8 @@ static double centre(const orc_problem *P, const double *const *U, const int c[3
 /* value at half-grid point p: a point-value DoF, or a reconstructed centre */
 static double H(const orc_problem *P, const double *const *U, const int p[3])
 {
-    if (bc_open(P) && p[0] <= -1) return bc_value(P, U, 0);
-    if (bc_open(P) && p[0] >= 2 * P->n[0] - 1) return bc_value(P, U, 1);
+    const int m = ends_of(P, p);
+    if (m) return bc_point(P, U, p, m);
     int q[3], c[3], b = 0;
     for (int l = 0; l < 3; l++) {
         q[l] = wrapi(p[l], 2 * P->n[l]);
@@ -780,7 +823,11 @@ static void rhs_cell(const orc_problem *P, const double *const *U, const int c[3
         int p[3] = {2 * c[0] + (b & 1), 2 * c[1] + ((b >> 1) & 1), 2 * c[2] + ((b >> 2) & 1)};
         out[zeta_of_mask(P->dim, b)] = pv_rhs(&Q, U, p);
     }
-    if (bc_open(P) && c[0] == P->n[0] - 1) out[1] = 0;  /* the boundary point is not an unknown */
+    if (bc_open(P))
+        for (int b = 1; b < nb; b++) {  /* boundary points are not unknowns */
+            const int p[3] = {2 * c[0] + (b & 1), 2 * c[1] + ((b >> 1) & 1), 2 * c[2] + ((b >> 2) & 1)};
+            if (ends_of(P, p)) out[zeta_of_mask(P->dim, b)] = 0;
+        }
 }
 
 /* one forward-Euler stage of the (limited) scheme for one cell */
@@ -840,7 +887,17 @@ static void fe_cell(const orc_problem *P, const double *const *U, double dt, con
         }
         out[zeta_of_mask(P->dim, b)] = v;
     }
-    if (bc_open(P) && c[0] == P->n[0] - 1) out[1] = P->bc[1] == ORC_BC_DIRICHLET ? P->bcval[1] : out[0];
+    if (bc_open(P))
+        for (int b = 1; b < nb; b++) {
+            const int p[3] = {2 * c[0] + (b & 1), 2 * c[1] + ((b >> 1) & 1), 2 * c[2] + ((b >> 2) & 1)};
+            const int m = ends_of(P, p);
+            if (!m) continue;
+            int dir = 0;  /* a Dirichlet end among those the point lies on */
+            double g = 0;
+            for (int l = 0; l < 3 && !dir; l++)
+                if ((m >> l & 1) && P->bc[l][1] == ORC_BC_DIRICHLET) { dir = 1; g = P->bcval[l][1]; }
+            out[zeta_of_mask(P->dim, b)] = dir ? g : U[zeta_of_mask(P->dim, b)][cell_index(P, c)];
+        }
 }
 
 static long ncells(const orc_problem *P) { return (long)P->n[0] * P->n[1] * P->n[2]; }
@@ -1028,7 +1085,7 @@ double orc_dt(const orc_problem *P, const double *const *U, double cfl)
             shift(c, l, 1, cp);
             double v = alpha_L(P, l, avg(P, U, c), avg(P, U, cp)) / P->dx[l] + P->kappa_max / (P->dx[l] * P->dx[l]);
             if (v > m) m = v;
-            if (bc_open(P) && c[0] == 0) {  /* the face x_{-1/2} with the ghost cell */
+            if (axis_open(P, l) && c[l] == 0) {  /* the face at the low end with the ghost cell */
                 int cm[3];
                 shift(c, l, -1, cm);
                 v = alpha_L(P, l, avg(P, U, cm), avg(P, U, c)) / P->dx[l] + P->kappa_max / (P->dx[l] * P->dx[l]);

@@ -956,3 +956,103 @@ def test_si_blended_average_matches_printed_formulas(gamma):
     mu, nu = dt / dx, dt / dx ** 2
     avg = ub - mu * (F - np.roll(F, 1)) + nu * (np.roll(A, -1) - 2 * A + np.roll(A, 1))
     np.testing.assert_allclose(V[0], avg, rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Open ends in 2D (the rule is the 1D one applied along each axis; corners
+# and edges take the mean of the boundary cells around the clamped point)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ends", [(("dirichlet", 0.9), ("dirichlet", 0.15)), ("outflow", "outflow"),
+                                  ("outflow", ("dirichlet", 0.3))])
+@pytest.mark.parametrize("lim", [False, True])
+def test_open_x_ends_2d_data_constant_in_y_reproduces_1d(ends, lim):
+    n, ny = 12, 5
+    rng = np.random.default_rng(21)
+    ub, up = rng.uniform(0.2, 0.8, n), rng.uniform(0.2, 0.8, n)
+    gl = ends[0][1] if not isinstance(ends[0], str) else ub[0]
+    gr = ends[1][1] if not isinstance(ends[1], str) else ub[-1]
+    up[-1] = gr
+    upe = up.copy()
+    ctr = (6 * ub - np.concatenate([[gl], upe[:-1]]) - upe) / 4  # Simpson with the boundary points
+    s1 = spec1d(n, 1.0, ("quad", 0.5, 0.0), ("power", 0.05, 2.0), umin=0.0, umax=1.0, limiter=lim, bc=ends)
+    s2 = dict(dim=2, n=[n, ny], lo=[0.0, 0.0], hi=[1.0, 0.7], flux=[("quad", 0.5, 0.0), ("quad", 0.5, 0.0)],
+              diff=("power", 0.05, 2.0), umin=0.0, umax=1.0, limiter=lim, bcs=[ends, ("periodic", "periodic")])
+    rows = lambda a: np.tile(a, ny)
+    P1, P2 = oracle.problem(s1), oracle.problem(s2)
+    dt = 2e-3
+    V1, _ = oracle.fe(P1, [ub, up], dt)
+    V2, _ = oracle.fe(P2, [rows(ub), rows(up), rows(ctr), rows(up)], dt)
+    np.testing.assert_allclose(V2[0], rows(V1[0]), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(V2[1], rows(V1[1]), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(V2[3], rows(V1[1]), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("ends", [("outflow", "outflow"), (("dirichlet", 0.4), ("dirichlet", 0.4))])
+def test_open_ends_2d_transpose_symmetry(ends):
+    """The same ends on both axes keep the scheme symmetric under x <-> y
+    (corner and edge ghost values included)."""
+    n = 14
+    rng = np.random.default_rng(33)
+    U = [rng.uniform(0.1, 0.9, n * n) for _ in range(4)]
+    spec = dict(dim=2, n=[n, n], lo=[0.0, 0.0], hi=[1.0, 1.0], flux=[("quad", 0.5, 0.0), ("quad", 0.5, 0.0)],
+                diff=("ramp2", 0.2, 0.3), umin=0.0, umax=1.0, limiter=True, bcs=[ends, ends])
+    P = oracle.problem(spec)
+    dt = oracle.dt_cfl(P, U, 0.1)
+    V, _ = oracle.fe(P, U, dt)
+    T = lambda a: a.reshape(n, n).T.reshape(-1)
+    VT, _ = oracle.fe(P, [T(U[0]), T(U[2]), T(U[1]), T(U[3])], dt)
+    for a, b in zip(VT, [T(V[0]), T(V[2]), T(V[1]), T(V[3])]):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("ends", [("outflow", "outflow"), (("dirichlet", 0.0), ("dirichlet", 0.0))])
+def test_open_ends_2d_leave_interior_solutions_alone(ends):
+    """A bump in the middle of a 2D box: while the data near every end equal
+    the boundary value, open ends give exactly the periodic result."""
+    n = 24
+    x = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(x, x)
+    bump = lambda X, Y: np.clip(1 - ((X - 0.5) ** 2 + (Y - 0.5) ** 2) / 0.04, 0, 1) ** 2
+    h = 0.5 / n
+    U = [bump(X, Y).reshape(-1), bump(X + h, Y).reshape(-1), bump(X, Y + h).reshape(-1), bump(X + h, Y + h).reshape(-1)]
+    # quadratic fluxes and a dead-zone potential keep exact zeros exactly zero
+    base = dict(dim=2, n=[n, n], lo=[0.0, 0.0], hi=[1.0, 1.0], flux=[("quad", 0.5, 0.0), ("quad", -0.3, 0.0)],
+                diff=("deadzone", 0.02, 0.3), umin=0.0, umax=1.0, limiter=True)
+    Pp, Pb = oracle.problem(base), oracle.problem(dict(base, bcs=[ends, ends]))
+    dts = [0.3 * oracle.dt_cfl(Pp, U, 0.1)] * 4
+    Up, _, _ = oracle.run(Pp, U, dts=dts)
+    Ub, _, _ = oracle.run(Pb, U, dts=dts)
+    for a, b in zip(Up, Ub):
+        np.testing.assert_array_equal(b, a)
+
+
+def test_open_ends_2d_constant_state_is_a_fixed_point():
+    n = 10
+    for ends in [("outflow", "outflow"), (("dirichlet", 0.25), ("dirichlet", 0.25))]:
+        spec = dict(dim=2, n=[n, n], lo=[0.0, 0.0], hi=[1.0, 1.0], flux=[("bl", 0.0, 0.0), ("bl_grav", 0.0, 5.0)],
+                    diff=("bl", 0.01, 0.0), umin=0.0, umax=1.0, limiter=True, bcs=[ends, ("outflow", "outflow")])
+        U = [np.full(n * n, 0.25) for _ in range(4)]
+        V, _, _ = oracle.run(oracle.problem(spec), U, nsteps=3, cfl=0.1)
+        for v in V:
+            np.testing.assert_allclose(v, 0.25, rtol=0, atol=1e-15)
+
+
+def test_open_x_ends_2d_y_reflection_symmetry():
+    """y -> -y (with f_y -> -f_y) maps the scheme with open x ends to itself:
+    the ghost value at a transverse half index is the mean of both adjacent
+    boundary cells, not one of them."""
+    nx, ny = 10, 8
+    rng = np.random.default_rng(55)
+    U = [rng.uniform(0.1, 0.9, nx * ny) for _ in range(4)]
+    mk = lambda cy: oracle.problem(dict(dim=2, n=[nx, ny], lo=[0.0, 0.0], hi=[1.0, 0.8],
+                                        flux=[("quad", 0.5, 0.0), ("quad", cy, 0.0)], diff=("power", 0.05, 2.0),
+                                        umin=0.0, umax=1.0, limiter=True,
+                                        bcs=[("outflow", ("dirichlet", 0.5)), ("periodic", "periodic")]))
+    R = oracle.rhs(mk(0.7), U)
+    # reflection in y: row j -> ny-1-j; a y half index j+1/2 -> (ny-1-j)-1/2, stored in row ny-2-j
+    cell = lambda a: a.reshape(ny, nx)[::-1].reshape(-1)
+    face = lambda a: np.roll(a.reshape(ny, nx)[::-1], -1, axis=0).reshape(-1)
+    RR = oracle.rhs(mk(-0.7), [cell(U[0]), cell(U[1]), face(U[2]), face(U[3])])
+    for got, want in zip(RR, [cell(R[0]), cell(R[1]), face(R[2]), face(R[3])]):
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
