@@ -6,7 +6,7 @@ projection on, FP32, SSP-RK3, all K steps in one HIP graph launch.  Prints one
 JSON line.  ``value`` is cell-DoF updates per second per RK stage (all
 instances, inputs resident in HBM before the timed region).
 
-    python bench.py [--steps K] [--warmup W] [--workload c4|c2|c3|c3f32|c5|nodc|ek]
+    python bench.py [--steps K] [--warmup W] [--workload c4|c2|c3|c3f32|c5|nodc|ek|c3out]
 """
 import argparse
 import glob
@@ -77,6 +77,10 @@ def workload(name):
         return "nodc_ek_batched_1024x8192_1d_fp64", W.config_nodc()
     if name == "ek":
         return "ek_dirichlet_batched_1024x8192_1d_fp64", W.config_ek()
+    if name == "c3out":
+        spec, U = W.config3(precision=64)
+        return ("c3_buckley_leverett_gravity_1024x1024_fp64_outflow",
+                [(dict(spec, bcs=[("outflow", "outflow"), ("outflow", "outflow")]), U)])
     raise SystemExit("unknown workload " + name)
 
 

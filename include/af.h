@@ -68,15 +68,18 @@ typedef enum {
                          five stages, two more state buffers */
 } af_integrator;
 
-/* Ends of axis 0 (1D problems).  The paper runs its Examples 6.5-6.8 with
- * Dirichlet or outflow ends but states no ghost treatment; the one used:
- * every value beyond the domain -- ghost cell averages, ghost point values
- * and both boundary points x_{-1/2}, x_{N-1/2} -- is the end's boundary
- * value: the Dirichlet value, or for outflow the average of the adjacent
- * boundary cell.  The stored point value at x_{N-1/2} (index N-1) is not
- * evolved: a stage writes the boundary value into it (its input value is
- * ignored; its right-hand side is 0).  The mass changes by the boundary
- * fluxes. */
+/* Ends of an axis (1D and 2D problems).  The paper runs its Examples
+ * 6.5-6.9 with Dirichlet or outflow ends but states no ghost treatment; the
+ * one used: a half-grid point on or beyond an open end -- ghost point values,
+ * ghost cell averages (their centres) and the boundary points x_{-1/2},
+ * x_{N-1/2} -- takes a boundary value: the Dirichlet value if one of the ends
+ * it lies on or beyond is Dirichlet (lowest axis first), else (outflow) the
+ * mean average of the domain cells whose closure contains the point moved
+ * onto the boundary (one cell, two along an edge in 2D).  The stored point
+ * values on the high ends (index N-1 of the faces normal to the axis, and of
+ * the corners) are not unknowns: their input is ignored, a stage writes the
+ * Dirichlet value (Dirichlet end) or passes the input through (outflow), and
+ * the right-hand side there is 0.  The mass changes by the boundary fluxes. */
 typedef enum {
     AF_BC_PERIODIC = 0,
     AF_BC_DIRICHLET = 1,  /* u = bc_value at the end */
@@ -115,10 +118,10 @@ typedef struct {
     int integrator;          /* af_integrator */
     int diffusion_form;      /* af_diffusion_form; AF_DIFF_NODC needs dim = 1 and no
                                 blending (else AF_ERR_UNSUPPORTED) */
-    int bc[2];               /* af_bc of the low and high end of axis 0: both periodic or
-                                neither (AF_ERR_ARG); non-periodic ends need dim = 1 and no
+    int bc[3][2];            /* af_bc of the low and high end of each axis: both periodic or
+                                neither (AF_ERR_ARG); non-periodic ends need dim <= 2 and no
                                 blending (AF_ERR_UNSUPPORTED) */
-    double bc_value[2];      /* Dirichlet values; with the limiter inside [umin, umax]
+    double bc_value[3][2];   /* Dirichlet values; with the limiter inside [umin, umax]
                                 (AF_ERR_BOUNDS, checked when the bounds are known) */
 } af_problem;
 

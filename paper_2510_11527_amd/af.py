@@ -47,8 +47,8 @@ class AfProblem(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("integrator", ctypes.c_int),
         ("diffusion_form", ctypes.c_int),
-        ("bc", ctypes.c_int * 2),
-        ("bc_value", ctypes.c_double * 2),
+        ("bc", (ctypes.c_int * 2) * 3),
+        ("bc_value", (ctypes.c_double * 2) * 3),
     ]
 
 
@@ -135,11 +135,14 @@ def make_problem(spec, precision=None, integrator="ssprk3"):
     P.precision = int(precision or spec.get("precision", 64))
     P.integrator = INTEGRATORS[integrator]
     P.diffusion_form = DIFFUSION_FORMS[spec.get("diffusion_form", "dc")]
-    bc = spec.get("bc", ("periodic", "periodic"))
-    for e in range(2):  # each end: "periodic", "outflow" or ("dirichlet", value)
-        kind = bc[e] if isinstance(bc[e], str) else bc[e][0]
-        P.bc[e] = BC_KINDS[kind]
-        P.bc_value[e] = 0.0 if isinstance(bc[e], str) else float(bc[e][1])
+    # ends per axis ("bcs": [(low, high), ...]; "bc": those of axis 0); each
+    # end "periodic", "outflow" or ("dirichlet", value)
+    ends = list(spec.get("bcs", [])) or ([spec["bc"]] if "bc" in spec else [])
+    for l, pair in enumerate(ends):
+        for e in range(2):
+            kind = pair[e] if isinstance(pair[e], str) else pair[e][0]
+            P.bc[l][e] = BC_KINDS[kind]
+            P.bc_value[l][e] = 0.0 if isinstance(pair[e], str) else float(pair[e][1])
     return P
 
 

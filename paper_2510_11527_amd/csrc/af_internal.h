@@ -35,8 +35,8 @@ struct InstDev {
     int pabs, ppow;
     int wstart, wcount;  // the instance's range in the work list of the stage kernels
     int nodc, pad0;      // 1: diffusion in the form of App. A (no double conservation; 1D)
-    int bc[2];           // af_bc of the low / high end of axis 0 (1D; both periodic or neither)
-    double bcv[2];       // Dirichlet values
+    int bc[3][2];        // af_bc of the low / high end of each axis (both periodic or neither)
+    double bcv[3][2];    // Dirichlet values
     double idx1[3];      // 1 / dx_l
     double idx2[3];      // 1 / dx_l^2
     double i6dx[3];      // 1 / (6 dx_l)

@@ -300,18 +300,23 @@ af_status validate(const af_problem &P, int idx)
         return bad(AF_ERR_ARG, "unknown diffusion form");
     if (P.diffusion_form == AF_DIFF_NODC && (P.dim != 1 || P.si_blend))
         return bad(AF_ERR_UNSUPPORTED, "the diffusion form of App. A is one-dimensional and unblended");
-    for (int e = 0; e < 2; e++)
-        if (P.bc[e] < AF_BC_PERIODIC || P.bc[e] > AF_BC_OUTFLOW) return bad(AF_ERR_ARG, "unknown boundary kind");
-    if ((P.bc[0] == AF_BC_PERIODIC) != (P.bc[1] == AF_BC_PERIODIC))
-        return bad(AF_ERR_ARG, "both ends periodic or neither");
-    if (P.bc[0] != AF_BC_PERIODIC && (P.dim != 1 || P.si_blend))
-        return bad(AF_ERR_UNSUPPORTED, "non-periodic ends are supported for unblended 1D problems");
-    for (int e = 0; e < 2; e++) {
-        if (P.bc[e] != AF_BC_DIRICHLET) continue;
-        if (!std::isfinite(P.bc_value[e])) return bad(AF_ERR_ARG, "Dirichlet value must be finite");
-        if (P.limiter && !std::isnan(P.umin) && !std::isnan(P.umax) &&
-            !(P.bc_value[e] >= P.umin && P.bc_value[e] <= P.umax))
-            return bad(AF_ERR_BOUNDS, "Dirichlet value outside [umin, umax]");
+    for (int l = 0; l < 3; l++) {
+        for (int e = 0; e < 2; e++)
+            if (P.bc[l][e] < AF_BC_PERIODIC || P.bc[l][e] > AF_BC_OUTFLOW)
+                return bad(AF_ERR_ARG, "unknown boundary kind");
+        if ((P.bc[l][0] == AF_BC_PERIODIC) != (P.bc[l][1] == AF_BC_PERIODIC))
+            return bad(AF_ERR_ARG, "both ends of an axis periodic or neither");
+        if (P.bc[l][0] == AF_BC_PERIODIC) continue;
+        if (l >= P.dim) return bad(AF_ERR_ARG, "ends of an unused axis must be periodic");
+        if (P.dim > 2 || P.si_blend)
+            return bad(AF_ERR_UNSUPPORTED, "non-periodic ends are supported for unblended 1D and 2D problems");
+        for (int e = 0; e < 2; e++) {
+            if (P.bc[l][e] != AF_BC_DIRICHLET) continue;
+            if (!std::isfinite(P.bc_value[l][e])) return bad(AF_ERR_ARG, "Dirichlet value must be finite");
+            if (P.limiter && !std::isnan(P.umin) && !std::isnan(P.umax) &&
+                !(P.bc_value[l][e] >= P.umin && P.bc_value[l][e] <= P.umax))
+                return bad(AF_ERR_BOUNDS, "Dirichlet value outside [umin, umax]");
+        }
     }
     return AF_OK;
 }
@@ -507,7 +512,8 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
     c->lim = !!probs[0].limiter;
     c->si = !!probs[0].si_blend;
     for (int i = 0; i < n_inst; i++)
-        if (probs[i].bc[0] != AF_BC_PERIODIC) c->open = true;
+        for (int l = 0; l < 3; l++)
+            if (probs[i].bc[l][0] != AF_BC_PERIODIC) c->open = true;
     c->integ = probs[0].integrator;
     c->prob.assign(probs, probs + n_inst);
     c->ih.resize(n_inst);
@@ -544,15 +550,16 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
         I.cfl = P.cfl;
         I.si_gamma = P.si_blend ? P.si_gamma : 0.0;
         I.nodc = P.diffusion_form == AF_DIFF_NODC;
-        for (int e = 0; e < 2; e++) {
-            I.bc[e] = P.bc[e];
-            I.bcv[e] = P.bc[e] == AF_BC_DIRICHLET ? P.bc_value[e] : 0.0;
-        }
+        for (int l = 0; l < 3; l++)
+            for (int e = 0; e < 2; e++) {
+                I.bc[l][e] = P.bc[l][e];
+                I.bcv[l][e] = P.bc[l][e] == AF_BC_DIRICHLET ? P.bc_value[l][e] : 0.0;
+            }
         if (!std::isnan(P.umin) && !std::isnan(P.umax)) derive_bounds_params(I, P, P.dim);
         set_f32_params(I);
     }
     c->total = off;
-    c->caps = af4::kCapQF | af4::kCapPP | af4::kCapI32 | af4::kCapBQ;
+    c->caps = af4::kCapQF | af4::kCapPP | af4::kCapI32 | af4::kCapBQ | (c->open ? af4::kCapOpen : 0u);
     for (int i = 0; i < n_inst; i++) {
         const InstDev &I = c->ih[i];
         for (int l = 0; l < c->dim; l++) {
@@ -705,21 +712,23 @@ af_status af_set_state(af_ctx *c, int inst, const double *const *dofs, double t)
     if (derive && !c->have_state[inst]) {
         umin = *std::min_element(r.begin(), r.end());
         umax = *std::max_element(r.begin(), r.end());
-        for (int e = 0; e < 2; e++)  // Dirichlet data bound the solution too
-            if (P.bc[e] == AF_BC_DIRICHLET) {
-                const double g = c->prec == 32 ? (double)(float)P.bc_value[e] : P.bc_value[e];
-                umin = std::min(umin, g);
-                umax = std::max(umax, g);
-            }
+        for (int l = 0; l < 3; l++)  // Dirichlet data bound the solution too
+            for (int e = 0; e < 2; e++)
+                if (P.bc[l][e] == AF_BC_DIRICHLET) {
+                    const double g = c->prec == 32 ? (double)(float)P.bc_value[l][e] : P.bc_value[l][e];
+                    umin = std::min(umin, g);
+                    umax = std::max(umax, g);
+                }
     }
     if (c->lim) {
         for (double v : r)
             if (v < umin || v > umax) return fail(c, AF_ERR_BOUNDS, "af_set_state: DoF outside [umin, umax]");
-        for (int e = 0; e < 2; e++) {
-            const double g = c->prec == 32 ? (double)(float)P.bc_value[e] : P.bc_value[e];
-            if (P.bc[e] == AF_BC_DIRICHLET && !(g >= umin && g <= umax))
-                return fail(c, AF_ERR_BOUNDS, "af_set_state: Dirichlet value outside [umin, umax]");
-        }
+        for (int l = 0; l < 3; l++)
+            for (int e = 0; e < 2; e++) {
+                const double g = c->prec == 32 ? (double)(float)P.bc_value[l][e] : P.bc_value[l][e];
+                if (P.bc[l][e] == AF_BC_DIRICHLET && !(g >= umin && g <= umax))
+                    return fail(c, AF_ERR_BOUNDS, "af_set_state: Dirichlet value outside [umin, umax]");
+            }
     }
     if (derive && !c->have_state[inst]) {
         I.umin = umin;

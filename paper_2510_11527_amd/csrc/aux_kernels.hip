@@ -28,7 +28,9 @@ __global__ void __launch_bounds__(256) wavespeed_kernel(const InstDev *inst, con
         kdx2[l] = I.kmax * I.idx2[l];
     }
     const double big = 1e6 * fmax(fmax(fabs(I.umin), fabs(I.umax)), 1.0);
-    const bool open = dim == 1 && I.bc[0] != 0;  // non-periodic ends: ghost values at both end faces
+    // non-periodic ends (1D, 2D): the faces at the ends see a ghost cell whose
+    // average is the Dirichlet value or (outflow) the boundary cell's average
+    const bool open0 = dim <= 2 && I.bc[0][0] != 0, open1 = dim == 2 && I.bc[1][0] != 0;
     double w = 0.0;
     bool bad = false;
     for (int r = r0; r < r1; r++) {
@@ -40,13 +42,21 @@ __global__ void __launch_bounds__(256) wavespeed_kernel(const InstDev *inst, con
             const double uc = (double)u[row + i];
             if (!(fabs(uc) <= big)) bad = true;  // also catches NaN
             double ux = (double)u[row + (i + 1 == n0 ? 0 : i + 1)];
-            if (open && i + 1 == n0) ux = I.bc[1] == 1 ? (double)(T)I.bcv[1] : uc;  // the face x_{N-1/2}
-            if (open && i == 0) {  // the face x_{-1/2}
-                const double ug = I.bc[0] == 1 ? (double)(T)I.bcv[0] : uc;
+            if (open0 && i + 1 == n0) ux = I.bc[0][1] == 1 ? (double)(T)I.bcv[0][1] : uc;
+            if (open0 && i == 0) {
+                const double ug = I.bc[0][0] == 1 ? (double)(T)I.bcv[0][0] : uc;
                 w = fmax(w, P.alpha_int(0, ug, uc) * idx[0] + kdx2[0]);
             }
             w = fmax(w, P.alpha_int(0, uc, ux) * idx[0] + kdx2[0]);
-            if (dim >= 2) w = fmax(w, P.alpha_int(1, uc, (double)u[rowy + i]) * idx[1] + kdx2[1]);
+            if (dim >= 2) {
+                double uy = (double)u[rowy + i];
+                if (open1 && j + 1 == n1) uy = I.bc[1][1] == 1 ? (double)(T)I.bcv[1][1] : uc;
+                if (open1 && j == 0) {
+                    const double ug = I.bc[1][0] == 1 ? (double)(T)I.bcv[1][0] : uc;
+                    w = fmax(w, P.alpha_int(1, ug, uc) * idx[1] + kdx2[1]);
+                }
+                w = fmax(w, P.alpha_int(1, uc, uy) * idx[1] + kdx2[1]);
+            }
             if (dim >= 3) w = fmax(w, P.alpha_int(2, uc, (double)u[rowz + i]) * idx[2] + kdx2[2]);
         }
     }

@@ -19,6 +19,7 @@ enum : unsigned {
     kCapPP = 2,   // every potential is c1 u + c2 u^2 + c3 u^3 without clamps or signs
     kCapI32 = 4,  // the DoF block of every instance holds fewer than 2^32 bytes
     kCapBQ = 8,   // every flux is c2 u^2 (no linear part)
+    kCapOpen = 16,  // some instance has non-periodic ends (only the generic kernel fills ghosts)
 };
 
 // One stage launch over nblocks (instance, tile) work items.

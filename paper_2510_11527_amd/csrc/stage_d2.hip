@@ -55,6 +55,7 @@ template <class T, int TX, int TY, int NT, int KIND>
 hipError_t launch_kind(bool lim, bool si, unsigned caps, int nblocks, const void *params, hipStream_t s)
 {
     const bool qf = (caps & kCapQF) != 0;
+    if (KIND != 0 && (caps & kCapOpen)) return hipErrorInvalidValue;
     if constexpr (KIND == 4) {
         if (si || !qf || !(caps & kCapI32)) return hipErrorInvalidValue;
         const int fl = ((caps & kCapPP) ? kOwnPP : 0) | ((caps & kCapBQ) ? kOwnBQ : 0);
@@ -85,6 +86,7 @@ template <class T, int TX, int TY, int KIND>
 bool fits_kind(bool lim, bool si, unsigned caps)
 {
     const bool qf = (caps & kCapQF) != 0;
+    if (KIND != 0 && (caps & kCapOpen)) return false;
     if constexpr (KIND == 4) {
         if (si || !qf || !(caps & kCapI32)) return false;
         return stage2o_lds_bytes<T, true, TX, TY>() <= kLdsCap && stage2o_lds_bytes<T, false, TX, TY>() <= kLdsCap;

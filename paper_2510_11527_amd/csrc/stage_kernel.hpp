@@ -395,16 +395,42 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
     const double dtd = p.st[wk.x].dt;
     // the 1D variant without double conservation (App. A)
     const bool nodc = D == 1 && I.nodc != 0;
-    // Non-periodic ends (1D): every value beyond the domain and both boundary
-    // points take the end's boundary value (Dirichlet value, or for outflow
-    // the boundary cell's average); the stored point value at x_{N-1/2} is
-    // not evolved but set to the boundary value by every stage.
-    const bool open = D == 1 && I.bc[0] != 0;
-    T bv0 = T(0), bv1 = T(0);
-    if (open) {
-        bv0 = I.bc[0] == 1 ? (T)I.bcv[0] : in[0];
-        bv1 = I.bc[1] == 1 ? (T)I.bcv[1] : in[n0 - 1];
-    }
+    // Non-periodic ends (1D, 2D): a half-grid point on or beyond an open end
+    // (global half indices q0, q1) takes a boundary value -- the Dirichlet
+    // value of the first Dirichlet end among those it lies on or beyond, else
+    // (outflow) the mean average of the domain cells around the point moved
+    // onto the boundary; the stored point values on the high ends are not
+    // evolved (Dirichlet value, or the input passed through).
+    const bool open = D <= 2 && (I.bc[0][0] != 0 || (D == 2 && I.bc[1][0] != 0));
+    auto ends = [&](int q0, int q1) -> int {
+        int m = 0;
+        if (I.bc[0][0] != 0 && (q0 <= -1 || q0 >= 2 * n0 - 1)) m |= 1;
+        if (D == 2 && I.bc[1][0] != 0 && (q1 <= -1 || q1 >= 2 * n1 - 1)) m |= 2;
+        return m;
+    };
+    auto bc_point = [&](int q0, int q1, int m) -> T {
+#pragma unroll
+        for (int l = 0; l < 2; l++) {
+            const int q = l == 0 ? q0 : q1, side = q <= -1 ? 0 : 1;
+            if ((m >> l & 1) && I.bc[l][side] == 1) return (T)I.bcv[l][side];
+        }
+        int lo[2], hi[2];
+#pragma unroll
+        for (int l = 0; l < 2; l++) {
+            const int q = l == 0 ? q0 : q1, nl = l == 0 ? n0 : n1;
+            if (m >> l & 1) lo[l] = hi[l] = q <= -1 ? 0 : nl - 1;
+            else if (q & 1) { lo[l] = (q - 1) >> 1; hi[l] = lo[l] + 1; }
+            else lo[l] = hi[l] = q >> 1;
+        }
+        T sum = T(0);
+        int cnt = 0;
+        for (int j = lo[1]; j <= hi[1]; j++)
+            for (int i = lo[0]; i <= hi[0]; i++) {
+                sum += in[wrap_index(i, n0) + (long long)n0 * wrap_index(j, n1)];
+                cnt++;
+            }
+        return sum / T(cnt);
+    };
 
     const T inf = __builtin_huge_val();
     T vlo = inf, vhi = -inf;  // min / max of the averages written
@@ -438,15 +464,16 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
     // ---- A: stage tile + halo (averages -> ub, point values -> half grid)
     box_loop<G::R0, G::R1, G::R2, NT>([&](int x, int y, int z) {
         if (open) {
-            const int gr = ox + x - G::H0;
-            if (gr < 0 || gr >= n0) {
-                const T g = gr < 0 ? bv0 : bv1;
-                ub[G::cidx(x, 0, 0)] = g;
-                hg[G::hidx(2 * x + 1, 0, 0)] = g;
-                return;
+            const int c0 = ox + x - G::H0, c1 = D >= 2 ? oy + y - G::H1 : 0;
+            const long long gi = wrap_index(c0, n0) + (long long)n0 * (D >= 2 ? wrap_index(c1, n1) : 0);
+#pragma unroll
+            for (int zk = 0; zk < NB; zk++) {
+                const int q0 = 2 * c0 + (zk & 1), q1 = 2 * c1 + ((zk >> 1) & 1);
+                const int m = ends(q0, q1);
+                const T v = m ? bc_point(q0, q1, m) : in[zk * kst + gi];
+                if (zk == 0) ub[G::cidx(x, y, 0)] = v;
+                else hg[G::hidx(2 * x + (zk & 1), 2 * y + ((zk >> 1) & 1), 0)] = v;
             }
-            ub[G::cidx(x, 0, 0)] = in[gr];
-            hg[G::hidx(2 * x + 1, 0, 0)] = gr == n0 - 1 ? bv1 : in[kst + gr];
             return;
         }
         int gx = wrap_index(ox + x - G::H0, n0);
@@ -470,9 +497,13 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
         constexpr T iW = D == 1 ? T(0.25) : (D == 2 ? T(0.0625) : T(0.015625));
         box_loop<E0, E1, E2, NT>([&](int i, int j, int k) {
             const int x = i + L0, y = j + L1, z = k + L2;
-            if (open && (ox + x - G::H0 < 0 || ox + x - G::H0 >= n0)) {
-                hg[G::hidx(2 * x, 0, 0)] = ox + x - G::H0 < 0 ? bv0 : bv1;  // ghost centre
-                return;
+            if (open) {
+                const int q0 = 2 * (ox + x - G::H0), q1 = D >= 2 ? 2 * (oy + y - G::H1) : 0;
+                const int m = ends(q0, q1);
+                if (m) {  // ghost centre
+                    hg[G::hidx(2 * x, 2 * y, 0)] = bc_point(q0, q1, m);
+                    return;
+                }
             }
             T acc = S * ub[G::cidx(x, y, z)];
 #pragma unroll
@@ -600,19 +631,25 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                 R += conv + d2;
             }
             if (!own) continue;
-            // the boundary point x_{N-1/2} of non-periodic ends: right-hand
-            // side 0; a stage gives it the boundary value (outflow: the new
-            // average, written with the average below)
-            const bool bpt = open && gi == n0 - 1;
+            // stored points on a high open end: right-hand side 0; a stage
+            // writes the Dirichlet value or passes the input through
+            const int me = open ? ends(2 * (ox + i) + (m & 1), 2 * (oy + j) + ((m >> 1) & 1)) : 0;
             if (residual) {
-                out[zk * kst + gi] = bpt ? T(0) : R;
+                out[zk * kst + gi] = me ? T(0) : R;
                 continue;
             }
-            if (bpt && I.bc[1] != 1) continue;
-            T v = bpt ? bv1 : u0 + dt * R;
+            T v = u0 + dt * R;
+            if (me) {
+                v = in[zk * kst + gi];
+#pragma unroll
+                for (int l = 1; l >= 0; l--)
+                    if ((me >> l & 1) && I.bc[l][1] == 1) v = (T)I.bcv[l][1];
+            }
             if (!isfinite(v)) bad = true;
             if constexpr (LIM) v = clampb(v, P.umin, P.umax);
-            v = stage_combine(p, v, un[zk * kst + gi], x1 ? x1[zk * kst + gi] : T(0), u0);
+            // (a stored boundary point combines with its stored input, not the
+            // boundary value the stencils see)
+            v = stage_combine(p, v, un[zk * kst + gi], x1 ? x1[zk * kst + gi] : T(0), me ? in[zk * kst + gi] : u0);
             if constexpr (LIM) v = clampb(v, P.umin, P.umax);
             out[zk * kst + gi] = v;
         }
@@ -786,13 +823,6 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
             T c = clampb(v, P.umin, P.umax);
             clamp_mag = fmax(clamp_mag, (double)fabs(c - v));
             v = c;
-        }
-        if (open && gi == n0 - 1 && I.bc[1] != 1) {
-            // outflow: the boundary point takes the stage's average, combined
-            // like every point value
-            T b = stage_combine(p, v, un[kst + gi], x1 ? x1[kst + gi] : T(0), in[kst + gi]);
-            if constexpr (LIM) b = clampb(b, P.umin, P.umax);
-            out[kst + gi] = b;
         }
         v = stage_combine(p, v, un[gi], x1 ? x1[gi] : T(0), u);
         if constexpr (LIM) {

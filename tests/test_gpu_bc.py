@@ -144,7 +144,91 @@ def test_open_end_validation():
     with pytest.raises(af.AFError) as e:
         af.Context(dict(spec, bc=(("dirichlet", 1.5), "outflow")))
     assert e.value.status == af.AF_ERR_BOUNDS
+    s3, _ = W.config5(n=8)
+    with pytest.raises(af.AFError) as e:
+        af.Context(dict(s3, bc=("outflow", "outflow")))
+    assert e.value.status == af.AF_ERR_UNSUPPORTED
     s2, _ = W.config2(n=16)
     with pytest.raises(af.AFError) as e:
-        af.Context(dict(s2, bc=("outflow", "outflow")))
+        af.Context(dict(s2, si=True, bcs=[("outflow", "outflow"), ("outflow", "outflow")]))
     assert e.value.status == af.AF_ERR_UNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# 2D (Examples 6.7 and 6.9 use outflow ends on [-1.5, 1.5]^2)
+# ---------------------------------------------------------------------------
+
+BCS2 = [[("outflow", "outflow"), ("outflow", "outflow")],
+        [(("dirichlet", 0.9), ("dirichlet", 0.2)), ("outflow", "outflow")],
+        [(("dirichlet", 0.7), "outflow"), (("dirichlet", 0.3), ("dirichlet", 0.6))],
+        [("periodic", "periodic"), ("outflow", ("dirichlet", 0.5))]]
+
+
+def spec2(n, fl, df, bcs, limiter=False, precision=64):
+    return dict(name="t2", dim=2, n=[n, n + 3], lo=[0.0, 0.0], hi=[1.0, 1.2], flux=[fl, fl], diff=df,
+                umin=0.0, umax=1.0, limiter=limiter, si=False, si_gamma=1.0, precision=precision, cfl=0.075,
+                bcs=bcs)
+
+
+def state2(spec, rng):
+    N = spec["n"][0] * spec["n"][1]
+    U = [rng.uniform(0, 1, size=N) for _ in range(4)]
+    U[0] = np.where(rng.uniform(size=N) < 0.6, U[0], rng.choice([0.0, 1.0], size=N))
+    return U
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_open_ends_2d_residual_matches_oracle(prec):
+    rng = np.random.default_rng(1100 + prec)
+    for k, bcs in enumerate(BCS2):
+        fl, df = CASES[k]
+        spec = spec2(21, fl, df, bcs, precision=prec)
+        s, U = prepare(spec, state2(spec, rng), prec)
+        note("bc2 residual prec=%d bcs=%s flux=%s" % (prec, bcs, fl[0]))
+        ctx = af.Context(s)
+        assert ctx.variant_name(ctx.variant()).startswith("generic")
+        ctx.set_state(0, U)
+        R = ctx.residual(0)
+        ctx.close()
+        Ro = oracle.rhs(oracle.problem(s), U)
+        err = rel_l1(R, Ro)
+        assert err <= TOL[prec] * (10 if prec == 32 else 1), err
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("lim", [False, True])
+def test_open_ends_2d_forward_euler_stage_matches_oracle(prec, lim):
+    rng = np.random.default_rng(1200 + prec + 3 * lim)
+    for k, bcs in enumerate(BCS2):
+        fl, df = CASES[(k + 1) % 4]
+        spec = spec2(19, fl, df, bcs, limiter=lim, precision=prec)
+        s, U = prepare(spec, state2(spec, rng), prec)
+        P = oracle.problem(s)
+        dt = oracle.dt_cfl(P, U, s["cfl"])
+        note("bc2 fe prec=%d lim=%d bcs=%s flux=%s dt=%.3e" % (prec, lim, bcs, fl[0], dt))
+        V, t, used, nrm = gpu_run(s, U, dts=[dt], integrator="euler")
+        Vo, dg = oracle.fe(P, U, dt)
+        err = rel_l1(V, Vo)
+        assert err <= TOL[prec], err
+        if lim:
+            assert min(v.min() for v in V) >= s["umin"] and max(v.max() for v in V) <= s["umax"]
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("integ", ["ssprk3", "ssprk54"])
+def test_outflow_buckley_leverett_2d_steps_match_oracle(prec, integ):
+    """Ten steps of the 2D Buckley-Leverett workload with outflow ends on all
+    four sides, as Example 6.7 is run (reduced size), the oracle's CFL steps
+    prescribed to both sides, and the CFL step itself."""
+    spec, U = W.config3(n=40, precision=prec)
+    spec = dict(spec, bcs=[("outflow", "outflow"), ("outflow", "outflow")])
+    s, U = prepare(spec, U, prec)
+    P = oracle.problem(s)
+    Uo, t, dts = oracle.run(P, U, nsteps=10, cfl=s["cfl"], integrator=integ)
+    note("bc2 bl steps %s prec=%d dt0=%.3e" % (integ, prec, dts[0]))
+    V, tg, used, nrm = gpu_run(s, U, dts=dts, integrator=integ)
+    err = rel_l1(V, Uo)
+    assert err <= TOL[prec], err
+    assert min(v.min() for v in V) >= s["umin"] and max(v.max() for v in V) <= s["umax"]
+    V1, t1, used1, _ = gpu_run(s, U, nsteps=1)
+    assert abs(used1[0] - dts[0]) <= (1e-15 if prec == 64 else 1e-6) * dts[0]
