@@ -217,7 +217,11 @@ struct Geo {
     static constexpr int T0 = TX, T1 = D >= 2 ? TY : 1, T2 = D >= 3 ? TZ : 1;
     static constexpr int H0 = HL, H1 = D >= 2 ? HL : 0, H2 = D >= 3 ? HL : 0;
     static constexpr int R0 = T0 + 2 * H0, R1 = T1 + 2 * H1, R2 = T2 + 2 * H2;
-    static constexpr int G0 = 2 * R0, G1 = D >= 2 ? 2 * R1 : 1, G2 = D >= 3 ? 2 * R2 : 1;
+    // the half grid covers the region less its outer HO cells: the point
+    // stencils reach two cells, only the smoothness indicators (averages)
+    // reach a third
+    static constexpr int HO = HL - 2;
+    static constexpr int G0 = 2 * (R0 - 2 * HO), G1 = D >= 2 ? 2 * (R1 - 2 * HO) : 1, G2 = D >= 3 ? 2 * (R2 - 2 * HO) : 1;
     static constexpr int NCELL = R0 * R1 * R2;
     static constexpr int NHG = G0 * G1 * G2;
     static constexpr int NTILE = T0 * T1 * T2;
@@ -240,7 +244,16 @@ struct Geo {
         return l == 0 ? 0 : (l == 1 ? (sb(0) + 2) * sb(1) * sb(2) : (sb(0) + 2) * sb(1) * sb(2) + sb(0) * (sb(1) + 2) * sb(2));
     }
     __device__ static __forceinline__ int cidx(int x, int y, int z) { return x + R0 * (y + R1 * z); }
-    __device__ static __forceinline__ int hidx(int x, int y, int z) { return x + G0 * (y + G1 * z); }
+    // half-grid point (x, y, z) in region half indices
+    __device__ static __forceinline__ int hidx(int x, int y, int z)
+    {
+        return (x - 2 * HO) + G0 * ((D >= 2 ? y - 2 * HO : y) + G1 * (D >= 3 ? z - 2 * HO : z));
+    }
+    // the cell's half-grid points are stored
+    __device__ static __forceinline__ bool in_hg(int x, int y, int z)
+    {
+        return x >= HO && x < R0 - HO && (D < 2 || (y >= HO && y < R1 - HO)) && (D < 3 || (z >= HO && z < R2 - HO));
+    }
 };
 
 // Loop over a box of extents E0 x E1 x E2, x fastest, spread over NT threads.
@@ -472,7 +485,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                 const int m = ends(q0, q1);
                 const T v = m ? bc_point(q0, q1, m) : in[zk * kst + gi];
                 if (zk == 0) ub[G::cidx(x, y, 0)] = v;
-                else hg[G::hidx(2 * x + (zk & 1), 2 * y + ((zk >> 1) & 1), 0)] = v;
+                else if (G::in_hg(x, y, 0)) hg[G::hidx(2 * x + (zk & 1), 2 * y + ((zk >> 1) & 1), 0)] = v;
             }
             return;
         }
@@ -481,6 +494,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
         int gz = D >= 3 ? wrap_index(oz + z - G::H2, n2) : 0;
         long long gi = gx + (long long)n0 * (gy + (long long)n1 * gz);
         ub[G::cidx(x, y, z)] = in[gi];
+        if (!G::in_hg(x, y, z)) return;
 #pragma unroll
         for (int zk = 1; zk < NB; zk++) {
             const int m = zeta_mask<D>(zk);
