@@ -98,8 +98,6 @@ struct StageParams {
     unsigned long long *mm;
 };
 
-constexpr int kMaxWavesPerBlock = 4;
-
 // Read-only per-launch parameters are read through the constant address
 // space so that uniform reads become scalar loads into SGPRs (the compiler
 // does not prove that on its own once the kernel also writes memory).

@@ -366,8 +366,9 @@ af_status build_work(af_ctx *c)
     HIPOK(c, hipMalloc(&c->d_work, sizeof(int4) * work.size()));
     if (c->d_mm) (void)hipFree(c->d_mm);
     c->d_mm = nullptr;
+    // one slot pair per wave of every work item
     c->waves_per_block = (vi.nt + 63) / 64;
-    HIPOK(c, hipMalloc(&c->d_mm, sizeof(unsigned long long) * 2 * af4::kMaxWavesPerBlock * work.size()));
+    HIPOK(c, hipMalloc(&c->d_mm, sizeof(unsigned long long) * 2 * c->waves_per_block * work.size()));
     c->keys_fresh = false;
     HIPOK(c, hipMemcpy(c->d_work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice));
     HIPOK(c, hipMemcpy(c->d_inst, c->ih.data(), sizeof(InstDev) * c->n_inst, hipMemcpyHostToDevice));
