@@ -26,6 +26,7 @@ struct InstDev {
     double cfl;
     int ncrit[3];
     double crit[3][kMaxCrit];  // interior local maxima of |f_l'|
+    double adfc[3][kMaxCrit];  // |f_l'| at them
     double vol;          // cell volume
     double si_gamma;     // smoothness-indicator blending strength
     // potential in the unified form a(u) = s * v (pc1 + v (pc2 + v pc3)) with
@@ -45,6 +46,7 @@ struct InstDev {
     float f_fp0[3];
     float f_pc[3];       // pc1, pc2, pc3
     float f_idx1[3], f_idx2[3], f_i6dx[3];
+    float f_crit[3][kMaxCrit], f_adfc[3][kMaxCrit];
 };
 
 // Control block read by the time-step kernels (uploaded before each af_step).

@@ -158,6 +158,10 @@ void set_f32_params(InstDev &I)
         I.f_idx1[l] = (float)I.idx1[l];
         I.f_idx2[l] = (float)I.idx2[l];
         I.f_i6dx[l] = (float)I.i6dx[l];
+        for (int k = 0; k < af4::kMaxCrit; k++) {
+            I.f_crit[l][k] = (float)I.crit[l][k];
+            I.f_adfc[l][k] = (float)I.adfc[l][k];
+        }
     }
 }
 
@@ -171,6 +175,8 @@ void derive_bounds_params(InstDev &I, const af_problem &P, int dim)
         if (l < dim)
             I.ncrit[l] = host_local_maxima(P.flux[l], P.flux_par[l][0], P.flux_par[l][1], I.umin - w - 1,
                                            I.umax + w + 1, I.crit[l], af4::kMaxCrit);
+        for (int k = 0; k < af4::kMaxCrit; k++)
+            I.adfc[l][k] = k < I.ncrit[l] ? host_adf(P.flux[l], P.flux_par[l][0], P.flux_par[l][1], I.crit[l][k]) : 0.0;
     }
 }
 
@@ -560,11 +566,12 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
         set_f32_params(I);
     }
     c->total = off;
-    c->caps = af4::kCapQF | af4::kCapPP | af4::kCapI32 | af4::kCapBQ | (c->open ? af4::kCapOpen : 0u);
+    c->caps = af4::kCapQF | af4::kCapPP | af4::kCapI32 | af4::kCapBQ | af4::kCapBLF | (c->open ? af4::kCapOpen : 0u);
     for (int i = 0; i < n_inst; i++) {
         const InstDev &I = c->ih[i];
         for (int l = 0; l < c->dim; l++) {
             if (probs[i].flux[l] != AF_F_LINEAR && probs[i].flux[l] != AF_F_QUAD) c->caps &= ~af4::kCapQF;
+            if (probs[i].flux[l] != AF_F_BL && probs[i].flux[l] != AF_F_BL_GRAV) c->caps &= ~af4::kCapBLF;
             if (probs[i].flux[l] != AF_F_QUAD && !(probs[i].flux[l] == AF_F_LINEAR && probs[i].flux_par[l][0] == 0.0))
                 c->caps &= ~af4::kCapBQ;
         }

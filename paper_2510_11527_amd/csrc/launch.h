@@ -20,6 +20,7 @@ enum : unsigned {
     kCapI32 = 4,  // the DoF block of every instance holds fewer than 2^32 bytes
     kCapBQ = 8,   // every flux is c2 u^2 (no linear part)
     kCapOpen = 16,  // some instance has non-periodic ends (only the generic kernel fills ghosts)
+    kCapBLF = 32,   // every flux is Buckley-Leverett, with or without gravity
 };
 
 // One stage launch over nblocks (instance, tile) work items.

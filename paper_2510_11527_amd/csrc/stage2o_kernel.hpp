@@ -57,7 +57,7 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
 }
 
 // kernel variant flags
-enum : int { kOwnPP = 1, kOwnBQ = 2 };
+enum : int { kOwnPP = 1, kOwnBQ = 2, kOwnGen = 4 };
 
 // LDS geometry.  Every array is indexed by the same cell index b = xx + SX yy
 // of the tile region (RX x RY cells: the tile and a halo of 2), so that all
@@ -84,7 +84,12 @@ struct Own2Geo {
 template <class T, bool LIM, int FL, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
 {
-    constexpr bool PP = (FL & kOwnPP) != 0, BQ = (FL & kOwnBQ) != 0;
+    // GEN: Buckley-Leverett fluxes f_l = q (1 - g_l (1-u)^2), q = u^2 / (u^2 +
+    // (1-u)^2) (g_l = 0 without gravity), one branch-free form with the
+    // hardware reciprocal in FP32, f and |f'| recomputed per use; alpha^L
+    // from the host's table of |f'| at the interior maxima
+    constexpr bool PP = (FL & kOwnPP) != 0, BQ = (FL & kOwnBQ) != 0, GEN = (FL & kOwnGen) != 0;
+    static_assert(!(GEN && BQ), "a general flux is not purely quadratic");
     static_assert(TX * TY == 2 * NT && TY % 2 == 0, "two cells per thread");
     static_assert(NT % TX == 0 && NT % 64 == 0, "threads cover whole columns and waves");
     using FG = Own2Geo<TX, TY>;
@@ -181,6 +186,12 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     };
     Phys<T> P;
     if constexpr (!PP) P.load(I, 2);
+    T gg[2], gg2[2];  // g_l and 2 g_l of the Buckley-Leverett fluxes
+#pragma unroll
+    for (int l = 0; l < 2; l++) {
+        gg[l] = Ic->fk[l] == kFBLGrav ? prm(Ic->fp1[l], (float)Ic->fp1[l]) : T(0);
+        gg2[l] = T(2) * gg[l];
+    }
     T c1[2], c2[2], c2x2[2];
 #pragma unroll
     for (int l = 0; l < 2; l++) {
@@ -235,8 +246,38 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         if constexpr (PP) return u * (pc1 + u * (pc2 + u * pc3));
         else return P.a(u);
     };
-    auto fq = [&](int l, T u) -> T { return u * (c1[l] + c2[l] * u); };
-    auto gq = [&](int l, T u) -> T { return fabs(c1[l] + c2x2[l] * u); };
+    auto fq = [&](int l, T u) -> T {
+        if constexpr (GEN) {
+            const T v = T(1) - u, u2 = u * u;
+            const T q = u2 * fast_rcp(u2 + v * v);
+            return q * (T(1) - gg[l] * v * v);
+        } else {
+            return u * (c1[l] + c2[l] * u);
+        }
+    };
+    auto gq = [&](int l, T u) -> T {
+        if constexpr (GEN) {
+            const T v = T(1) - u, u2 = u * u;
+            const T r = fast_rcp(u2 + v * v);
+            const T d1 = T(2) * (u * v) * (r * r);
+            return fabs(d1 * (T(1) - gg[l] * v * v) + (u2 * r) * (gg2[l] * v));
+        } else {
+            return fabs(c1[l] + c2x2[l] * u);
+        }
+    };
+    // max of |f_l'| over [min(a,b), max(a,b)]: the end points and the interior
+    // maxima inside (their |f_l'| tabulated on the host)
+    auto alpha_iv = [&](int l, T a, T b) -> T {
+        const T lo = vmin(a, b), hi = vmax(a, b);
+        T r = vmax(gq(l, a), gq(l, b));
+        const int nc = Ic->ncrit[l];
+        for (int k = 0; k < nc; k++) {
+            const T cv = prm(Ic->crit[l][k], Ic->f_crit[l][k]);
+            const T av = prm(Ic->adfc[l][k], Ic->f_adfc[l][k]);
+            r = (cv >= lo && cv <= hi) ? vmax(r, av) : r;
+        }
+        return r;
+    };
     // grid s at cell index b (the neighbours of b are b +- 1 and b +- SX)
     auto S = [&](int s, int b) -> V2<T> { return smem[s * SG + b]; };
     auto Su = [&](int s, int b) -> T { return smem[s * SG + b].x; };
@@ -443,7 +484,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
                 um = B.x - Km * (dA + D * gph);
             } else {
                 const T fa = fq(l, A.x), fb = fq(l, B.x);
-                const T al = fmax(gq(l, A.x), gq(l, B.x));
+                const T al = GEN ? alpha_iv(l, A.x, B.x) : fmax(gq(l, A.x), gq(l, B.x));
                 fL = T(0.5) * (fa + fb) - T(0.5) * al * (B.x - A.x);
                 up = A.x + Km * (dA - fL + fa);
                 um = B.x + Km * (fL - fb - dA);

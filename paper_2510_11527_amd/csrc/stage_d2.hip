@@ -57,7 +57,9 @@ hipError_t launch_kind(bool lim, bool si, unsigned caps, int nblocks, const void
     const bool qf = (caps & kCapQF) != 0;
     if (KIND != 0 && (caps & kCapOpen)) return hipErrorInvalidValue;
     if constexpr (KIND == 4) {
-        if (si || !qf || !(caps & kCapI32)) return hipErrorInvalidValue;
+        if (si || !(caps & kCapI32) || !(qf || (caps & kCapBLF))) return hipErrorInvalidValue;
+        if (!qf) return (caps & kCapPP) ? launch_own_lim<T, kOwnGen | kOwnPP, TX, TY, NT>(lim, nblocks, params, s)
+                                        : launch_own_lim<T, kOwnGen, TX, TY, NT>(lim, nblocks, params, s);
         const int fl = ((caps & kCapPP) ? kOwnPP : 0) | ((caps & kCapBQ) ? kOwnBQ : 0);
         switch (fl) {
         case 0: return launch_own_lim<T, 0, TX, TY, NT>(lim, nblocks, params, s);
@@ -88,7 +90,7 @@ bool fits_kind(bool lim, bool si, unsigned caps)
     const bool qf = (caps & kCapQF) != 0;
     if (KIND != 0 && (caps & kCapOpen)) return false;
     if constexpr (KIND == 4) {
-        if (si || !qf || !(caps & kCapI32)) return false;
+        if (si || !(caps & kCapI32) || !(qf || (caps & kCapBLF))) return false;
         return stage2o_lds_bytes<T, true, TX, TY>() <= kLdsCap && stage2o_lds_bytes<T, false, TX, TY>() <= kLdsCap;
     } else if constexpr (KIND == 0) {
         if (lim) return si ? stage_lds_bytes<2, T, true, true, TX, TY, 1>() <= kLdsCap
