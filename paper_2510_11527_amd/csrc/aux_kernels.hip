@@ -312,9 +312,9 @@ bool stage_supported(int dim, int prec, bool lim, bool si, unsigned caps, int va
 hipError_t stage_launch(int dim, int prec, bool lim, bool si, unsigned caps, int variant, int nblocks, const void *params,
                         hipStream_t s)
 {
-    if (dim == 1) return stage_launch_d1(prec, lim, si, variant, nblocks, params, s);
+    if (dim == 1) return stage_launch_d1(prec, lim, si, caps, variant, nblocks, params, s);
     if (dim == 2) return stage_launch_d2(prec, lim, si, caps, variant, nblocks, params, s);
-    if (dim == 3) return stage_launch_d3(prec, lim, si, variant, nblocks, params, s);
+    if (dim == 3) return stage_launch_d3(prec, lim, si, caps, variant, nblocks, params, s);
     return hipErrorInvalidValue;
 }
 

@@ -34,10 +34,10 @@ bool stage_supported(int dim, int prec, bool lim, bool si, unsigned caps, int va
 bool stage_supported_d1(int prec, bool lim, bool si, int variant);
 bool stage_supported_d2(int prec, bool lim, bool si, unsigned caps, int variant);
 bool stage_supported_d3(int prec, bool lim, bool si, int variant);
-hipError_t stage_launch_d1(int prec, bool lim, bool si, int variant, int nblocks, const void *params, hipStream_t s);
+hipError_t stage_launch_d1(int prec, bool lim, bool si, unsigned caps, int variant, int nblocks, const void *params, hipStream_t s);
 hipError_t stage_launch_d2(int prec, bool lim, bool si, unsigned caps, int variant, int nblocks, const void *params,
                            hipStream_t s);
-hipError_t stage_launch_d3(int prec, bool lim, bool si, int variant, int nblocks, const void *params, hipStream_t s);
+hipError_t stage_launch_d3(int prec, bool lim, bool si, unsigned caps, int variant, int nblocks, const void *params, hipStream_t s);
 
 // FP64 max over faces of alpha_l/dx_l + kappa_max/dx_l^2 of the averages of
 // U (per instance, into InstState::wmax), plus the divergence check.

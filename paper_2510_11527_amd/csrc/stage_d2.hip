@@ -8,13 +8,13 @@ namespace {
 
 constexpr long kLdsCap = 160L * 1024L;
 
-template <class T, bool LIM, bool SI, int TX, int TY, int NT>
+template <class T, bool LIM, bool SI, bool QF, int TX, int TY, int NT>
 hipError_t launch_generic(int nblocks, const void *params, hipStream_t s)
 {
     if constexpr (stage_lds_bytes<2, T, LIM, SI, TX, TY, 1>() > kLdsCap) {
         return hipErrorInvalidValue;
     } else {
-        hipLaunchKernelGGL((stage_kernel<2, T, LIM, SI, TX, TY, 1, NT>), dim3(nblocks), dim3(NT), 0, s,
+        hipLaunchKernelGGL((stage_kernel<2, T, LIM, SI, QF, TX, TY, 1, NT>), dim3(nblocks), dim3(NT), 0, s,
                            *(const StageParams<T> *)params);
         return hipGetLastError();
     }
@@ -68,10 +68,16 @@ hipError_t launch_kind(bool lim, bool si, unsigned caps, int nblocks, const void
         default: return launch_own_lim<T, kOwnPP | kOwnBQ, TX, TY, NT>(lim, nblocks, params, s);
         }
     } else if constexpr (KIND == 0) {
-        if (lim) return si ? launch_generic<T, true, true, TX, TY, NT>(nblocks, params, s)
-                           : launch_generic<T, true, false, TX, TY, NT>(nblocks, params, s);
-        return si ? launch_generic<T, false, true, TX, TY, NT>(nblocks, params, s)
-                  : launch_generic<T, false, false, TX, TY, NT>(nblocks, params, s);
+        if (qf) {
+            if (lim) return si ? launch_generic<T, true, true, true, TX, TY, NT>(nblocks, params, s)
+                               : launch_generic<T, true, false, true, TX, TY, NT>(nblocks, params, s);
+            return si ? launch_generic<T, false, true, true, TX, TY, NT>(nblocks, params, s)
+                      : launch_generic<T, false, false, true, TX, TY, NT>(nblocks, params, s);
+        }
+        if (lim) return si ? launch_generic<T, true, true, false, TX, TY, NT>(nblocks, params, s)
+                           : launch_generic<T, true, false, false, TX, TY, NT>(nblocks, params, s);
+        return si ? launch_generic<T, false, true, false, TX, TY, NT>(nblocks, params, s)
+                  : launch_generic<T, false, false, false, TX, TY, NT>(nblocks, params, s);
     } else {
         constexpr bool FT = KIND == 1;
         if (si) return hipErrorInvalidValue;

@@ -6,31 +6,34 @@ namespace af4 {
 
 namespace {
 
-template <class T, bool LIM, bool SI, int TX, int TY, int TZ, int NT>
+template <class T, bool LIM, bool SI, bool QF, int TX, int TY, int TZ, int NT>
 hipError_t launch_one(int nblocks, const void *params, hipStream_t s)
 {
     if constexpr (stage_lds_bytes<3, T, LIM, SI, TX, TY, TZ>() > 160L * 1024L) {
         return hipErrorInvalidValue;
     } else {
-        hipLaunchKernelGGL((stage_kernel<3, T, LIM, SI, TX, TY, TZ, NT>), dim3(nblocks), dim3(NT), 0, s,
+        hipLaunchKernelGGL((stage_kernel<3, T, LIM, SI, QF, TX, TY, TZ, NT>), dim3(nblocks), dim3(NT), 0, s,
                            *(const StageParams<T> *)params);
         return hipGetLastError();
     }
 }
 
-template <int TX, int TY, int TZ, int NT>
-hipError_t launch_tile(int prec, bool lim, bool si, int nblocks, const void *params, hipStream_t s)
+template <class T, bool QF, int TX, int TY, int TZ, int NT>
+hipError_t launch_tq(bool lim, bool si, int nblocks, const void *params, hipStream_t s)
 {
-    if (prec == 32) {
-        if (lim) return si ? launch_one<float, true, true, TX, TY, TZ, NT>(nblocks, params, s)
-                           : launch_one<float, true, false, TX, TY, TZ, NT>(nblocks, params, s);
-        return si ? launch_one<float, false, true, TX, TY, TZ, NT>(nblocks, params, s)
-                  : launch_one<float, false, false, TX, TY, TZ, NT>(nblocks, params, s);
-    }
-    if (lim) return si ? launch_one<double, true, true, TX, TY, TZ, NT>(nblocks, params, s)
-                       : launch_one<double, true, false, TX, TY, TZ, NT>(nblocks, params, s);
-    return si ? launch_one<double, false, true, TX, TY, TZ, NT>(nblocks, params, s)
-              : launch_one<double, false, false, TX, TY, TZ, NT>(nblocks, params, s);
+    if (lim) return si ? launch_one<T, true, true, QF, TX, TY, TZ, NT>(nblocks, params, s)
+                       : launch_one<T, true, false, QF, TX, TY, TZ, NT>(nblocks, params, s);
+    return si ? launch_one<T, false, true, QF, TX, TY, TZ, NT>(nblocks, params, s)
+              : launch_one<T, false, false, QF, TX, TY, TZ, NT>(nblocks, params, s);
+}
+
+template <int TX, int TY, int TZ, int NT>
+hipError_t launch_tile(int prec, bool lim, bool si, bool qf, int nblocks, const void *params, hipStream_t s)
+{
+    if (prec == 32) return qf ? launch_tq<float, true, TX, TY, TZ, NT>(lim, si, nblocks, params, s)
+                              : launch_tq<float, false, TX, TY, TZ, NT>(lim, si, nblocks, params, s);
+    return qf ? launch_tq<double, true, TX, TY, TZ, NT>(lim, si, nblocks, params, s)
+              : launch_tq<double, false, TX, TY, TZ, NT>(lim, si, nblocks, params, s);
 }
 
 template <int TX, int TY, int TZ>
@@ -62,12 +65,13 @@ bool stage_supported_d3(int prec, bool lim, bool si, int variant)
     return false;
 }
 
-hipError_t stage_launch_d3(int prec, bool lim, bool si, int variant, int nblocks, const void *params, hipStream_t s)
+hipError_t stage_launch_d3(int prec, bool lim, bool si, unsigned caps, int variant, int nblocks, const void *params,
+                           hipStream_t s)
 {
     if (nblocks <= 0) return hipSuccess;
     switch (variant) {
 #define AF4_CASE(V, TX, TY, TZ, NT, NAME) \
-    case V: return launch_tile<TX, TY, TZ, NT>(prec, lim, si, nblocks, params, s);
+    case V: return launch_tile<TX, TY, TZ, NT>(prec, lim, si, (caps & kCapQF) != 0, nblocks, params, s);
         AF4_VARIANTS_D3(AF4_CASE)
 #undef AF4_CASE
     }

@@ -374,7 +374,9 @@ __device__ __forceinline__ void atomic_max_wave_t(unsigned long long *dst, T v)
     }
 }
 
-template <int D, class T, bool LIM, bool SI, int TX, int TY, int TZ, int NT>
+// QF: every flux is c1 u + c2 u^2 (evaluated in closed form, no branches on
+// the flux kind)
+template <int D, class T, bool LIM, bool SI, bool QF, int TX, int TY, int TZ, int NT>
 __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
 {
     constexpr int HL = SI ? 3 : 2;
@@ -462,6 +464,24 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
 
     Phys<T> P;
     P.load(I, D);
+    T qc1[3], qc2[3];  // QF: f_l = qc1 u + qc2 u^2
+#pragma unroll
+    for (int l = 0; l < 3; l++) {
+        qc1[l] = I.fk[l] == kFLinear ? (T)I.fp0[l] : T(0);
+        qc2[l] = I.fk[l] == kFQuad ? (T)I.fp0[l] : T(0);
+    }
+    auto Ff = [&](int l, T u) -> T {
+        if constexpr (QF) return u * (qc1[l] + qc2[l] * u);
+        else return P.f(l, u);
+    };
+    auto Fg = [&](int l, T u) -> T {
+        if constexpr (QF) return fabs(qc1[l] + T(2) * qc2[l] * u);
+        else return P.adf(l, u);
+    };
+    auto Fint = [&](int l, T x, T y) -> T {  // max |f_l'| over [min(x,y), max(x,y)]
+        if constexpr (QF) return fmax(Fg(l, x), Fg(l, y));
+        else return P.alpha_int(l, x, y);
+    };
     const T dt = (T)dtd * p.dts;
     const T K = T(2 * D);
     T idx1[3], idx2[3], i6dx[3], mu[3], nu[3];
@@ -592,9 +612,9 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
 #pragma unroll
                 for (int s = -2; s <= 2; s++) {
                     zz[s + 2] = hg[G::hidx(px + s * sx, py + s * sy, pz + s * sz)];
-                    ff[s + 2] = P.f(l, zz[s + 2]);
+                    ff[s + 2] = Ff(l, zz[s + 2]);
                     aa[s + 2] = P.a(zz[s + 2]);
-                    alpha = fmax(alpha, P.adf(l, zz[s + 2]));
+                    alpha = fmax(alpha, Fg(l, zz[s + 2]));
                 }
                 T conv = -((ff[0] - T(8) * ff[1] + T(8) * ff[3] - ff[4]) +
                            alpha * (zz[0] - T(4) * zz[1] + T(6) * zz[2] - T(4) * zz[3] + zz[4])) * i6dx[l];
@@ -607,7 +627,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                             nm = ub[G::cidx(x, y, z)];
                             np = ub[G::cidx(x + sx, y + sy, z + sz)];
                         }
-                        const T fm = P.f(l, nm), fp = P.f(l, np);
+                        const T fm = Ff(l, nm), fp = Ff(l, np);
                         const T Fr = T(0.5) * (ff[2] + fp) - T(0.5) * alpha * (np - u0);
                         const T Fl = T(0.5) * (fm + ff[2]) - T(0.5) * alpha * (u0 - nm);
                         const T convL = -T(2) * idx1[l] * (Fr - Fl);
@@ -689,8 +709,8 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
             const T ua = ub[G::cidx(x, y, z)], ubb = ub[G::cidx(x + sx, y + sy, z + sz)];
             T fL = T(0), up = T(0), um = T(0), dA = T(0);
             if (LIM || use_si) {
-                const T fa = P.f(l, ua), fb = P.f(l, ubb);
-                const T al = P.alpha_int(l, ua, ubb);
+                const T fa = Ff(l, ua), fb = Ff(l, ubb);
+                const T al = Fint(l, ua, ubb);
                 fL = T(0.5) * (fa + fb) - T(0.5) * al * (ubb - ua);
                 if constexpr (LIM) {
                     dA = (P.a(ubb) - P.a(ua)) * idx1[l];
@@ -715,7 +735,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                         for (int oxx = (l != 0 ? -1 : 0); oxx <= (l != 0 ? 1 : 0); oxx++) {
                             const T w = T((l != 0 && oxx == 0 ? 4 : 1) * (l != 1 && D >= 2 && oy == 0 ? 4 : 1) *
                                           (l != 2 && D >= 3 && oz == 0 ? 4 : 1));
-                            fH += w * P.f(l, hg[G::hidx(bx + oxx, by + oy, bz + oz)]);
+                            fH += w * Ff(l, hg[G::hidx(bx + oxx, by + oy, bz + oz)]);
                         }
                 fH *= D == 1 ? T(1) : (D == 2 ? T(1.0 / 6.0) : T(1.0 / 36.0));
             }
