@@ -65,3 +65,47 @@ def test_package_has_no_oracle_dependency():
             if f.endswith((".py", ".cpp", ".hip", ".h", ".hpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "liborc" not in txt and "af_oracle" not in txt, f
+
+
+def test_new_problem_fields_validated_before_device_use():
+    """The diffusion form and the ends are checked by af_create before any
+    device call."""
+    from paper_2510_11527_amd import af
+    from paper_2510_11527_amd import workloads as W
+    s2, _ = W.config2(n=8)
+    s1, _ = W.config_ek(n_inst=1, n=16)[0]
+    s3, _ = W.config5(n=4)
+    cases = [
+        (dict(s2, diffusion_form="nodc"), af.AF_ERR_UNSUPPORTED),       # App. A is 1D
+        (dict(s1, bc=("periodic", "outflow")), af.AF_ERR_ARG),          # both ends periodic or neither
+        (dict(s1, bc=(("dirichlet", 1.5), "outflow")), af.AF_ERR_BOUNDS),
+        (dict(s1, bc=(("dirichlet", float("nan")), "outflow")), af.AF_ERR_ARG),
+        (dict(s3, bc=("outflow", "outflow")), af.AF_ERR_UNSUPPORTED),   # no 3D open ends
+        (dict(s2, si=True, bcs=[("outflow", "outflow"), ("periodic", "periodic")]), af.AF_ERR_UNSUPPORTED),
+        (dict(s1, bcs=[("outflow", "outflow"), ("outflow", "outflow")]), af.AF_ERR_ARG),  # unused axis
+    ]
+    for spec, status in cases:
+        with pytest.raises(af.AFError) as e:
+            af.Context(spec)
+        assert e.value.status == status, (spec.get("bc"), spec.get("bcs"), e.value)
+
+
+def test_problem_struct_layout_matches_the_header(tmp_path):
+    """The ctypes mirror of af_problem / af_norms_t has the C layout: a C
+    program compiled against include/af.h prints sizes and offsets."""
+    import subprocess
+    from paper_2510_11527_amd import af
+    fields = [f for f, _ in af.AfProblem._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "af.h"', 'int main(void) {',
+           '  printf("%zu %zu\\n", sizeof(af_problem), sizeof(af_norms_t));']
+    src += ['  printf("%%zu\\n", offsetof(af_problem, %s));' % f for f in fields]
+    src += ['  return 0;', '}']
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    assert int(out[0]) == ctypes.sizeof(af.AfProblem)
+    assert int(out[1]) == ctypes.sizeof(af.AfNorms)
+    for f, off in zip(fields, out[2:]):
+        assert int(off) == getattr(af.AfProblem, f).offset, f
