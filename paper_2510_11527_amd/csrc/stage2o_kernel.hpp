@@ -57,7 +57,7 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned vof
 }
 
 // kernel variant flags
-enum : int { kOwnPP = 1, kOwnBQ = 2, kOwnGen = 4 };
+enum : int { kOwnPP = 1, kOwnBQ = 2, kOwnGen = 4, kOwnOpen = 8 };
 
 // LDS geometry.  Every array is indexed by the same cell index b = xx + SX yy
 // of the tile region (RX x RY cells: the tile and a halo of 2), so that all
@@ -89,6 +89,7 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     // hardware reciprocal in FP32, f and |f'| recomputed per use; alpha^L
     // from the host's table of |f'| at the interior maxima
     constexpr bool PP = (FL & kOwnPP) != 0, BQ = (FL & kOwnBQ) != 0, GEN = (FL & kOwnGen) != 0;
+    constexpr bool OPEN = (FL & kOwnOpen) != 0;
     static_assert(!(GEN && BQ), "a general flux is not purely quadratic");
     static_assert(TX * TY == 2 * NT && TY % 2 == 0, "two cells per thread");
     static_assert(NT % TX == 0 && NT % 64 == 0, "threads cover whole columns and waves");
@@ -284,6 +285,42 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     auto Sa = [&](int s, int b) -> T { return smem[s * SG + b].y; };
     auto bix = [](int xx, int yy) -> int { return xx + SX * yy; };
 
+    // Non-periodic ends: a half-grid point on or beyond an open end (global
+    // half indices q0, q1) takes the Dirichlet value of the first Dirichlet
+    // end among those it lies on or beyond, else (outflow) the mean average of
+    // the domain cells around the point moved onto the boundary; the stored
+    // point values on the high ends are not evolved.
+    // (OPEN: instances may have non-periodic ends; a separate instantiation
+    // keeps this code out of the periodic kernels)
+    const bool open = OPEN && (Ic->bc[0][0] != 0 || Ic->bc[1][0] != 0);
+    auto ends = [&](int q0, int q1) -> int {
+        return ((Ic->bc[0][0] != 0 && (q0 <= -1 || q0 >= 2 * n0 - 1)) ? 1 : 0) |
+               ((Ic->bc[1][0] != 0 && (q1 <= -1 || q1 >= 2 * n1 - 1)) ? 2 : 0);
+    };
+    auto bc_point = [&](int q0, int q1, int m) -> T {
+#pragma unroll
+        for (int l = 0; l < 2; l++) {
+            const int q = l == 0 ? q0 : q1, side = q <= -1 ? 0 : 1;
+            if ((m >> l & 1) && Ic->bc[l][side] == 1) return prm(Ic->bcv[l][side], (float)Ic->bcv[l][side]);
+        }
+        int lo[2], hi[2];
+#pragma unroll
+        for (int l = 0; l < 2; l++) {
+            const int q = l == 0 ? q0 : q1, nl = l == 0 ? n0 : n1;
+            if (m >> l & 1) lo[l] = hi[l] = q <= -1 ? 0 : nl - 1;
+            else if (q & 1) { lo[l] = (q - 1) >> 1; hi[l] = lo[l] + 1; }
+            else lo[l] = hi[l] = q >> 1;
+        }
+        T sum = T(0);
+        int cnt = 0;
+        for (int j = lo[1]; j <= hi[1]; j++)
+            for (int i = lo[0]; i <= hi[0]; i++) {
+                sum += ld(rin, 0, (unsigned)(wrap(i, n0, false) + n0 * wrap(j, n1, false)));
+                cnt++;
+            }
+        return sum / T(cnt);
+    };
+
     // ---- A: cells of the tile and its halo -> LDS with their potentials.
     // Loads are issued in the order they are consumed (own cells, halo cells,
     // then U^n, which is needed only by the updates): the memory counter the
@@ -339,6 +376,23 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
 #pragma unroll
         for (int z = 0; z < 4; z++) x1v[0][z] = x1v[1][z] = T(0);
     }
+    if (open) {
+        // values on or beyond open ends (own cells past a partial tile's
+        // domain edge included) take the boundary rule
+        auto fix = [&](int xx, int yy, T *u) {
+            const int c0 = ox + xx - 2, c1 = oy + yy - 2;
+#pragma unroll
+            for (int z = 0; z < 4; z++) {
+                const int q0 = 2 * c0 + (z & 1), q1 = 2 * c1 + (z >> 1);
+                const int m = ends(q0, q1);
+                if (m) u[z] = bc_point(q0, q1, m);
+            }
+        };
+        fix(x, y, own[0]);
+        fix(x, y + 1, own[1]);
+#pragma unroll
+        for (int k = 0; k < NHI; k++) fix(hb[k] % SX, hb[k] / SX, halo[k]);
+    }
     auto put_cell = [&](int b, const T *u) {
         smem[b] = V2<T>{u[0], pot(u[0])};
         smem[SXF * SG + b] = V2<T>{u[1], pot(u[1])};
@@ -354,6 +408,15 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
 
     // ---- B: cell centres by inverting the tensor Simpson rule
     auto centre = [&](int b) {
+        if (open) {
+            const int c0 = ox + b % SX - 2, c1 = oy + b / SX - 2;
+            const int m = ends(2 * c0, 2 * c1);
+            if (m) {  // a ghost cell's centre
+                const T u = bc_point(2 * c0, 2 * c1, m);
+                smem[SC * SG + b] = V2<T>{u, pot(u)};
+                return;
+            }
+        }
         const T faces = Su(SXF, b - 1) + Su(SXF, b) + Su(SYF, b - SX) + Su(SYF, b);
         const T corners = Su(SK, b - 1 - SX) + Su(SK, b - SX) + Su(SK, b - 1) + Su(SK, b);
         const T u = (T(36) * Su(0, b) - T(4) * faces - corners) * T(0.0625);
@@ -443,14 +506,25 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
             if (!own) continue;
 #pragma unroll
             for (int z = 1; z < 4; z++) {
+                // stored points on a high open end: right-hand side 0; a stage
+                // writes the Dirichlet value or passes the input through, and
+                // combines with the stored input
+                const int me = open ? ends(2 * (ox + ci) + (z & 1), 2 * (oy + cj + c) + (z >> 1)) : 0;
                 if (residual) {
-                    st(z, gi, R[c][z - 1]);
+                    st(z, gi, me ? T(0) : R[c][z - 1]);
                     continue;
                 }
                 T v = R[c][z - 1];
+                T vin = Su(z == 1 ? SXF : (z == 2 ? SYF : SK), c == 0 ? b0 : b1);
+                if (me) {
+                    vin = v = ld(rin, z, gi);
+#pragma unroll
+                    for (int l = 1; l >= 0; l--)
+                        if ((me >> l & 1) && Ic->bc[l][1] == 1) v = prm(Ic->bcv[l][1], (float)Ic->bcv[l][1]);
+                }
                 if (!isfinite(v)) bad = true;
                 if constexpr (LIM) v = clampb(v, umin, umaxv);
-                v = combine(v, unv[c][z], x1v[c][z], Su(z == 1 ? SXF : (z == 2 ? SYF : SK), c == 0 ? b0 : b1));
+                v = combine(v, unv[c][z], x1v[c][z], vin);
                 if constexpr (LIM) v = clampb(v, umin, umaxv);
                 st(z, gi, v);
             }

@@ -55,18 +55,20 @@ template <class T, int TX, int TY, int NT, int KIND>
 hipError_t launch_kind(bool lim, bool si, unsigned caps, int nblocks, const void *params, hipStream_t s)
 {
     const bool qf = (caps & kCapQF) != 0;
-    if (KIND != 0 && (caps & kCapOpen)) return hipErrorInvalidValue;
+    if (KIND != 0 && KIND != 4 && (caps & kCapOpen)) return hipErrorInvalidValue;  // ghosts: generic, own-items
     if constexpr (KIND == 4) {
         if (si || !(caps & kCapI32) || !(qf || (caps & kCapBLF))) return hipErrorInvalidValue;
-        if (!qf) return (caps & kCapPP) ? launch_own_lim<T, kOwnGen | kOwnPP, TX, TY, NT>(lim, nblocks, params, s)
-                                        : launch_own_lim<T, kOwnGen, TX, TY, NT>(lim, nblocks, params, s);
-        const int fl = ((caps & kCapPP) ? kOwnPP : 0) | ((caps & kCapBQ) ? kOwnBQ : 0);
+        const int fl = (!qf ? kOwnGen : 0) | ((caps & kCapPP) ? kOwnPP : 0) | ((qf && (caps & kCapBQ)) ? kOwnBQ : 0) |
+                       ((caps & kCapOpen) ? kOwnOpen : 0);
         switch (fl) {
-        case 0: return launch_own_lim<T, 0, TX, TY, NT>(lim, nblocks, params, s);
-        case kOwnPP: return launch_own_lim<T, kOwnPP, TX, TY, NT>(lim, nblocks, params, s);
-        case kOwnBQ: return launch_own_lim<T, kOwnBQ, TX, TY, NT>(lim, nblocks, params, s);
-        default: return launch_own_lim<T, kOwnPP | kOwnBQ, TX, TY, NT>(lim, nblocks, params, s);
+#define AF4_OWN_FL(F) \
+    case F: return launch_own_lim<T, F, TX, TY, NT>(lim, nblocks, params, s);
+            AF4_OWN_FL(0) AF4_OWN_FL(kOwnPP) AF4_OWN_FL(kOwnBQ) AF4_OWN_FL(kOwnPP | kOwnBQ) AF4_OWN_FL(kOwnGen)
+            AF4_OWN_FL(kOwnGen | kOwnPP) AF4_OWN_FL(kOwnOpen) AF4_OWN_FL(kOwnOpen | kOwnPP) AF4_OWN_FL(kOwnOpen | kOwnBQ)
+            AF4_OWN_FL(kOwnOpen | kOwnPP | kOwnBQ) AF4_OWN_FL(kOwnOpen | kOwnGen) AF4_OWN_FL(kOwnOpen | kOwnGen | kOwnPP)
+#undef AF4_OWN_FL
         }
+        return hipErrorInvalidValue;
     } else if constexpr (KIND == 0) {
         if (qf) {
             if (lim) return si ? launch_generic<T, true, true, true, TX, TY, NT>(nblocks, params, s)
@@ -94,7 +96,7 @@ template <class T, int TX, int TY, int KIND>
 bool fits_kind(bool lim, bool si, unsigned caps)
 {
     const bool qf = (caps & kCapQF) != 0;
-    if (KIND != 0 && (caps & kCapOpen)) return false;
+    if (KIND != 0 && KIND != 4 && (caps & kCapOpen)) return false;
     if constexpr (KIND == 4) {
         if (si || !(caps & kCapI32) || !(qf || (caps & kCapBLF))) return false;
         return stage2o_lds_bytes<T, true, TX, TY>() <= kLdsCap && stage2o_lds_bytes<T, false, TX, TY>() <= kLdsCap;

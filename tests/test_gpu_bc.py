@@ -185,14 +185,19 @@ def test_open_ends_2d_residual_matches_oracle(prec):
         spec = spec2(21, fl, df, bcs, precision=prec)
         s, U = prepare(spec, state2(spec, rng), prec)
         note("bc2 residual prec=%d bcs=%s flux=%s" % (prec, bcs, fl[0]))
-        ctx = af.Context(s)
-        assert ctx.variant_name(ctx.variant()).startswith("generic")
-        ctx.set_state(0, U)
-        R = ctx.residual(0)
-        ctx.close()
         Ro = oracle.rhs(oracle.problem(s), U)
-        err = rel_l1(R, Ro)
-        assert err <= TOL[prec] * (10 if prec == 32 else 1), err
+        ctx = af.Context(s)
+        for v in range(ctx.num_variants()):  # every 2D kernel family that takes open ends
+            try:
+                ctx.set_variant(v)
+            except af.AFError:
+                continue
+            ctx.set_state(0, U)
+            R = ctx.residual(0)
+            err = rel_l1(R, Ro)
+            note("   variant %s: %.2e" % (ctx.variant_name(v), err))
+            assert err <= TOL[prec] * (10 if prec == 32 else 1), (ctx.variant_name(v), err)
+        ctx.close()
 
 
 @pytest.mark.parametrize("prec", [64, 32])
@@ -205,13 +210,14 @@ def test_open_ends_2d_forward_euler_stage_matches_oracle(prec, lim):
         s, U = prepare(spec, state2(spec, rng), prec)
         P = oracle.problem(s)
         dt = oracle.dt_cfl(P, U, s["cfl"])
-        note("bc2 fe prec=%d lim=%d bcs=%s flux=%s dt=%.3e" % (prec, lim, bcs, fl[0], dt))
-        V, t, used, nrm = gpu_run(s, U, dts=[dt], integrator="euler")
         Vo, dg = oracle.fe(P, U, dt)
-        err = rel_l1(V, Vo)
-        assert err <= TOL[prec], err
-        if lim:
-            assert min(v.min() for v in V) >= s["umin"] and max(v.max() for v in V) <= s["umax"]
+        for var in (0, 5):  # own-items 32x16 and generic 32x8
+            note("bc2 fe prec=%d lim=%d bcs=%s flux=%s dt=%.3e variant=%d" % (prec, lim, bcs, fl[0], dt, var))
+            V, t, used, nrm = gpu_run(s, U, dts=[dt], integrator="euler", variant=var)
+            err = rel_l1(V, Vo)
+            assert err <= TOL[prec], err
+            if lim:
+                assert min(v.min() for v in V) >= s["umin"] and max(v.max() for v in V) <= s["umax"]
 
 
 @pytest.mark.parametrize("prec", [64, 32])
