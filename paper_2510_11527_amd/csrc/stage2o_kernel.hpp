@@ -1,5 +1,6 @@
 // stage2o_kernel.hpp -- 2D stage kernel for fluxes f_l = c1 u + c2 u^2 (linear
-// advection, Burgers), organised around thread-owned work items.
+// advection, Burgers) and Buckley-Leverett fluxes, organised around
+// thread-owned work items.
 //
 // Same arithmetic as the generic kernel of stage_kernel.hpp (the compact
 // fourth-order AF scheme with monolithic convex limiting, J. Duan, arXiv
@@ -28,6 +29,12 @@
 //     factored differences f(a) - f^L and f^L - f(b);
 //   * the scales 1/(6 dx), 1/dx^2 and dt are folded into one multiply-add
 //     per term of the point-value update;
+//   * Buckley-Leverett fluxes (flag kOwnGen) take one branch-free rational
+//     form with the hardware reciprocal in FP32, recomputed per use, and the
+//     interval maximum of |f'| from host-tabulated values at the interior
+//     maxima;
+//   * non-periodic ends (flag kOwnOpen, separate instantiations) replace the
+//     values on or beyond an open end by the boundary rule after the loads;
 //   * global memory is addressed with 32-bit byte offsets from per-DoF-kind
 //     base pointers (a plane holds fewer than 2^32 bytes; the host checks).
 #pragma once

@@ -7,10 +7,11 @@ namespace af4 {
 // 1D: two cells per thread measured fastest (more work per barrier)
 #define AF4_VARIANTS_D1(X) X(0, 512, 1, 1, 256, "generic-512") X(1, 256, 1, 1, 256, "generic-256") \
     X(2, 128, 1, 1, 128, "generic-128")
-// 2D: KIND 4 = thread-owned-items kernel for fluxes c1 u + c2 u^2, 1 = tuned
-// kernel with a {u,a,f_x,f_y} half-grid table (any flux), 2 = tuned kernel
-// with a {u,a} table (fluxes c1 u + c2 u^2), 0 = generic kernel (the only one
-// with SI blending)
+// 2D: KIND 4 = thread-owned-items kernel for fluxes c1 u + c2 u^2 and
+// Buckley-Leverett fluxes (periodic or open ends), 1 = tuned kernel with a
+// {u,a,f_x,f_y} half-grid table (any flux, periodic), 2 = tuned kernel with a
+// {u,a} table (fluxes c1 u + c2 u^2, periodic), 0 = generic kernel (the only
+// one with SI blending)
 #define AF4_VARIANTS_D2(X)                                                                          \
     X(0, 32, 16, 1, 256, 4, "2d-own-32x16") X(1, 32, 8, 1, 128, 4, "2d-own-32x8")                    \
     X(2, 32, 16, 1, 256, 1, "2d-table4-32x16") X(3, 32, 8, 1, 128, 1, "2d-table4-32x8")              \
