@@ -42,6 +42,20 @@ __device__ __forceinline__ float fast_rcp<float>(float v)
     return __builtin_amdgcn_rcpf(v);
 }
 
+// e^x of a blending weight (x <= 0): exp in FP64; in FP32 the hardware 2^y
+// of y = x log2(e), whose relative error (about |y| 2^-24 from rounding y,
+// plus an ulp) is far inside the FP32 tolerance for the weights' arguments
+template <class T>
+__device__ __forceinline__ T blend_exp(T x)
+{
+    return exp(x);
+}
+template <>
+__device__ __forceinline__ float blend_exp<float>(float x)
+{
+    return __builtin_amdgcn_exp2f(x * 1.44269504f);
+}
+
 // p0 * u^p (powers other than 1, 2, 3): kept out of line so that the
 // stage kernels do not carry a pow expansion at every evaluation site
 template <class T>
@@ -217,11 +231,20 @@ struct Geo {
     static constexpr int T0 = TX, T1 = D >= 2 ? TY : 1, T2 = D >= 3 ? TZ : 1;
     static constexpr int H0 = HL, H1 = D >= 2 ? HL : 0, H2 = D >= 3 ? HL : 0;
     static constexpr int R0 = T0 + 2 * H0, R1 = T1 + 2 * H1, R2 = T2 + 2 * H2;
-    // the half grid covers the region less its outer HO cells: the point
-    // stencils reach two cells, only the smoothness indicators (averages)
-    // reach a third
-    static constexpr int HO = HL - 2;
-    static constexpr int G0 = 2 * (R0 - 2 * HO), G1 = D >= 2 ? 2 * (R1 - 2 * HO) : 1, G2 = D >= 3 ? 2 * (R2 - 2 * HO) : 1;
+    // the half grid holds, along every axis, the half indices [2h-3, 2h+2t+1]:
+    // the tile's points, the reach of their 5-point stencils, the centres of
+    // one more cell on each side and the outer face points of those cells
+    // (the centre inversion and the potentials of the outermost cells read
+    // them); the averages of the region reach further only for the
+    // smoothness indicators.  LDS is ample in 1D and 2D: in 2D the held
+    // range starts one point earlier, on a cell's first point (even
+    // positions keep a cell's two points in one aligned pair), and in 1D the
+    // half grid spans the whole region, so that staging needs no checks.
+    static constexpr int AL = D == 2 ? 1 : 0;
+    static constexpr int HB0 = D == 1 ? 0 : 2 * H0 - 3 - AL, HB1 = D >= 2 ? 2 * H1 - 3 - AL : 0,
+                         HB2 = D >= 3 ? 2 * H2 - 3 : 0;
+    static constexpr int G0 = D == 1 ? 2 * R0 : 2 * T0 + 5 + AL, G1 = D >= 2 ? 2 * T1 + 5 + AL : 1,
+                         G2 = D >= 3 ? 2 * T2 + 5 : 1;
     static constexpr int NCELL = R0 * R1 * R2;
     static constexpr int NHG = G0 * G1 * G2;
     static constexpr int NTILE = T0 * T1 * T2;
@@ -234,25 +257,36 @@ struct Geo {
     static constexpr int cell_off(int l) { return l == 0 ? 0 : (l == 1 ? ncl(0) : ncl(0) + ncl(1)); }
     static constexpr int NFACE = nface(0) + nface(1) + nface(2);
     static constexpr int NCL = ncl(0) + ncl(1) + ncl(2);
-    // SI boxes: s on [h-1, h+t+1)^D, s~ of direction l on [h-2,h+t+2) along l
-    static constexpr int sb(int l) { return l < D ? t(l) + 2 : 1; }
-    static constexpr int NSB = sb(0) * sb(1) * sb(2);
-    static constexpr int NST = (sb(0) + 2) * sb(1) * sb(2) + (D >= 2 ? sb(0) * (sb(1) + 2) * sb(2) : 0) +
-                               (D >= 3 ? sb(0) * sb(1) * (sb(2) + 2) : 0);
-    static constexpr int st_off(int l)
-    {
-        return l == 0 ? 0 : (l == 1 ? (sb(0) + 2) * sb(1) * sb(2) : (sb(0) + 2) * sb(1) * sb(2) + sb(0) * (sb(1) + 2) * sb(2));
-    }
+    // SI boxes of direction l: s_l on [h-1, h+t+1) along l, s~_l on
+    // [h-2, h+t+2) along l, both on [h, h+t+1) across (the cells that the
+    // tile's points, faces and potentials blend with)
+    static constexpr int sbe(int l, int a) { return a >= D ? 1 : (a == l ? t(a) + 2 : t(a) + 1); }
+    static constexpr int ste(int l, int a) { return a >= D ? 1 : (a == l ? t(a) + 4 : t(a) + 1); }
+    static constexpr int nsb(int l) { return l < D ? sbe(l, 0) * sbe(l, 1) * sbe(l, 2) : 0; }
+    static constexpr int nst(int l) { return l < D ? ste(l, 0) * ste(l, 1) * ste(l, 2) : 0; }
+    static constexpr int sb_off(int l) { return l == 0 ? 0 : (l == 1 ? nsb(0) : nsb(0) + nsb(1)); }
+    static constexpr int st_off(int l) { return l == 0 ? 0 : (l == 1 ? nst(0) : nst(0) + nst(1)); }
+    static constexpr int NSB = nsb(0) + nsb(1) + nsb(2);
+    static constexpr int NST = nst(0) + nst(1) + nst(2);
     __device__ static __forceinline__ int cidx(int x, int y, int z) { return x + R0 * (y + R1 * z); }
     // half-grid point (x, y, z) in region half indices
     __device__ static __forceinline__ int hidx(int x, int y, int z)
     {
-        return (x - 2 * HO) + G0 * ((D >= 2 ? y - 2 * HO : y) + G1 * (D >= 3 ? z - 2 * HO : z));
+        return (x - HB0) + G0 * ((y - HB1) + G1 * (z - HB2));
     }
-    // the cell's half-grid points are stored
-    __device__ static __forceinline__ bool in_hg(int x, int y, int z)
+    // some half-grid point of region cell (x, y, z) is held
+    __device__ static __forceinline__ bool cell_held(int x, int y, int z)
     {
-        return x >= HO && x < R0 - HO && (D < 2 || (y >= HO && y < R1 - HO)) && (D < 3 || (z >= HO && z < R2 - HO));
+        if (D == 1) return true;
+        return (unsigned)(x - (H0 - 2)) <= (unsigned)T0 + 2 && (D < 2 || (unsigned)(y - (H1 - 2)) <= (unsigned)T1 + 2) &&
+               (D < 3 || (unsigned)(z - (H2 - 2)) <= (unsigned)T2 + 2);
+    }
+    // the half-grid point (x, y, z) is held
+    __device__ static __forceinline__ bool held(int x, int y, int z)
+    {
+        if (D == 1) return true;
+        return (unsigned)(x - HB0) < (unsigned)G0 && (D < 2 || (unsigned)(y - HB1) < (unsigned)G1) &&
+               (D < 3 || (unsigned)(z - HB2) < (unsigned)G2);
     }
 };
 
@@ -374,6 +408,23 @@ __device__ __forceinline__ void atomic_max_wave_t(unsigned long long *dst, T v)
     }
 }
 
+// a(u) is staged per half-grid point (more LDS, fewer evaluations)
+template <int D>
+constexpr bool stage_staged_a()
+{
+    return true;
+}
+
+// elements of the shared face arrays (fluxes, and u^{L,+-} when limiting) or
+// of the raw smoothness indicators, whichever is larger
+template <int D, bool LIM, bool SI, int TX, int TY, int TZ>
+constexpr int stage_face_area()
+{
+    using G = Geo<D, TX, TY, TZ, SI ? 3 : 2>;
+    const int f = G::NFACE * (LIM ? 3 : 1), st = SI ? G::NST : 0;
+    return f > st ? f : st;
+}
+
 // QF: every flux is c1 u + c2 u^2 (evaluated in closed form, no branches on
 // the flux kind)
 template <int D, class T, bool LIM, bool SI, bool QF, int TX, int TY, int TZ, int NT>
@@ -385,12 +436,17 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
 
     __shared__ T ub[G::NCELL];
     __shared__ T hg[G::NHG];
-    __shared__ T fl[G::NFACE];                 // flux used in the update, per face
-    __shared__ T ulp[LIM ? G::NFACE : 1];      // u^{L,+} of the left cell of a face
-    __shared__ T ulm[LIM ? G::NFACE : 1];      // u^{L,-} of the right cell of a face
+    constexpr bool PA = stage_staged_a<D>();
+    __shared__ T ah[PA ? G::NHG : 1];          // a(u) at the half-grid points
+    // face arrays of phases D1-D3; the raw indicators s~_l of phase B' share
+    // their storage (they are consumed before phase C)
+    __shared__ T fla[stage_face_area<D, LIM, SI, TX, TY, TZ>()];
+    T *const fl = fla;                         // flux used in the update, per face
+    T *const ulp = fla + G::NFACE;             // u^{L,+} of the left cell of a face
+    T *const ulm = fla + 2 * G::NFACE;         // u^{L,-} of the right cell of a face
+    T *const stl = fla;                        // raw indicator s~_l
     __shared__ T pc[G::NCL];                   // potential used in the update, per cell
-    __shared__ T ssm[SI ? D * G::NSB : 1];     // smoothed indicator s_l
-    __shared__ T stl[SI ? G::NST : 1];         // raw indicator s~_l
+    __shared__ T ssm[SI ? G::NSB : 1];         // smoothed indicator s_l
 
     // block -> (instance, tile); consecutive logical tiles on the same XCD
     const int nb = (int)gridDim.x, b = (int)blockIdx.x;
@@ -410,6 +466,9 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
     const double dtd = p.st[wk.x].dt;
     // the 1D variant without double conservation (App. A)
     const bool nodc = D == 1 && I.nodc != 0;
+    // PA: a(u) at the half-grid points is evaluated once, where the point is
+    // staged (App. A's form uses kappa instead)
+    const bool pa = PA && !nodc;
     // Non-periodic ends (1D, 2D): a half-grid point on or beyond an open end
     // (global half indices q0, q1) takes a boundary value -- the Dirichlet
     // value of the first Dirichlet end among those it lies on or beyond, else
@@ -464,6 +523,11 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
 
     Phys<T> P;
     P.load(I, D);
+    // a(u) at half-grid point h holding u
+    auto a_at = [&](int h, T u) -> T {
+        if constexpr (PA) return ah[h];
+        else return P.a(u);
+    };
     T qc1[3], qc2[3];  // QF: f_l = qc1 u + qc2 u^2
 #pragma unroll
     for (int l = 0; l < 3; l++) {
@@ -501,11 +565,17 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
             const long long gi = wrap_index(c0, n0) + (long long)n0 * (D >= 2 ? wrap_index(c1, n1) : 0);
 #pragma unroll
             for (int zk = 0; zk < NB; zk++) {
+                const int hx = 2 * x + (zk & 1), hy = 2 * y + ((zk >> 1) & 1);
+                if (zk != 0 && !G::held(hx, hy, 0)) continue;
                 const int q0 = 2 * c0 + (zk & 1), q1 = 2 * c1 + ((zk >> 1) & 1);
                 const int m = ends(q0, q1);
                 const T v = m ? bc_point(q0, q1, m) : in[zk * kst + gi];
-                if (zk == 0) ub[G::cidx(x, y, 0)] = v;
-                else if (G::in_hg(x, y, 0)) hg[G::hidx(2 * x + (zk & 1), 2 * y + ((zk >> 1) & 1), 0)] = v;
+                if (zk == 0) {
+                    ub[G::cidx(x, y, 0)] = v;
+                } else {
+                    hg[G::hidx(hx, hy, 0)] = v;
+                    if (pa) ah[G::hidx(hx, hy, 0)] = P.a(v);
+                }
             }
             return;
         }
@@ -514,11 +584,18 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
         int gz = D >= 3 ? wrap_index(oz + z - G::H2, n2) : 0;
         long long gi = gx + (long long)n0 * (gy + (long long)n1 * gz);
         ub[G::cidx(x, y, z)] = in[gi];
-        if (!G::in_hg(x, y, z)) return;
+        if (!G::cell_held(x, y, z)) return;
+        // all loads of the cell first (one wait), then the held points
+        T v[NB];
+#pragma unroll
+        for (int zk = 1; zk < NB; zk++) v[zk] = in[zk * kst + gi];
 #pragma unroll
         for (int zk = 1; zk < NB; zk++) {
             const int m = zeta_mask<D>(zk);
-            hg[G::hidx(2 * x + (m & 1), 2 * y + ((m >> 1) & 1), 2 * z + ((m >> 2) & 1))] = in[zk * kst + gi];
+            const int hx = 2 * x + (m & 1), hy = 2 * y + ((m >> 1) & 1), hz = 2 * z + ((m >> 2) & 1);
+            if (!G::held(hx, hy, hz)) continue;
+            hg[G::hidx(hx, hy, hz)] = v[zk];
+            if (pa) ah[G::hidx(hx, hy, hz)] = P.a(v[zk]);
         }
     });
     __syncthreads();
@@ -535,7 +612,9 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                 const int q0 = 2 * (ox + x - G::H0), q1 = D >= 2 ? 2 * (oy + y - G::H1) : 0;
                 const int m = ends(q0, q1);
                 if (m) {  // ghost centre
-                    hg[G::hidx(2 * x, 2 * y, 0)] = bc_point(q0, q1, m);
+                    const T v = bc_point(q0, q1, m);
+                    hg[G::hidx(2 * x, 2 * y, 0)] = v;
+                    if (pa) ah[G::hidx(2 * x, 2 * y, 0)] = P.a(v);
                     return;
                 }
             }
@@ -550,7 +629,9 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                         const T w = T((oxx == 0 ? 4 : 1) * (D >= 2 && oy == 0 ? 4 : 1) * (D >= 3 && oz == 0 ? 4 : 1));
                         acc -= w * hg[G::hidx(2 * x + oxx, 2 * y + oy, 2 * z + oz)];
                     }
-            hg[G::hidx(2 * x, 2 * y, 2 * z)] = acc * iW;
+            const T v = acc * iW;
+            hg[G::hidx(2 * x, 2 * y, 2 * z)] = v;
+            if (pa) ah[G::hidx(2 * x, 2 * y, 2 * z)] = P.a(v);
         });
     }
 
@@ -558,12 +639,10 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
     if constexpr (SI) {
 #pragma unroll
         for (int l = 0; l < D; l++) {
-            // s~_l on the box extended by one more cell along l
-            const int e0 = G::sb(0) + (l == 0 ? 2 : 0), e1 = G::sb(1) + (l == 1 ? 2 : 0);
-            const int ne = e0 * e1 * (G::sb(2) + (l == 2 ? 2 : 0));
+            const int e0 = G::ste(l, 0), e1 = G::ste(l, 1), ne = G::nst(l);
             for (int id = (int)threadIdx.x; id < ne; id += NT) {
                 int i = id % e0, r = id / e0, j = r % e1, k = r / e1;
-                int x = i + G::H0 - 1 - (l == 0), y = j + (D >= 2 ? G::H1 - 1 : 0) - (l == 1), z = k + (D >= 3 ? G::H2 - 1 : 0) - (l == 2);
+                int x = i + G::H0 - 2 * (l == 0), y = j + G::H1 - 2 * (l == 1), z = k + G::H2 - 2 * (l == 2);
                 const int sx = l == 0, sy = l == 1, sz = l == 2;
                 T um = ub[G::cidx(x - sx, y - sy, z - sz)], u0 = ub[G::cidx(x, y, z)], up = ub[G::cidx(x + sx, y + sy, z + sz)];
                 stl[G::st_off(l) + id] = fabs(um - T(2) * u0 + up) / (fabs(um) + T(2) * fabs(u0) + fabs(up) + T(1e-13));
@@ -572,21 +651,23 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
         __syncthreads();
 #pragma unroll
         for (int l = 0; l < D; l++) {
-            const int e0 = G::sb(0) + (l == 0 ? 2 : 0), e1 = G::sb(1) + (l == 1 ? 2 : 0);
-            box_loop<G::sb(0), G::sb(1), G::sb(2), NT>([&](int i, int j, int k) {
+            const int e0 = G::ste(l, 0), e1 = G::ste(l, 1);
+            const int b0 = G::sbe(l, 0), b1 = G::sbe(l, 1), nb = G::nsb(l);
+            for (int id = (int)threadIdx.x; id < nb; id += NT) {
+                const int i = id % b0, r = id / b0, j = r % b1, k = r / b1;
                 const int si = i + (l == 0), sj = j + (l == 1), sk = k + (l == 2);
                 const int st = l == 0 ? 1 : (l == 1 ? e0 : e0 * e1);
                 const int c = G::st_off(l) + si + e0 * (sj + e1 * sk);
-                ssm[l * G::NSB + i + G::sb(0) * (j + G::sb(1) * k)] = (stl[c - st] + T(4) * stl[c] + stl[c + st]) * T(1.0 / 6.0);
-            });
+                ssm[G::sb_off(l) + id] = (stl[c - st] + T(4) * stl[c] + stl[c + st]) * T(1.0 / 6.0);
+            }
         }
     }
     __syncthreads();
 
-    // s_l at region cell (x, y, z) (inside the s box)
+    // s_l at region cell (x, y, z) (inside the s box of direction l)
     auto s_at = [&](int l, int x, int y, int z) -> T {
-        return ssm[l * G::NSB + (x - (G::H0 - 1)) +
-                   G::sb(0) * ((D >= 2 ? y - (G::H1 - 1) : 0) + G::sb(1) * (D >= 3 ? z - (G::H2 - 1) : 0))];
+        return ssm[G::sb_off(l) + (x - (G::H0 - (l == 0))) +
+                   G::sbe(l, 0) * ((y - (G::H1 - (l == 1))) + G::sbe(l, 1) * (z - (G::H2 - (l == 2))))];
     };
     const T gam = (T)I.si_gamma;
 
@@ -607,13 +688,12 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
 #pragma unroll
             for (int l = 0; l < D; l++) {
                 const int sx = l == 0, sy = l == 1, sz = l == 2;
-                T zz[5], ff[5], aa[5];
+                T zz[5], ff[5];
                 T alpha = T(0);
 #pragma unroll
                 for (int s = -2; s <= 2; s++) {
                     zz[s + 2] = hg[G::hidx(px + s * sx, py + s * sy, pz + s * sz)];
                     ff[s + 2] = Ff(l, zz[s + 2]);
-                    aa[s + 2] = P.a(zz[s + 2]);
                     alpha = fmax(alpha, Fg(l, zz[s + 2]));
                 }
                 T conv = -((ff[0] - T(8) * ff[1] + T(8) * ff[3] - ff[4]) +
@@ -643,7 +723,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                                     ssum += s_at(l, x + dxx, y + dy, z + dz);
                                     cnt++;
                                 }
-                        const T th = exp(-gam * ssum / T(cnt));
+                        const T th = blend_exp(-gam * ssum / T(cnt));
                         conv = th * conv + (T(1) - th) * convL;
                     }
                 }
@@ -660,6 +740,9 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                          (((P.kappa(zz[0]) * b0 + P.kappa(zz[1]) * b1) + P.kappa(zz[2]) * b2) +
                           (P.kappa(zz[3]) * b3 + P.kappa(zz[4]) * b4));
                 } else {
+                    T aa[5];
+#pragma unroll
+                    for (int s = -2; s <= 2; s++) aa[s + 2] = a_at(G::hidx(px + s * sx, py + s * sy, pz + s * sz), zz[s + 2]);
                     d2 = (-(aa[0] + aa[4]) * T(1.0 / 3.0) + (aa[1] + aa[3]) * T(16.0 / 3.0) - T(10) * aa[2]) * idx2[l];
                 }
                 R += conv + d2;
@@ -740,7 +823,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                 fH *= D == 1 ? T(1) : (D == 2 ? T(1.0 / 6.0) : T(1.0 / 36.0));
             }
             if (use_si) {
-                const T th = exp(-gam * T(0.5) * (s_at(l, x, y, z) + s_at(l, x + sx, y + sy, z + sz)));
+                const T th = blend_exp(-gam * T(0.5) * (s_at(l, x, y, z) + s_at(l, x + sx, y + sy, z + sz)));
                 fH = th * fH + (T(1) - th) * fL;
             }
             if (nodc) {
@@ -793,12 +876,13 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                         if (l != 0) w *= oxx == 0 ? T(4) : T(1);
                         if (l != 1 && D >= 2) w *= oy == 0 ? T(4) : T(1);
                         if (l != 2 && D >= 3) w *= oz == 0 ? T(4) : T(1);
-                        aH += w * P.a(hg[G::hidx(2 * x + oxx, 2 * y + oy, 2 * z + oz)]);
+                        const int h = G::hidx(2 * x + oxx, 2 * y + oy, 2 * z + oz);
+                        aH += w * a_at(h, PA ? T(0) : hg[h]);
                     }
             aH *= D == 1 ? T(1.0 / 6.0) : (D == 2 ? T(1.0 / 36.0) : T(1.0 / 216.0));
             const T aL = P.a(ub[G::cidx(x, y, z)]);
             if (use_si) {
-                const T th = exp(-gam * s_at(l, x, y, z));
+                const T th = blend_exp(-gam * s_at(l, x, y, z));
                 aH = th * aH + (T(1) - th) * aL;
             }
             T Pv = aH;
@@ -880,7 +964,8 @@ template <int D, class T, bool LIM, bool SI, int TX, int TY, int TZ>
 constexpr long stage_lds_bytes()
 {
     using G = Geo<D, TX, TY, TZ, SI ? 3 : 2>;
-    return (long)sizeof(T) * (G::NCELL + G::NHG + G::NFACE * (LIM ? 3 : 1) + G::NCL + (SI ? D * G::NSB + G::NST : 2));
+    return (long)sizeof(T) *
+           (G::NCELL + (stage_staged_a<D>() ? 2 : 1) * G::NHG + stage_face_area<D, LIM, SI, TX, TY, TZ>() + G::NCL + (SI ? G::NSB : 1));
 }
 
 }  // namespace af4
