@@ -3,7 +3,8 @@
  *
  * A plain, slow, FP64 CPU implementation of the compact fourth-order doubly
  * conservative active flux (AF) method with monolithic convex limiting for
- * u_t + div f(u) = Lap a(u) on periodic Cartesian meshes
+ * u_t + div f(u) = Lap a(u) on Cartesian meshes (periodic ends; Dirichlet or
+ * outflow ends in 1D and 2D by the ghost rule of ends_of / bc_point)
  * (J. Duan, "A compact fourth-order doubly conservative active flux method
  * with maximum-principle-preserving limiting for degenerate
  * convection-diffusion equations", arXiv 2510.11527).
@@ -22,6 +23,12 @@
  * double conservation: kappa(u) D_c(u) face fluxes in the average, the
  * compact B-matrix operator in the point value; its limiting is a reading
  * (see F_nodc_lim).
+ *
+ * Smoothness-indicator blending (Sec. 5.1.3) of the point values defers its
+ * low-order scheme to other work; the one here is a reading (LLF on the
+ * half grid, a cell average for a cell centre).  Its gamma -> inf limit and
+ * its 1D weight are pinned by the tests; the multi-D point weights at finite
+ * gamma > 0 (means of s over 2 to 8 cells) are parity unpinned.
  *
  * Half-grid reading (used by the paper's "half-index shifts", Sec. 4): along
  * axis l, the points x_{i-1/2}, x_i, x_{i+1/2}, x_{i+1}, ... form a uniform

@@ -958,6 +958,145 @@ def test_si_blended_average_matches_printed_formulas(gamma):
     np.testing.assert_allclose(V[0], avg, rtol=0, atol=1e-14)
 
 
+def _halfgrid_from_simpson(d, n, U):
+    """The periodic half grid (index [py, px] in 2D) with every cell centre
+    recovered from the average by inverting the (tensor) Simpson rule of
+    Sec. 4, written out here independently of the oracle."""
+    if d == 1:
+        ub, up = U
+        H = np.empty(2 * n)
+        H[1::2] = up
+        H[0::2] = (6 * ub - np.roll(up, 1) - up) / 4
+        return H
+    H = np.empty((2 * n, 2 * n))
+    H[0::2, 1::2] = U[1].reshape(n, n)      # (i+1/2, j)
+    H[1::2, 0::2] = U[2].reshape(n, n)      # (i, j+1/2)
+    H[1::2, 1::2] = U[3].reshape(n, n)      # (i+1/2, j+1/2)
+    H[0::2, 0::2] = 0.0
+    w = {-1: 1.0, 0: 4.0, 1: 1.0}
+    acc = 36 * U[0].reshape(n, n)
+    for b in (-1, 0, 1):
+        for a in (-1, 0, 1):
+            if a or b:
+                acc = acc - w[a] * w[b] * np.roll(np.roll(H, -b, axis=0), -a, axis=1)[0::2, 0::2]
+    H[0::2, 0::2] = acc / 16
+    return H
+
+
+def _low_order_point_neighbours(d, n, U, H, py, px, l):
+    """The point (py, px) and its two neighbours dx_l/2 away along axis l, a
+    cell average standing in for a cell centre (reading R12)."""
+    def val(qy, qx):
+        qy, qx = qy % (2 * n), qx % (2 * n)
+        if qx % 2 == 0 and qy % 2 == 0:
+            return U[0][qx // 2 + (n * (qy // 2) if d == 2 else 0)]
+        return H[qx] if d == 1 else H[qy, qx]
+    e = (0, 1) if l == 0 else (1, 0)
+    return val(py - e[0], px - e[1]), val(py + e[0], px + e[1])
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_si_low_order_point_values_obey_the_maximum_principle(d):
+    """gamma -> inf on data with s > 0 everywhere leaves every point value
+    with its low-order LLF update (reading R12).  That update is monotone in
+    the point and its neighbours dx_l/2 away wherever the point's alpha along
+    every axis bounds |f'| over them and sum_l (2 dt / dx_l) alpha_l <= 1, so
+    there it must stay within their min and max.  Burgers flux on rough data,
+    up to 90% of the Courant limit; the point's alpha (max |f'| over its
+    5-point stencil, centres included) is recomputed here from an independent
+    Simpson inversion.  A central low-order flux, a flipped dissipation sign,
+    a reconstructed centre in place of the average or a missing factor 2
+    fails it."""
+    rng = np.random.default_rng(61 + d)
+    n = {1: 48, 2: 14}[d]
+    dx = 1.0 / n
+    checked = 0
+    for trial in range(6):
+        spec = dict(dim=d, n=[n] * d, lo=[0.0] * d, hi=[1.0] * d, flux=[("quad", 0.5, 0.0)] * d,
+                    diff=("linear", 0.0, 0.0), umin=-1.0, umax=1.0, limiter=False, si=True, si_gamma=1e7)
+        U = [rng.uniform(-1, 1, size=n ** d) for _ in range(2 ** d)]
+        lam = 2 * (0.45 / d) * (0.5 + 0.5 * trial / 5)    # 2 dt / dx_l, up to 0.9 / d per axis
+        V, _ = oracle.fe(oracle.problem(spec), U, lam * dx / 2)
+        H = _halfgrid_from_simpson(d, n, U)
+        for z, mx_, my_ in ([(1, 1, 0)] if d == 1 else [(1, 1, 0), (2, 0, 1), (3, 1, 1)]):
+            for j in range(n if d == 2 else 1):
+                for i in range(n):
+                    px, py = 2 * i + mx_, 2 * j + my_
+                    u = H[px] if d == 1 else H[py, px]
+                    vals, courant, ok = [u], 0.0, True
+                    for l in range(d):
+                        if l == 0:
+                            st = [H[(px + s) % (2 * n)] if d == 1 else H[py, (px + s) % (2 * n)] for s in range(-2, 3)]
+                        else:
+                            st = [H[(py + s) % (2 * n), px] for s in range(-2, 3)]
+                        alpha = max(abs(v) for v in st)
+                        nm, npl = _low_order_point_neighbours(d, n, U, H, py, px, l)
+                        ok &= alpha >= max(abs(u), abs(nm), abs(npl))
+                        courant += lam * alpha
+                        vals += [nm, npl]
+                    if not ok or courant > 1.0:
+                        continue
+                    v = V[z][i + n * j]
+                    assert min(vals) - 1e-14 <= v <= max(vals) + 1e-14, (d, z, i, j, v, min(vals), max(vals))
+                    checked += 1
+    assert checked > (0.5 if d == 1 else 0.3) * 6 * n ** d * (2 ** d - 1)
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_si_low_order_point_values_reduce_to_half_grid_upwind(d):
+    """For linear fluxes the low-order point-value update (gamma -> inf,
+    reading R12) is the first-order upwind scheme on the half grid of spacing
+    dx_l/2, the upwind neighbour being a cell average where it falls on a
+    cell centre: u - (2 dt / dx_l) |c_l| (u - u_upwind), summed over axes."""
+    rng = np.random.default_rng(71 + d)
+    n = {1: 20, 2: 8}[d]
+    c = [0.8, -0.6][:d]
+    spec = dict(dim=d, n=[n] * d, lo=[0.0] * d, hi=[1.0] * d, flux=[("linear", cl, 0.0) for cl in c],
+                diff=("linear", 0.0, 0.0), umin=-1.0, umax=1.0, limiter=False, si=True, si_gamma=1e7)
+    U = [rng.uniform(-1, 1, size=n ** d) for _ in range(2 ** d)]
+    dt = 0.1 / n
+    V, _ = oracle.fe(oracle.problem(spec), U, dt)
+    H = _halfgrid_from_simpson(d, n, U)
+    for z, mx_, my_ in ([(1, 1, 0)] if d == 1 else [(1, 1, 0), (2, 0, 1), (3, 1, 1)]):
+        for j in range(n if d == 2 else 1):
+            for i in range(n):
+                px, py = 2 * i + mx_, 2 * j + my_
+                u = H[px] if d == 1 else H[py, px]
+                want = u
+                for l in range(d):
+                    nm, npl = _low_order_point_neighbours(d, n, U, H, py, px, l)
+                    up = nm if c[l] > 0 else npl
+                    want -= 2 * dt * n * abs(c[l]) * (u - up)
+                assert abs(V[z][i + n * j] - want) < 1e-13, (d, z, i, j)
+
+
+@pytest.mark.parametrize("gamma", [0.7, 5.0])
+def test_si_1d_point_value_weight_is_the_printed_face_coefficient(gamma):
+    """In 1D the point value u_{i+1/2} sits on the face i+1/2, and its blend
+    of the high- and low-order convection (reading R12: the mean of s over
+    the cells whose closure contains the point) is the printed face
+    coefficient theta^{c,s}_{i+1/2} = exp(-gamma (s_i + s_{i+1})/2), s from
+    the printed s~ and (1,4,1)/6 smoothing.  The weight is recovered from the
+    updates at gamma = 0 (theta = 1), gamma and gamma -> inf (theta = 0) with
+    a = 0, where the point-value update is affine in theta."""
+    N, dx = 23, 1.0 / 23
+    rng = np.random.default_rng(91)
+    ub, up = rng.uniform(0.1, 1.0, N), rng.uniform(0.1, 1.0, N)
+    base = spec1d(N, 1.0, ("quad", 0.5, 0.0), ("linear", 0.0, 0.0), si=True)
+    dt = 0.05 * dx
+    V0 = oracle.fe(oracle.problem(dict(base, si_gamma=0.0)), [ub, up], dt)[0][1]
+    Vg = oracle.fe(oracle.problem(dict(base, si_gamma=gamma)), [ub, up], dt)[0][1]
+    Vi = oracle.fe(oracle.problem(dict(base, si_gamma=1e7)), [ub, up], dt)[0][1]
+    um, upp = np.roll(ub, 1), np.roll(ub, -1)
+    st = np.abs(um - 2 * ub + upp) / (np.abs(um) + 2 * np.abs(ub) + np.abs(upp) + 1e-13)
+    sm = (np.roll(st, 1) + 4 * st + np.roll(st, -1)) / 6
+    want = np.exp(-gamma * 0.5 * (sm + np.roll(sm, -1)))
+    span = V0 - Vi
+    use = np.abs(span) > 1e-6
+    assert use.sum() > N // 2
+    np.testing.assert_allclose((Vg - Vi)[use] / span[use], want[use], rtol=1e-7)
+
+
 # ---------------------------------------------------------------------------
 # Open ends in 2D (the rule is the 1D one applied along each axis; corners
 # and edges take the mean of the boundary cells around the clamped point)
