@@ -57,6 +57,21 @@ def test_invalid_problem_rejected_before_device_use():
     assert e.value.status == af.AF_ERR_UNSUPPORTED
 
 
+def test_empty_batch_rejected_before_device_use():
+    """A batch of no instances, or a missing problem array or handle, is an
+    argument error, returned before any device call."""
+    import ctypes
+    from paper_2510_11527_amd import af
+    from paper_2510_11527_amd import workloads as W
+    spec, _ = W.config2(n=8)
+    arr = (af.AfProblem * 1)(af.make_problem(spec, None, "ssprk3"))
+    h = ctypes.c_void_p()
+    assert af.lib().af_create(0, arr, ctypes.byref(h)) == af.AF_ERR_ARG
+    assert af.lib().af_create(1, None, ctypes.byref(h)) == af.AF_ERR_ARG
+    assert af.lib().af_create(1, arr, None) == af.AF_ERR_ARG
+    assert not h.value
+
+
 def test_package_has_no_oracle_dependency():
     """The product path never imports or loads the oracle."""
     pkg = os.path.join(ROOT, "paper_2510_11527_amd")

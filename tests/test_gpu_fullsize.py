@@ -126,3 +126,74 @@ def test_full_size_step_conserves_mass_and_bounds(wl):
         assert nrm["min_pv"] >= s["umin"] and nrm["max_pv"] <= s["umax"], i
         assert nrm["max_clamp"] <= 4 * eps * max(abs(s["umin"]), abs(s["umax"]), 1.0), (i, nrm["max_clamp"])
     ctx.close()
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_minimum_grid_matches_oracle(d):
+    """Four cells per axis, the smallest grid accepted: every halo (three cells
+    with the smoothness indicators) wraps around the periodic instance, in a
+    batch next to a larger instance.  One limited, blended FE stage in FP64
+    and FP32 against the oracle over all DoFs."""
+    rng = np.random.default_rng(400 + d)
+    for prec in (64, 32):
+        items = []
+        for n in (4, 11):
+            spec = dict(name="min", dim=d, n=[n] * d, lo=[0.0] * d, hi=[1.0] * d, flux=[("quad", 0.5, 0.0)] * d,
+                        diff=("power", 0.05, 2.0), umin=0.0, umax=1.0, limiter=True, si=True, si_gamma=1.0,
+                        precision=prec, cfl=0.05)
+            U = [rng.uniform(0, 1, size=n ** d) for _ in range(2 ** d)]
+            if prec == 32:
+                U = [u.astype(np.float32).astype(np.float64) for u in U]
+            items.append((spec, U))
+        ctx = bench.make_ctx(items, integrator="euler")
+        note("minimum grid d=%d prec=%d variant %s" % (d, prec, ctx.variant_name(ctx.variant())))
+        dts = ctx.step(1)
+        for i, (s, U) in enumerate(items):
+            V, _ = ctx.get_state(i)
+            Vo, _ = oracle.fe(oracle.problem(s), U, dts[i])
+            for z in range(2 ** d):
+                err = np.abs(V[z] - Vo[z]).sum() / np.abs(Vo[z]).sum()
+                assert err <= TOL[prec], (i, z, err)
+            assert min(v.min() for v in V) >= 0.0 and max(v.max() for v in V) <= 1.0
+        ctx.close()
+
+
+def test_instance_beyond_2_pow_31_dofs_matches_oracle():
+    """One 2D FP64 instance of 23200^2 cells: its DoF block holds more than
+    2^31 values (17 GB), past every 32-bit offset.  The own-items kernel,
+    which addresses a block with 32-bit byte offsets, is not selected; the
+    default (table) kernel and the generic kernel, both with 64-bit offsets,
+    each run one limited FE stage that matches the oracle on sampled cells,
+    among them the last cells, whose offsets exceed 2^31."""
+    n = 23200
+    ncell = n * n
+    assert 4 * ncell > 2 ** 31
+    rng = np.random.default_rng(2311)
+    spec = dict(name="big", dim=2, n=[n, n], lo=[0.0, 0.0], hi=[1.0, 1.0], flux=[("quad", 0.5, 0.0)] * 2,
+                diff=("power", 0.05, 2.0), umin=0.0, umax=1.0, limiter=True, si=False, si_gamma=1.0,
+                precision=64, cfl=0.075)
+    U = [rng.random(ncell) for _ in range(4)]
+    ctx = bench.make_ctx([(spec, U)], integrator="euler")
+    names = [ctx.variant_name(v) for v in range(ctx.num_variants())]
+    generic = next(v for v, nm in enumerate(names) if nm.startswith("generic"))
+    dt = None
+    for v in (ctx.variant(), generic):
+        ctx.set_variant(v)
+        ctx.set_state(0, U)
+        note("instance of %d cells, variant %s" % (ncell, names[v]))
+        assert "own" not in names[v]
+        if dt is None:
+            dt = ctx.step(1)[0]
+        else:
+            ctx.step(1, dt=dt)
+        V, _ = ctx.get_state(0)
+        cells = sample_cells(spec, U, tile_of(names[v], 2), rng, 64)
+        cells = np.unique(np.concatenate([cells, np.arange(ncell - 40, ncell), ncell - n + np.arange(40)]))
+        Vo, _ = oracle.fe_cells(oracle.problem(spec), U, dt, cells)
+        G = np.stack([V[z][cells] for z in range(4)], axis=1)
+        del V
+        err = float(np.max(np.abs(G - Vo).sum(axis=0) / np.abs(Vo).sum(axis=0)))
+        note("  %d sampled cells, relative l1 %.3e" % (cells.size, err))
+        assert err <= TOL[64], err
+        assert G.min() >= 0.0 and G.max() <= 1.0
+    ctx.close()
