@@ -152,7 +152,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c4")
-    ap.add_argument("--variant", type=int, default=None)
+    ap.add_argument("--variant", type=int, default=None, help="tile variant (default: autotuned)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile variant")
+    ap.add_argument("--autotune-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
@@ -174,10 +176,17 @@ def main():
     prec = items[0][0]["precision"]
     ctx = make_ctx(items, variant=args.variant, integrator=args.integrator)
     work = ctx.work()
-    variant_name = ctx.variant_name(ctx.variant())
     if args.warmup > 0:
         ctx.step(args.warmup)
     log("warmup done")
+    tuned = None
+    if args.variant is None and not args.no_autotune:
+        # untimed: every built tile variant on the warmed-up state, which the
+        # tuner restores afterwards
+        chosen, ms = ctx.autotune(args.autotune_steps)
+        tuned = {ctx.variant_name(v): round(float(m), 5) for v, m in enumerate(ms) if m > 0}
+        log("autotune: %s (stage ms %s)" % (ctx.variant_name(chosen), tuned))
+    variant_name = ctx.variant_name(ctx.variant())
     # timed region: K steps in one graph launch; inputs already in HBM
     ctx.step(1)
     ctx.step(args.steps)  # builds the graph for K steps (and runs them)
@@ -210,11 +219,14 @@ def main():
             "config": {"workload": wname, "instances": len(items), "cells": work["cells"], "dofs": work["dofs"],
                        "integrator": args.integrator, "limiter": bool(items[0][0]["limiter"]),
                        "si": bool(items[0][0]["si"]), "cfl": items[0][0]["cfl"], "tile": variant_name,
+                       "tile_choice": "autotuned" if tuned else ("given" if args.variant is not None else "default"),
                        "graph": "one hipGraph launch of %d steps" % args.steps},
             "cell_updates_per_s": work["cells"] * stages / el,
             "step_hbm_frac": work["bytes_per_stage"] * stages / el / 1e9 / HBM_PEAK_GBS}
     if roof:
         line["roofline"] = roof
+    if tuned:
+        line["autotune_stage_ms"] = tuned
     if not args.no_fp64_plain and prec == 32:
         try:
             line["fp64_plain"] = fp64_plain(items, max(10, args.steps // 10), 4_000_000, args.integrator)

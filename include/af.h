@@ -202,6 +202,24 @@ const char *af_variant_name(const af_ctx *ctx, int variant);
 af_status af_step_timed(af_ctx *ctx, int nsteps, double t_end, const double *dt_prescribed, double *mean_stage_ms,
                         int *launches);
 
+/* Tile autotuner: times every tile variant built for the context's
+ * dimension, precision and flags on the current state of all instances and
+ * selects the fastest by mean stage-kernel duration.  After one untimed pass
+ * of nsteps steps, every variant runs one warm-up step and nsteps (>= 1) CFL
+ * steps timed as af_step_timed, in two passes (index order, then reverse),
+ * and keeps its faster figure; then, in index order, a variant replaces the
+ * selection only when more than 3% faster, so that timing noise does not
+ * move the choice.  The state, time, step count
+ * and flags of every instance are restored after each variant, so the call
+ * leaves the solution where it was; cached graphs are dropped.  Needs
+ * af_set_state for every instance (AF_ERR_STATE); allocates one temporary
+ * device copy of the state (AF_ERR_ALLOC if that fails), released before
+ * returning.  On success *chosen (if not NULL) holds the selected variant
+ * and ms_per_stage (if not NULL, af_num_variants entries) the measured mean
+ * stage time of every variant, -1 for those not built.  On an error the
+ * variant selected before the call is restored. */
+af_status af_autotune(af_ctx *ctx, int nsteps, int *chosen, double *ms_per_stage);
+
 /* Algorithmic HBM bytes of one stage launch over all instances, averaged over
  * the stages of one step: (2 + 1 for stages that read U^n) * 2^d * cells *
  * value size.  Grid cells and DoFs of the context in *cells, *dofs. */

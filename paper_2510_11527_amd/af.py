@@ -25,7 +25,7 @@ INTEGRATORS = {"ssprk3": 0, "euler": 1, "ssprk54": 2}
 
 EXPORTS = ["af_create", "af_destroy", "af_set_state", "af_get_state", "af_step", "af_residual", "af_norms",
            "af_last_error", "af_set_stream", "af_set_variant", "af_num_variants", "af_variant_name",
-           "af_step_timed", "af_work", "af_get_variant"]
+           "af_step_timed", "af_work", "af_get_variant", "af_autotune"]
 
 
 class AfProblem(ctypes.Structure):
@@ -93,6 +93,7 @@ def lib():
         L.af_variant_name.argtypes = [vp, ctypes.c_int]
         L.af_variant_name.restype = ctypes.c_char_p
         L.af_work.argtypes = [vp, dp, dp, dp]
+        L.af_autotune.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
         for name in EXPORTS:
             if name not in ("af_last_error", "af_num_variants", "af_variant_name", "af_get_variant"):
                 getattr(L, name).restype = ctypes.c_int
@@ -245,6 +246,16 @@ class Context:
 
     def variant(self):
         return lib().af_get_variant(self.h)
+
+    def autotune(self, nsteps=5):
+        """Select the fastest tile variant on the current state (af_autotune);
+        returns the chosen index and the mean stage time per variant (ms, -1
+        for variants not built)."""
+        ms = np.empty(self.num_variants())
+        chosen = ctypes.c_int()
+        self._check(lib().af_autotune(self.h, int(nsteps), ctypes.byref(chosen),
+                                      ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return chosen.value, ms
 
     def work(self):
         b, c, d = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -860,6 +860,84 @@ af_status af_step_timed(af_ctx *c, int nsteps, double t_end, const double *dt_pr
     return s;
 }
 
+af_status af_autotune(af_ctx *c, int nsteps, int *chosen, double *ms_per_stage)
+{
+    if (!c || nsteps < 1) return fail(c, AF_ERR_ARG, "af_autotune: bad arguments");
+    af_status s = check_ready(c);
+    if (s != AF_OK) return s;
+    const int nv = af4::stage_num_variants(c->dim);
+    if (ms_per_stage)
+        for (int v = 0; v < nv; v++) ms_per_stage[v] = -1.0;
+    // the state (buffer A) and the per-instance scalars, restored after
+    // every variant
+    const size_t bytes = (size_t)c->total * vbytes(c);
+    void *backup = nullptr;
+    if (hipMalloc(&backup, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, AF_ERR_ALLOC, "af_autotune: no device memory for the state copy");
+    }
+    std::vector<InstState> st(c->n_inst);
+    hipError_t e = hipMemcpyAsync(backup, c->buf[0], bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(st.data(), c->d_st, sizeof(InstState) * c->n_inst, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    auto restore = [&]() -> hipError_t {
+        hipError_t r = hipMemcpyAsync(c->buf[0], backup, bytes, hipMemcpyDeviceToDevice, c->stream);
+        if (r == hipSuccess)
+            r = hipMemcpyAsync(c->d_st, st.data(), sizeof(InstState) * c->n_inst, hipMemcpyHostToDevice, c->stream);
+        if (r == hipSuccess) r = hipStreamSynchronize(c->stream);
+        c->keys_fresh = false;  // the restored state's min / max are not reduced
+        return r;
+    };
+    const int v0 = c->variant;
+    if (e != hipSuccess) s = fail(c, AF_ERR_DEVICE, std::string("af_autotune: ") + hipGetErrorString(e));
+    // one untimed pass first, so that the variant timed first does not pay
+    // for clocks and caches still settling
+    if (s == AF_OK) {
+        double ms = 0.0;
+        int launches = 0;
+        s = af_step_timed(c, nsteps, 0.0, nullptr, &ms, &launches);
+        if (s == AF_OK && (e = restore()) != hipSuccess)
+            s = fail(c, AF_ERR_DEVICE, std::string("af_autotune: ") + hipGetErrorString(e));
+    }
+    // two timed passes, in index order and back, keeping each variant's
+    // faster figure: neither a variant's position in the order nor one slow
+    // measurement decides the choice
+    std::vector<double> t(nv, -1.0);
+    for (int pass = 0; pass < 2 && s == AF_OK; pass++)
+        for (int k = 0; k < nv && s == AF_OK; k++) {
+            const int v = pass == 0 ? k : nv - 1 - k;
+            if (!af4::stage_supported(c->dim, c->prec, c->lim, c->si, c->caps, v)) continue;
+            double ms = 0.0;
+            int launches = 0;
+            if ((s = af_set_variant(c, v)) != AF_OK) break;
+            if ((s = af_step_timed(c, 1, 0.0, nullptr, &ms, &launches)) != AF_OK) break;
+            if ((s = af_step_timed(c, nsteps, 0.0, nullptr, &ms, &launches)) != AF_OK) break;
+            if ((e = restore()) != hipSuccess) {
+                s = fail(c, AF_ERR_DEVICE, std::string("af_autotune: ") + hipGetErrorString(e));
+                break;
+            }
+            t[v] = t[v] < 0 ? ms : std::min(t[v], ms);
+        }
+    int best = -1;
+    for (int v = 0; v < nv && s == AF_OK; v++) {
+        if (t[v] < 0) continue;
+        if (ms_per_stage) ms_per_stage[v] = t[v];
+        if (best < 0 || t[v] < 0.97 * t[best]) best = v;
+    }
+    if (s == AF_OK) {
+        s = af_set_variant(c, best);
+    } else {
+        const std::string msg = c->err;
+        (void)af_set_variant(c, v0);
+        (void)restore();
+        c->err = msg;
+    }
+    (void)hipFree(backup);
+    if (s == AF_OK && chosen) *chosen = best;
+    return s;
+}
+
 af_status af_residual(af_ctx *c, int inst, double *const *rhs)
 {
     if (!c || inst < 0 || inst >= c->n_inst || !rhs) return fail(c, AF_ERR_ARG, "af_residual: bad arguments");

@@ -263,6 +263,47 @@ def test_tile_variants_agree(d, fl):
     ctx.close()
 
 
+@pytest.mark.parametrize("case", ["c4", "c5"])
+def test_autotune_selects_a_built_variant_and_leaves_the_solution(case):
+    """af_autotune times every built tile variant, keeps one within 3% of
+    the fastest, and restores state, time and norms bit for bit; stepping on
+    afterwards equals a fresh context on the chosen variant."""
+    items = W.config4(n_inst=5, sizes=(40, 72)) if case == "c4" else [W.config5(n=14)]
+    specs = [s for s, _ in items]
+    ctx = af.Context(specs)
+    with pytest.raises(af.AFError) as e:
+        ctx.autotune(1)
+    assert e.value.status == af.AF_ERR_STATE
+    for i, (_, U) in enumerate(items):
+        ctx.set_state(i, U)
+    ctx.step(2)
+    before = [ctx.get_state(i) for i in range(len(items))]
+    nb = [ctx.norms(i) for i in range(len(items))]
+    chosen, ms = ctx.autotune(2)
+    built = [m for m in ms if m > 0]
+    note("autotune %s: chosen %s, ms %s" % (case, ctx.variant_name(chosen), np.round(ms, 4)))
+    assert ctx.variant() == chosen and ms[chosen] > 0 and len(built) >= 2
+    assert min(built) >= 0.97 * ms[chosen] * (1 - 1e-12)
+    for i in range(len(items)):
+        V, t = ctx.get_state(i)
+        assert t == before[i][1]
+        for a, b in zip(V, before[i][0]):
+            assert np.array_equal(a, b)
+        assert ctx.norms(i) == nb[i]
+    d1 = ctx.step(2)
+    ref = af.Context(specs)
+    ref.set_variant(chosen)
+    for i, (V, t) in enumerate(before):
+        ref.set_state(i, V, t)
+    d2 = ref.step(2)
+    assert np.array_equal(d1, d2)
+    for i in range(len(items)):
+        for a, b in zip(ctx.get_state(i)[0], ref.get_state(i)[0]):
+            assert np.array_equal(a, b)
+    ctx.close()
+    ref.close()
+
+
 def test_graph_equals_eager_and_checkpoint_resume():
     spec, U = W.config2(n=64)
     ctx = af.Context(spec)
