@@ -627,11 +627,9 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
     // wave-speed chunks
     std::vector<int2> chunks;
     for (int i = 0; i < n_inst; i++) {
-        // whole rows per chunk (the wave-speed kernel walks rows)
+        // rows, or segments of long rows, per chunk (af4::wave_chunk)
         const InstDev &I = c->ih[i];
-        const long long rows = (long long)I.n[1] * I.n[2];
-        const long long rpc = (af4::kWaveChunk + I.n[0] - 1) / I.n[0];
-        const long long nch = (rows + rpc - 1) / rpc;
+        const long long nch = af4::wave_chunk_count(I.n[0], (long long)I.n[1] * I.n[2]);
         for (long long k = 0; k < nch; k++) chunks.push_back(make_int2(i, (int)k));
     }
     c->nchunks = (int)chunks.size();

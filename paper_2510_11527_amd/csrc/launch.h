@@ -41,7 +41,39 @@ hipError_t stage_launch_d3(int prec, bool lim, bool si, unsigned caps, int varia
 
 // FP64 max over faces of alpha_l/dx_l + kappa_max/dx_l^2 of the averages of
 // U (per instance, into InstState::wmax), plus the divergence check.
-constexpr int kWaveChunk = 2048;  // cells per wave-speed block (rounded up to whole rows)
+constexpr int kWaveChunk = 2048;  // cells per wave-speed block (about)
+constexpr int kWaveThreads = 256;  // threads per wave-speed block (four waves)
+// Cells of wave-speed chunk k of an instance whose rows hold n0 cells
+// (nrows rows): whole rows [r0, r1) when a row holds at most kWaveChunk
+// cells, else one row r0 split into equal column segments [i0, i1).
+struct WaveChunk {
+    int r0, r1, i0, i1;
+};
+__host__ __device__ inline int wave_chunks_per_row(int n0) { return (n0 + kWaveChunk - 1) / kWaveChunk; }
+__host__ __device__ inline long long wave_chunk_count(int n0, long long nrows)
+{
+    if (n0 > kWaveChunk) return nrows * wave_chunks_per_row(n0);
+    const long long rpc = (kWaveChunk + n0 - 1) / n0;
+    return (nrows + rpc - 1) / rpc;
+}
+__host__ __device__ inline WaveChunk wave_chunk(int n0, long long nrows, long long k)
+{
+    WaveChunk c;
+    if (n0 > kWaveChunk) {
+        const int spr = wave_chunks_per_row(n0), seg = (n0 + spr - 1) / spr, s = (int)(k % spr);
+        c.r0 = (int)(k / spr);
+        c.r1 = c.r0 + 1;
+        c.i0 = s * seg;
+        c.i1 = s * seg + seg < n0 ? s * seg + seg : n0;
+    } else {
+        const long long rpc = (kWaveChunk + n0 - 1) / n0;
+        c.r0 = (int)(k * rpc);
+        c.r1 = (int)(k * rpc + rpc < nrows ? k * rpc + rpc : nrows);
+        c.i0 = 0;
+        c.i1 = n0;
+    }
+    return c;
+}
 hipError_t wavespeed_launch(int dim, int prec, const InstDev *inst, const int2 *chunks, int nchunks, const void *U,
                             InstState *st, hipStream_t s);
 
