@@ -36,6 +36,7 @@ struct af_ctx {
     int2 *d_chunks = nullptr;
     unsigned long long *d_mm = nullptr;  // per-wave min / max slots of the last stage
     int waves_per_block = 1;
+    long long max_slots = 0;  // most min / max slot pairs of one instance
     int nchunks = 0;
     void *buf[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // state buffers (A = U^n)
     long long total = 0;     // elements per state buffer
@@ -340,8 +341,9 @@ void drop_graph(af_ctx *c)
 }
 
 // Fluxes with convex |f'| (linear, quadratic): the CFL wave speed is a
-// function of the min / max average, which the last stage of a step reduces.
-bool cfl_from_keys(const af_ctx *c) { return (c->caps & af4::kCapQF) != 0 && !c->open; }
+// function of the min / max average, which the last stage of a step reduces
+// (with open ends, together with the Dirichlet ghost values).
+bool cfl_from_keys(const af_ctx *c) { return (c->caps & af4::kCapQF) != 0; }
 
 // Work list (instance, tile) for the current variant; instances are kept
 // contiguous so that one instance can be launched alone.
@@ -374,6 +376,9 @@ af_status build_work(af_ctx *c)
     c->d_mm = nullptr;
     // one slot pair per wave of every work item
     c->waves_per_block = (vi.nt + 63) / 64;
+    c->max_slots = 0;
+    for (int i = 0; i < c->n_inst; i++)
+        c->max_slots = std::max(c->max_slots, (long long)c->work_count[i] * c->waves_per_block);
     HIPOK(c, hipMalloc(&c->d_mm, sizeof(unsigned long long) * 2 * c->waves_per_block * work.size()));
     c->keys_fresh = false;
     HIPOK(c, hipMemcpy(c->d_work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice));
@@ -432,8 +437,8 @@ hipError_t enqueue_step(af_ctx *c, bool ws, std::vector<hipEvent_t> *events, siz
         e = af4::wavespeed_launch(c->dim, c->prec, c->d_inst, c->d_chunks, c->nchunks, c->buf[0], c->d_st, c->stream);
         if (e != hipSuccess) return e;
     }
-    e = af4::finalize_launch(c->n_inst, c->d_inst, c->d_ctl, c->d_dtp, c->d_st, c->dim, ws ? nullptr : c->d_mm,
-                             c->waves_per_block, c->stream);
+    e = af4::finalize_launch(c->n_inst, c->d_inst, c->d_ctl, c->d_dtp, c->d_st, c->dim, c->prec,
+                             ws ? nullptr : c->d_mm, c->waves_per_block, c->max_slots, c->stream);
     if (e != hipSuccess) return e;
     const bool mm = cfl_from_keys(c);
     const StageSpec *sp = stages_of(c->integ);

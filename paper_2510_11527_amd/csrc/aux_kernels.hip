@@ -129,10 +129,14 @@ __global__ void __launch_bounds__(kWaveThreads) wavespeed_kernel(const InstDev *
 // is convex on the bounds interval (linear and quadratic fluxes, no interior
 // maxima): then the maximum of alpha_int over all faces is
 // max(|f_l'(min)|, |f_l'(max)|), evaluated in FP64 exactly as the wave-speed
-// kernel evaluates it per face, so the time step is the same to the bit.
-constexpr int kFinalizeThreads = 1024;  // a large instance has 4 slot pairs per 256 cells
-__global__ void __launch_bounds__(kFinalizeThreads) finalize_kernel(const InstDev *inst, const StepCtl *ctl, const double *dtp,
-                                                      InstState *st, int dim, const unsigned long long *mm,
+// kernel evaluates it per face, so the time step is the same to the bit
+// (min and max over the averages and, with open ends, the Dirichlet ghost
+// values as stored).
+// NT threads per block: 1024 where an instance has many slot pairs (a large
+// grid has one pair per wave of 64 cells), else 256.
+template <int NT>
+__global__ void __launch_bounds__(NT) finalize_kernel(const InstDev *inst, const StepCtl *ctl, const double *dtp,
+                                                      InstState *st, int dim, int prec, const unsigned long long *mm,
                                                       int waves_per_block)
 {
     const int i = blockIdx.x;
@@ -146,16 +150,15 @@ __global__ void __launch_bounds__(kFinalizeThreads) finalize_kernel(const InstDe
     if (mm) {
         // slot pairs of the instance: four independent loads in flight per
         // thread, then a wave and a block reduction
-        constexpr int NW = kFinalizeThreads / 64;
+        constexpr int NW = NT / 64;
         __shared__ unsigned long long ka[NW], kb[NW];
         unsigned long long a = ~0ull, b = 0ull;
         const int n = I.wcount * waves_per_block;
         const ulonglong2 *m = (const ulonglong2 *)(mm + 2 * (long long)I.wstart * waves_per_block);
-        for (int k0 = threadIdx.x; k0 < n; k0 += 4 * kFinalizeThreads) {
+        for (int k0 = threadIdx.x; k0 < n; k0 += 4 * NT) {
             ulonglong2 v[4];
 #pragma unroll
-            for (int j = 0; j < 4; j++)
-                v[j] = k0 + kFinalizeThreads * j < n ? m[k0 + kFinalizeThreads * j] : make_ulonglong2(~0ull, 0ull);
+            for (int j = 0; j < 4; j++) v[j] = k0 + NT * j < n ? m[k0 + NT * j] : make_ulonglong2(~0ull, 0ull);
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 a = min(a, v[j].x);
@@ -186,6 +189,15 @@ __global__ void __launch_bounds__(kFinalizeThreads) finalize_kernel(const InstDe
     if (mm) {
         const double big = 1e6 * fmax(fmax(fabs(I.umin), fabs(I.umax)), 1.0);
         if (!(fabs(lo) <= big && fabs(hi) <= big)) st[i].flags |= 1u;  // divergent or non-finite
+        // a Dirichlet end's ghost value (as stored) is an average of the end
+        // faces too; outflow ghosts repeat a boundary average
+        for (int l = 0; l < 2; l++)
+            for (int e = 0; e < 2; e++)
+                if (l < dim && I.bc[l][e] == 1) {
+                    const double g = prec == 32 ? (double)(float)I.bcv[l][e] : I.bcv[l][e];
+                    lo = fmin(lo, g);
+                    hi = fmax(hi, g);
+                }
         Phys<double> P;
         P.load(I, dim);
         // constant axes: Phys stays in registers
@@ -303,10 +315,15 @@ hipError_t wavespeed_launch(int dim, int prec, const InstDev *inst, const int2 *
 }
 
 hipError_t finalize_launch(int n_inst, const InstDev *inst, const StepCtl *ctl, const double *dtp, InstState *st,
-                           int dim, const unsigned long long *mm, int waves_per_block, hipStream_t s)
+                           int dim, int prec, const unsigned long long *mm, int waves_per_block, long long max_slots,
+                           hipStream_t s)
 {
-    hipLaunchKernelGGL(finalize_kernel, dim3(n_inst), dim3(kFinalizeThreads), 0, s, inst, ctl, dtp, st, dim, mm,
-                       waves_per_block);
+    if (mm && max_slots > 16384)
+        hipLaunchKernelGGL(finalize_kernel<1024>, dim3(n_inst), dim3(1024), 0, s, inst, ctl, dtp, st, dim, prec, mm,
+                           waves_per_block);
+    else
+        hipLaunchKernelGGL(finalize_kernel<256>, dim3(n_inst), dim3(256), 0, s, inst, ctl, dtp, st, dim, prec, mm,
+                           waves_per_block);
     return hipGetLastError();
 }
 

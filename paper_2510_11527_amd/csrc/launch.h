@@ -80,9 +80,12 @@ hipError_t wavespeed_launch(int dim, int prec, const InstDev *inst, const int2 *
 // dt and t of every instance from the wave speeds (or the prescribed steps);
 // mm != nullptr: from the min / max average slots written by the previous
 // step's last stage (waves_per_block slot pairs per work item) instead of the
-// wave-speed kernel (fluxes with convex |f'| only).
+// wave-speed kernel (fluxes with convex |f'| only); prec: storage precision
+// (the Dirichlet ghost values enter the min / max as stored); max_slots: the
+// largest number of slot pairs of one instance (sizes the reduction).
 hipError_t finalize_launch(int n_inst, const InstDev *inst, const StepCtl *ctl, const double *dtp, InstState *st,
-                           int dim, const unsigned long long *mm, int waves_per_block, hipStream_t s);
+                           int dim, int prec, const unsigned long long *mm, int waves_per_block, long long max_slots,
+                           hipStream_t s);
 
 // dst = src over n values.
 hipError_t copy_launch(int prec, const void *src, void *dst, long long n, hipStream_t s);

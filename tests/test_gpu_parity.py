@@ -360,13 +360,20 @@ def test_conservation_and_bounds_long_run():
 
 
 @pytest.mark.parametrize("name,integ", [("c2", "ssprk3"), ("c4", "ssprk3"), ("c5", "ssprk3"), ("c1", "ssprk3"),
-                                        ("c2", "euler"), ("c4", "ssprk54")])
+                                        ("c2", "euler"), ("c4", "ssprk54"), ("ek", "ssprk3"), ("ek", "ssprk54"),
+                                        ("c2open", "ssprk3")])
 def test_cfl_from_last_stage_minmax_equals_wave_speed_pass(name, integ):
     """For convex |f'| the last stage of a step reduces the min / max average
     and the next step's CFL step comes from them; it must equal, to the bit,
     the step the separate FP64 wave-speed pass computes on the same state."""
     if name == "c4":
         items = W.config4(n_inst=4, sizes=(32, 48))
+    elif name == "ek":              # Dirichlet ends, 1D: ghost values in the min / max
+        items = W.config_ek(n_inst=3, n=48)
+    elif name == "c2open":          # Dirichlet and outflow ends, 2D (own-items kernel)
+        spec, U = W.config2(n=40)
+        g0, g1 = spec["umin"], 0.5 * (spec["umin"] + spec["umax"])
+        items = [(dict(spec, bcs=[(("dirichlet", g1), ("dirichlet", g0)), ("outflow", "outflow")]), U)]
     else:
         items = [_steps_case(name)]
     specs = [s for s, _ in items]
