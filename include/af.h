@@ -220,6 +220,19 @@ af_status af_step_timed(af_ctx *ctx, int nsteps, double t_end, const double *dt_
  * variant selected before the call is restored. */
 af_status af_autotune(af_ctx *ctx, int nsteps, int *chosen, double *ms_per_stage);
 
+/* Limiter activity of instance inst (Sec. 5.1.1, 5.2.1): one forward-Euler
+ * stage of the current state with the current CFL step is evaluated, with
+ * the generic stage kernel, into scratch memory, and the limiting parameters
+ * below 1 are counted: counts[0] face fluxes evaluated (one per cell and
+ * direction, the face c + 1/2), counts[1] of those with theta < 1,
+ * counts[2] cell potentials evaluated (one per cell and direction; 0 in the
+ * App. A form, which limits face fluxes only), counts[3] of those with
+ * theta < 1.  The state, time, step count and flags are left as they were;
+ * the tile variant in use is restored.  AF_ERR_UNSUPPORTED without the
+ * limiter, AF_ERR_STATE before af_set_state; allocates 16 bytes per instance
+ * of device memory on the first call (kept until af_destroy). */
+af_status af_limiter_activity(af_ctx *ctx, int inst, long long *counts);
+
 /* Algorithmic HBM bytes of one stage launch over all instances, averaged over
  * the stages of one step: (2 + 1 for stages that read U^n) * 2^d * cells *
  * value size.  Grid cells and DoFs of the context in *cells, *dofs. */

@@ -25,7 +25,7 @@ INTEGRATORS = {"ssprk3": 0, "euler": 1, "ssprk54": 2}
 
 EXPORTS = ["af_create", "af_destroy", "af_set_state", "af_get_state", "af_step", "af_residual", "af_norms",
            "af_last_error", "af_set_stream", "af_set_variant", "af_num_variants", "af_variant_name",
-           "af_step_timed", "af_work", "af_get_variant", "af_autotune"]
+           "af_step_timed", "af_work", "af_get_variant", "af_autotune", "af_limiter_activity"]
 
 
 class AfProblem(ctypes.Structure):
@@ -94,6 +94,7 @@ def lib():
         L.af_variant_name.restype = ctypes.c_char_p
         L.af_work.argtypes = [vp, dp, dp, dp]
         L.af_autotune.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
+        L.af_limiter_activity.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
         for name in EXPORTS:
             if name not in ("af_last_error", "af_num_variants", "af_variant_name", "af_get_variant"):
                 getattr(L, name).restype = ctypes.c_int
@@ -246,6 +247,14 @@ class Context:
 
     def variant(self):
         return lib().af_get_variant(self.h)
+
+    def limiter_activity(self, inst):
+        """Counts of af_limiter_activity: face fluxes, of which limited, cell
+        potentials, of which limited (one forward-Euler stage of the current
+        state; the state is left unchanged)."""
+        c = (ctypes.c_longlong * 4)()
+        self._check(lib().af_limiter_activity(self.h, int(inst), c))
+        return {"faces": c[0], "faces_limited": c[1], "potentials": c[2], "potentials_limited": c[3]}
 
     def autotune(self, nsteps=5):
         """Select the fastest tile variant on the current state (af_autotune);

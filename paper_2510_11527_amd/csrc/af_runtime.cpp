@@ -37,6 +37,8 @@ struct af_ctx {
     unsigned long long *d_mm = nullptr;  // per-wave min / max slots of the last stage
     int waves_per_block = 1;
     long long max_slots = 0;  // most min / max slot pairs of one instance
+    unsigned long long *d_lact = nullptr;  // limiter-activity counters (2 per instance), on demand
+    bool lact_on = false;                  // stage launches count limited faces / potentials
     int nchunks = 0;
     void *buf[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // state buffers (A = U^n)
     long long total = 0;     // elements per state buffer
@@ -406,6 +408,7 @@ StageParams<T> stage_params(af_ctx *c, const StageSpec &sp, int stage)
     p.cin = (T)sp.cin;
     p.dts = (T)sp.dts;
     p.mm = nullptr;
+    p.lact = c->lact_on ? c->d_lact : nullptr;
     return p;
 }
 
@@ -658,9 +661,10 @@ af_status af_destroy(af_ctx *c)
     if (!c) return AF_OK;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
-    for (int b = 0; b < 3; b++)
+    for (int b = 0; b < 5; b++)  // SSP-RK(5,4) contexts hold five state buffers
         if (c->buf[b]) (void)hipFree(c->buf[b]);
-    void *ptrs[] = {c->d_inst, c->d_st, c->d_ctl, c->d_dtp, c->d_work, c->d_chunks, c->d_npart, c->d_nout, c->d_mm};
+    void *ptrs[] = {c->d_inst, c->d_st,     c->d_ctl,  c->d_dtp, c->d_work,
+                    c->d_chunks, c->d_npart, c->d_nout, c->d_mm,  c->d_lact};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -939,6 +943,68 @@ af_status af_autotune(af_ctx *c, int nsteps, int *chosen, double *ms_per_stage)
     (void)hipFree(backup);
     if (s == AF_OK && chosen) *chosen = best;
     return s;
+}
+
+af_status af_limiter_activity(af_ctx *c, int inst, long long *counts)
+{
+    if (!c || inst < 0 || inst >= c->n_inst || !counts) return fail(c, AF_ERR_ARG, "af_limiter_activity: bad arguments");
+    af_status s = check_ready(c);
+    if (s != AF_OK) return s;
+    if (!c->lim) return fail(c, AF_ERR_UNSUPPORTED, "af_limiter_activity: the limiter is off");
+    // the generic kernel counts; the tile variant in use is restored after
+    const int nv = af4::stage_num_variants(c->dim), v0 = c->variant;
+    int vg = -1;
+    for (int v = 0; v < nv && vg < 0; v++)
+        if (af4::stage_variant(c->dim, v).generic && af4::stage_supported(c->dim, c->prec, c->lim, c->si, c->caps, v))
+            vg = v;
+    if (vg < 0) return fail(c, AF_ERR_UNSUPPORTED, "af_limiter_activity: no generic kernel for this combination");
+    if (!c->d_lact) {
+        if (hipMalloc(&c->d_lact, sizeof(unsigned long long) * 2 * c->n_inst) != hipSuccess) {
+            (void)hipGetLastError();
+            c->d_lact = nullptr;
+            return fail(c, AF_ERR_ALLOC, "af_limiter_activity: counters");
+        }
+    }
+    std::vector<InstState> st(c->n_inst);
+    HIPOK(c, hipMemcpyAsync(st.data(), c->d_st, sizeof(InstState) * c->n_inst, hipMemcpyDeviceToHost, c->stream));
+    HIPOK(c, hipStreamSynchronize(c->stream));
+    if (vg != v0 && (s = af_set_variant(c, vg)) != AF_OK) return s;
+    unsigned long long h[2] = {0, 0};
+    hipError_t e = hipMemsetAsync(c->d_lact, 0, sizeof(unsigned long long) * 2 * c->n_inst, c->stream);
+    if (e == hipSuccess && (s = upload_ctl(c, 0.0, nullptr)) != AF_OK) e = hipErrorUnknown;
+    // the CFL step of the current state, then one forward-Euler stage into
+    // the scratch buffer B with counting on
+    if (e == hipSuccess && s == AF_OK)
+        e = af4::wavespeed_launch(c->dim, c->prec, c->d_inst, c->d_chunks, c->nchunks, c->buf[0], c->d_st, c->stream);
+    if (e == hipSuccess && s == AF_OK)
+        e = af4::finalize_launch(c->n_inst, c->d_inst, c->d_ctl, c->d_dtp, c->d_st, c->dim, c->prec, nullptr,
+                                 c->waves_per_block, c->max_slots, c->stream);
+    if (e == hipSuccess && s == AF_OK) {
+        const StageSpec fe = {0, 1, -1, af4::kCombFE, 1.0, 0, 0, 0, 1.0, false};
+        c->lact_on = true;
+        e = launch_stage(c, fe, 1, c->lim, c->si, c->work_start[inst], c->work_count[inst]);
+        c->lact_on = false;
+    }
+    if (e == hipSuccess && s == AF_OK)
+        e = hipMemcpyAsync(h, c->d_lact + 2 * inst, sizeof h, hipMemcpyDeviceToHost, c->stream);
+    // restore the per-instance scalars and the variant
+    if (e == hipSuccess && s == AF_OK)
+        e = hipMemcpyAsync(c->d_st, st.data(), sizeof(InstState) * c->n_inst, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && s == AF_OK) e = hipStreamSynchronize(c->stream);
+    c->keys_fresh = false;
+    const std::string msg = e != hipSuccess ? std::string("af_limiter_activity: ") + hipGetErrorString(e) : c->err;
+    if (vg != v0) {
+        const af_status s2 = af_set_variant(c, v0);
+        if (s == AF_OK && e == hipSuccess) s = s2;
+    }
+    if (e != hipSuccess) return fail(c, AF_ERR_DEVICE, msg);
+    if (s != AF_OK) return s;
+    const long long ncell = c->ih[inst].ncell;
+    counts[0] = c->dim * ncell;                                        // face fluxes
+    counts[1] = (long long)h[0];                                       // of which limited
+    counts[2] = c->ih[inst].nodc ? 0 : c->dim * ncell;                 // cell potentials
+    counts[3] = (long long)h[1];                                       // of which limited
+    return AF_OK;
 }
 
 af_status af_residual(af_ctx *c, int inst, double *const *rhs)

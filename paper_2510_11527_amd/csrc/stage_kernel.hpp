@@ -772,6 +772,8 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
         }
     });
 
+    unsigned nlf = 0, nlp = 0;  // limited own faces and potentials (p.lact)
+
     // ---- D1: per direction, faces and cells of the average update.
     // Face array of direction l: index f along l <-> left cell h_l - 2 + f,
     // f in [0, t_l + 3); other axes: own range.  Cell array: index c along l
@@ -845,7 +847,12 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                     const T s3 = (nodc ? T(1) : T(3)) * K * mu[l] * df;
                     // min(Theta(up, up - s3), Theta(um, um + s3)) with one reciprocal
                     const T gap = gap2<T>(s3, um, up, P.umin, P.umax);
-                    F = fL + theta_from_gap<T>(gap, (T)fabs(s3)) * df;
+                    const T th = theta_from_gap<T>(gap, (T)fabs(s3));
+                    F = fL + th * df;
+                    // the face c+1/2 of a tile cell c inside the instance
+                    if (p.lact && th < T(1) && fidx >= 2 && fidx < G::t(l) + 2 &&
+                        ox + i - 2 * sx < n0 && oy + j - 2 * sy < n1 && oz + k - 2 * sz < n2)
+                        nlf++;
                 }
             }
             fl[G::face_off(l) + id] = F;
@@ -897,7 +904,13 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                     const T s3 = T(3) * K * nu[l] * da;
                     // min of the four Theta's (pL, mR move by +s3; pC, mC by -s3)
                     const T gap = gap4<T>(s3, pL, mR, pC, mC, P.umin, P.umax);
-                    Pv = aL + theta_from_gap<T>(gap, (T)fabs(s3)) * da;
+                    const T th = theta_from_gap<T>(gap, (T)fabs(s3));
+                    Pv = aL + th * da;
+                    // a tile cell inside the instance
+                    const int cl = l == 0 ? i : (l == 1 ? j : k);
+                    if (p.lact && th < T(1) && cl >= 1 && cl <= G::t(l) && ox + i - sx < n0 && oy + j - sy < n1 &&
+                        oz + k - sz < n2)
+                        nlp++;
                 }
             }
             pc[G::cell_off(l) + id] = Pv;
@@ -956,6 +969,19 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
         if (bad) atomicOr(&p.st[wk.x].flags, 1u);
         if constexpr (LIM) atomic_max_wave(&p.st[wk.x].clampmax, clamp_mag);
         if (p.mm) minmax_slot(p.mm, logical, vlo, vhi);
+        if constexpr (LIM) {
+            if (p.lact) {
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) {
+                    nlf += __shfl_xor(nlf, o);
+                    nlp += __shfl_xor(nlp, o);
+                }
+                if ((threadIdx.x & 63) == 0) {
+                    if (nlf) atomicAdd(&p.lact[2 * wk.x], (unsigned long long)nlf);
+                    if (nlp) atomicAdd(&p.lact[2 * wk.x + 1], (unsigned long long)nlp);
+                }
+            }
+        }
     }
 }
 

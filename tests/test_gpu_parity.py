@@ -304,6 +304,47 @@ def test_autotune_selects_a_built_variant_and_leaves_the_solution(case):
     ref.close()
 
 
+@pytest.mark.parametrize("d,form", [(1, "dc"), (2, "dc"), (3, "dc"), (1, "nodc")])
+def test_limiter_activity_matches_oracle(d, form):
+    """af_limiter_activity counts, in one FE stage with the CFL step, the face
+    fluxes and cell potentials whose limiting parameter is below 1, once
+    each.  The oracle evaluates every face from both its cells and every
+    potential from three cells (periodic grid), so its count of theta < 1 is
+    2 F + 3 P.  The call leaves state and variant as they were."""
+    rng = np.random.default_rng(700 + 10 * d + (form == "nodc"))
+    n = {1: 61, 2: 19, 3: 9}[d]
+    spec = small_spec(d, n, ("quad", 0.5, 0.0), ("power", 0.05, 2.0), limiter=True, precision=64)
+    spec["diffusion_form"] = form
+    U = state_for(spec, rng)
+    s, U = prepare(spec, U, 64)
+    ctx = af.Context(s)
+    v0 = ctx.variant()
+    ctx.set_state(0, U)
+    c = ctx.limiter_activity(0)
+    note("limiter activity d=%d %s: %s" % (d, form, c))
+    assert ctx.variant() == v0
+    V, t = ctx.get_state(0)
+    assert t == 0.0 and all(np.array_equal(a, b) for a, b in zip(V, U))
+    P = oracle.problem(s)
+    dt = oracle.dt_cfl(P, U, s["cfl"])
+    _, dg = oracle.fe(P, U, dt)
+    N = int(np.prod(s["n"][:d]))
+    assert c["faces"] == d * N and c["potentials"] == (0 if form == "nodc" else d * N)
+    assert dg["n_theta"] == 2 * c["faces"] + 3 * c["potentials"]
+    lim = 2 * c["faces_limited"] + 3 * c["potentials_limited"]
+    assert c["faces_limited"] > 0
+    assert abs(lim - dg["n_theta_lt1"]) <= 2, (lim, dg["n_theta_lt1"])
+    # stepping on is unaffected by the diagnostic
+    d1 = ctx.step(2)
+    ref = af.Context(s)
+    ref.set_state(0, U)
+    d2 = ref.step(2)
+    assert np.array_equal(d1, d2)
+    assert all(np.array_equal(a, b) for a, b in zip(ctx.get_state(0)[0], ref.get_state(0)[0]))
+    ctx.close()
+    ref.close()
+
+
 def test_graph_equals_eager_and_checkpoint_resume():
     spec, U = W.config2(n=64)
     ctx = af.Context(spec)
