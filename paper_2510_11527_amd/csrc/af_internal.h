@@ -98,9 +98,10 @@ struct StageParams {
     // keys (see ordered_key) of the min and max average it wrote to
     // mm[2 (k W + w)] and mm[2 (k W + w) + 1], W = waves per block
     unsigned long long *mm;
-    // not null (limiter-activity diagnostic; generic kernel only): the block
-    // adds its own faces and cell potentials whose limiting parameter is
-    // below 1 to lact[2 i] and lact[2 i + 1] of its instance i
+    // not null: the limiter-counting form of the generic kernel runs (one
+    // tile variant per dimension, limiter on); each block adds its own faces
+    // and cell potentials whose limiting parameter is below 1 to lact[2 i]
+    // and lact[2 i + 1] of its instance i
     unsigned long long *lact;
 };
 

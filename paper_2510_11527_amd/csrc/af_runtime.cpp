@@ -14,6 +14,7 @@
 #include "af.h"
 #include "af_internal.h"
 #include "launch.h"
+#include "variants.h"
 
 using af4::InstDev;
 using af4::InstState;
@@ -951,13 +952,11 @@ af_status af_limiter_activity(af_ctx *c, int inst, long long *counts)
     af_status s = check_ready(c);
     if (s != AF_OK) return s;
     if (!c->lim) return fail(c, AF_ERR_UNSUPPORTED, "af_limiter_activity: the limiter is off");
-    // the generic kernel counts; the tile variant in use is restored after
-    const int nv = af4::stage_num_variants(c->dim), v0 = c->variant;
-    int vg = -1;
-    for (int v = 0; v < nv && vg < 0; v++)
-        if (af4::stage_variant(c->dim, v).generic && af4::stage_supported(c->dim, c->prec, c->lim, c->si, c->caps, v))
-            vg = v;
-    if (vg < 0) return fail(c, AF_ERR_UNSUPPORTED, "af_limiter_activity: no generic kernel for this combination");
+    // the generic kernel of one tile variant has the counting form; the
+    // tile variant in use is restored after
+    const int v0 = c->variant, vg = af4::count_variant(c->dim);
+    if (!af4::stage_supported(c->dim, c->prec, c->lim, c->si, c->caps, vg))
+        return fail(c, AF_ERR_UNSUPPORTED, "af_limiter_activity: the counting kernel does not fit this combination");
     if (!c->d_lact) {
         if (hipMalloc(&c->d_lact, sizeof(unsigned long long) * 2 * c->n_inst) != hipSuccess) {
             (void)hipGetLastError();

@@ -374,11 +374,11 @@ int stage_num_variants(int dim)
 
 VariantInfo stage_variant(int dim, int v)
 {
-    VariantInfo r = {{1, 1, 1}, 0, "", 0};
+    VariantInfo r = {{1, 1, 1}, 0, ""};
 #define AF4_INFO(V, TX, TY, TZ, NT, NAME) \
-    if (v == V) r = VariantInfo{{TX, TY, TZ}, NT, NAME, 1};
+    if (v == V) r = VariantInfo{{TX, TY, TZ}, NT, NAME};
 #define AF4_INFO2(V, TX, TY, TZ, NT, KIND, NAME) \
-    if (v == V) r = VariantInfo{{TX, TY, TZ}, NT, NAME, KIND == 0};
+    if (v == V) r = VariantInfo{{TX, TY, TZ}, NT, NAME};
     if (dim == 1) { AF4_VARIANTS_D1(AF4_INFO) }
     if (dim == 2) { AF4_VARIANTS_D2(AF4_INFO2) }
     if (dim == 3) { AF4_VARIANTS_D3(AF4_INFO) }

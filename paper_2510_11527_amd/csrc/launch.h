@@ -8,7 +8,6 @@ struct VariantInfo {
     int tile[3];
     int nt;
     const char *name;
-    int generic;  // the generic stage kernel (every dimension, flux, end and blending)
 };
 
 int stage_num_variants(int dim);

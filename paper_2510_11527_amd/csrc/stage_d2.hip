@@ -8,14 +8,21 @@ namespace {
 
 constexpr long kLdsCap = 160L * 1024L;
 
-template <class T, bool LIM, bool SI, bool QF, int TX, int TY, int NT>
+// CV: the variant with the limiter-counting form (p.lact not null)
+template <class T, bool LIM, bool SI, bool QF, int TX, int TY, int NT, bool CV>
 hipError_t launch_generic(int nblocks, const void *params, hipStream_t s)
 {
+    const StageParams<T> &p = *(const StageParams<T> *)params;
     if constexpr (stage_lds_bytes<2, T, LIM, SI, TX, TY, 1>() > kLdsCap) {
         return hipErrorInvalidValue;
+    } else if (p.lact) {
+        if constexpr (CV && LIM) {
+            hipLaunchKernelGGL((stage_kernel<2, T, LIM, SI, QF, TX, TY, 1, NT, true>), dim3(nblocks), dim3(NT), 0, s, p);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
     } else {
-        hipLaunchKernelGGL((stage_kernel<2, T, LIM, SI, QF, TX, TY, 1, NT>), dim3(nblocks), dim3(NT), 0, s,
-                           *(const StageParams<T> *)params);
+        hipLaunchKernelGGL((stage_kernel<2, T, LIM, SI, QF, TX, TY, 1, NT>), dim3(nblocks), dim3(NT), 0, s, p);
         return hipGetLastError();
     }
 }
@@ -51,10 +58,11 @@ hipError_t launch_own_lim(bool lim, int nblocks, const void *params, hipStream_t
                : launch_own<T, false, FL, TX, TY, NT>(nblocks, params, s);
 }
 
-template <class T, int TX, int TY, int NT, int KIND>
+template <class T, int TX, int TY, int NT, int KIND, bool CV>
 hipError_t launch_kind(bool lim, bool si, unsigned caps, int nblocks, const void *params, hipStream_t s)
 {
     const bool qf = (caps & kCapQF) != 0;
+    if (KIND != 0 && ((const StageParams<T> *)params)->lact) return hipErrorInvalidValue;  // counting: generic only
     if (KIND != 0 && KIND != 4 && (caps & kCapOpen)) return hipErrorInvalidValue;  // ghosts: generic, own-items
     if constexpr (KIND == 4) {
         if (si || !(caps & kCapI32) || !(qf || (caps & kCapBLF))) return hipErrorInvalidValue;
@@ -71,15 +79,15 @@ hipError_t launch_kind(bool lim, bool si, unsigned caps, int nblocks, const void
         return hipErrorInvalidValue;
     } else if constexpr (KIND == 0) {
         if (qf) {
-            if (lim) return si ? launch_generic<T, true, true, true, TX, TY, NT>(nblocks, params, s)
-                               : launch_generic<T, true, false, true, TX, TY, NT>(nblocks, params, s);
-            return si ? launch_generic<T, false, true, true, TX, TY, NT>(nblocks, params, s)
-                      : launch_generic<T, false, false, true, TX, TY, NT>(nblocks, params, s);
+            if (lim) return si ? launch_generic<T, true, true, true, TX, TY, NT, CV>(nblocks, params, s)
+                               : launch_generic<T, true, false, true, TX, TY, NT, CV>(nblocks, params, s);
+            return si ? launch_generic<T, false, true, true, TX, TY, NT, CV>(nblocks, params, s)
+                      : launch_generic<T, false, false, true, TX, TY, NT, CV>(nblocks, params, s);
         }
-        if (lim) return si ? launch_generic<T, true, true, false, TX, TY, NT>(nblocks, params, s)
-                           : launch_generic<T, true, false, false, TX, TY, NT>(nblocks, params, s);
-        return si ? launch_generic<T, false, true, false, TX, TY, NT>(nblocks, params, s)
-                  : launch_generic<T, false, false, false, TX, TY, NT>(nblocks, params, s);
+        if (lim) return si ? launch_generic<T, true, true, false, TX, TY, NT, CV>(nblocks, params, s)
+                           : launch_generic<T, true, false, false, TX, TY, NT, CV>(nblocks, params, s);
+        return si ? launch_generic<T, false, true, false, TX, TY, NT, CV>(nblocks, params, s)
+                  : launch_generic<T, false, false, false, TX, TY, NT, CV>(nblocks, params, s);
     } else {
         constexpr bool FT = KIND == 1;
         if (si) return hipErrorInvalidValue;
@@ -136,8 +144,8 @@ hipError_t stage_launch_d2(int prec, bool lim, bool si, unsigned caps, int varia
     switch (variant) {
 #define AF4_CASE(V, TX, TY, TZ, NT, KIND, NAME)                                                            \
     case V:                                                                                                \
-        return prec == 32 ? launch_kind<float, TX, TY, NT, KIND>(lim, si, caps, nblocks, params, s)         \
-                          : launch_kind<double, TX, TY, NT, KIND>(lim, si, caps, nblocks, params, s);
+        return prec == 32 ? launch_kind<float, TX, TY, NT, KIND, V == count_variant(2)>(lim, si, caps, nblocks, params, s) \
+                          : launch_kind<double, TX, TY, NT, KIND, V == count_variant(2)>(lim, si, caps, nblocks, params, s);
         AF4_VARIANTS_D2(AF4_CASE)
 #undef AF4_CASE
     }

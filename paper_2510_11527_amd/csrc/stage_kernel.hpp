@@ -426,8 +426,9 @@ constexpr int stage_face_area()
 }
 
 // QF: every flux is c1 u + c2 u^2 (evaluated in closed form, no branches on
-// the flux kind)
-template <int D, class T, bool LIM, bool SI, bool QF, int TX, int TY, int TZ, int NT>
+// the flux kind); CNT (with LIM): the limiter-counting form, which also adds
+// the own faces and potentials limited to p.lact
+template <int D, class T, bool LIM, bool SI, bool QF, int TX, int TY, int TZ, int NT, bool CNT = false>
 __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
 {
     constexpr int HL = SI ? 3 : 2;
@@ -850,7 +851,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                     const T th = theta_from_gap<T>(gap, (T)fabs(s3));
                     F = fL + th * df;
                     // the face c+1/2 of a tile cell c inside the instance
-                    if (p.lact && th < T(1) && fidx >= 2 && fidx < G::t(l) + 2 &&
+                    if (CNT && th < T(1) && fidx >= 2 && fidx < G::t(l) + 2 &&
                         ox + i - 2 * sx < n0 && oy + j - 2 * sy < n1 && oz + k - 2 * sz < n2)
                         nlf++;
                 }
@@ -908,7 +909,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                     Pv = aL + th * da;
                     // a tile cell inside the instance
                     const int cl = l == 0 ? i : (l == 1 ? j : k);
-                    if (p.lact && th < T(1) && cl >= 1 && cl <= G::t(l) && ox + i - sx < n0 && oy + j - sy < n1 &&
+                    if (CNT && th < T(1) && cl >= 1 && cl <= G::t(l) && ox + i - sx < n0 && oy + j - sy < n1 &&
                         oz + k - sz < n2)
                         nlp++;
                 }
@@ -969,8 +970,8 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
         if (bad) atomicOr(&p.st[wk.x].flags, 1u);
         if constexpr (LIM) atomic_max_wave(&p.st[wk.x].clampmax, clamp_mag);
         if (p.mm) minmax_slot(p.mm, logical, vlo, vhi);
-        if constexpr (LIM) {
-            if (p.lact) {
+        if constexpr (LIM && CNT) {
+            {
 #pragma unroll
                 for (int o = 32; o >= 1; o >>= 1) {
                     nlf += __shfl_xor(nlf, o);

@@ -17,6 +17,10 @@ namespace af4 {
     X(2, 32, 16, 1, 256, 1, "2d-table4-32x16") X(3, 32, 8, 1, 128, 1, "2d-table4-32x8")              \
     X(4, 32, 16, 1, 256, 2, "2d-table2-32x16") X(5, 32, 8, 1, 256, 0, "generic-32x8")                \
     X(6, 16, 16, 1, 256, 0, "generic-16x16") X(7, 32, 32, 1, 512, 4, "2d-own-32x32")
+// the tile variant whose generic kernel also has the limiter-counting form
+// (af_limiter_activity)
+constexpr int count_variant(int dim) { return dim == 2 ? 5 : 0; }
+
 #define AF4_VARIANTS_D3(X) X(0, 8, 8, 4, 256, "generic-8x8x4") X(1, 8, 4, 4, 128, "generic-8x4x4") X(2, 4, 4, 4, 64, "generic-4x4x4")
 
 }  // namespace af4
