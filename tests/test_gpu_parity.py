@@ -304,16 +304,17 @@ def test_autotune_selects_a_built_variant_and_leaves_the_solution(case):
     ref.close()
 
 
-@pytest.mark.parametrize("d,form", [(1, "dc"), (2, "dc"), (3, "dc"), (1, "nodc")])
-def test_limiter_activity_matches_oracle(d, form):
+@pytest.mark.parametrize("d,form,si", [(1, "dc", False), (2, "dc", False), (3, "dc", False), (1, "nodc", False),
+                                       (2, "dc", True), (3, "dc", True)])
+def test_limiter_activity_matches_oracle(d, form, si):
     """af_limiter_activity counts, in one FE stage with the CFL step, the face
     fluxes and cell potentials whose limiting parameter is below 1, once
     each.  The oracle evaluates every face from both its cells and every
     potential from three cells (periodic grid), so its count of theta < 1 is
     2 F + 3 P.  The call leaves state and variant as they were."""
-    rng = np.random.default_rng(700 + 10 * d + (form == "nodc"))
+    rng = np.random.default_rng(700 + 10 * d + (form == "nodc") + 3 * si)
     n = {1: 61, 2: 19, 3: 9}[d]
-    spec = small_spec(d, n, ("quad", 0.5, 0.0), ("power", 0.05, 2.0), limiter=True, precision=64)
+    spec = small_spec(d, n, ("quad", 0.5, 0.0), ("power", 0.05, 2.0), limiter=True, si=si, precision=64)
     spec["diffusion_form"] = form
     U = state_for(spec, rng)
     s, U = prepare(spec, U, 64)
@@ -321,7 +322,7 @@ def test_limiter_activity_matches_oracle(d, form):
     v0 = ctx.variant()
     ctx.set_state(0, U)
     c = ctx.limiter_activity(0)
-    note("limiter activity d=%d %s: %s" % (d, form, c))
+    note("limiter activity d=%d %s si=%d: %s" % (d, form, si, c))
     assert ctx.variant() == v0
     V, t = ctx.get_state(0)
     assert t == 0.0 and all(np.array_equal(a, b) for a, b in zip(V, U))
@@ -343,6 +344,39 @@ def test_limiter_activity_matches_oracle(d, form):
     assert all(np.array_equal(a, b) for a, b in zip(ctx.get_state(0)[0], ref.get_state(0)[0]))
     ctx.close()
     ref.close()
+
+
+def test_limiter_activity_fp32_and_validation():
+    """FP32 contexts count too (within a few borderline decisions of the
+    FP64 count on the same rounded data); without the limiter the call is
+    unsupported, before af_set_state out of order."""
+    rng = np.random.default_rng(77)
+    spec = small_spec(2, 23, ("bl_grav", 0.0, 5.0), ("ramp2", 0.1, 0.3), limiter=True, precision=32)
+    U = state_for(spec, rng)
+    s32, U32 = prepare(spec, U, 32)
+    ctx = af.Context(s32)
+    with pytest.raises(af.AFError) as e:
+        ctx.limiter_activity(0)
+    assert e.value.status == af.AF_ERR_STATE
+    ctx.set_state(0, U32)
+    c32 = ctx.limiter_activity(0)
+    ctx.close()
+    s64 = dict(s32, precision=64)
+    ctx = af.Context(s64)
+    ctx.set_state(0, U32)
+    c64 = ctx.limiter_activity(0)
+    ctx.close()
+    note("limiter activity fp32 %s fp64 %s" % (c32, c64))
+    assert c32["faces"] == c64["faces"] and c32["potentials"] == c64["potentials"]
+    assert 0 < c64["faces_limited"] < c64["faces"]
+    tot = c64["faces"] + c64["potentials"]
+    assert abs(c32["faces_limited"] - c64["faces_limited"]) + abs(c32["potentials_limited"] - c64["potentials_limited"]) <= 0.01 * tot
+    ctx = af.Context(dict(s64, limiter=False))
+    ctx.set_state(0, U32)
+    with pytest.raises(af.AFError) as e:
+        ctx.limiter_activity(0)
+    assert e.value.status == af.AF_ERR_UNSUPPORTED
+    ctx.close()
 
 
 def test_graph_equals_eager_and_checkpoint_resume():
