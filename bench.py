@@ -43,10 +43,10 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_name, tile):
-    """HBM bytes per stage launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary of this workload and tile, if the kernel sources are
-    the ones it was measured with; else None."""
+def measured_counters(workload_name, tile):
+    """The committed rocprofv3 summary of this workload and tile -- HBM bytes
+    per stage launch (FETCH_SIZE / WRITE_SIZE) and VALU busy % -- if the
+    kernel sources are the ones it was measured with; else an empty dict."""
     sha = kernel_source_sha()
     for f in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.txt")):
         kv = {}
@@ -56,8 +56,20 @@ def measured_traffic(workload_name, tile):
                     k, v = line.strip().split("=", 1)
                     kv[k] = v
         if kv.get("workload") == workload_name and kv.get("tile") == tile and kv.get("source_sha") == sha:
-            return float(kv["traffic_bytes_per_launch"])
-    return None
+            return kv
+    return {}
+
+
+def measured_traffic(workload_name, tile):
+    """HBM bytes per stage launch (see measured_counters), or None."""
+    kv = measured_counters(workload_name, tile)
+    return float(kv["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in kv else None
+
+
+def measured_valu_busy(workload_name, tile):
+    """VALU busy % of the stage kernel (see measured_counters), or None."""
+    kv = measured_counters(workload_name, tile)
+    return float(kv["valu_busy_pct"]) if "valu_busy_pct" in kv else None
 
 
 def workload(name):
@@ -207,6 +219,7 @@ def main():
         achieved = work["bytes_per_stage"] / (ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wname, variant_name),
+                "valu_busy_pct": measured_valu_busy(wname, variant_name),
                 "kernel": "stage kernel %s (%s)" % (variant_name, "fp32" if prec == 32 else "fp64"),
                 "mean_launch_ms": ms, "launches": nl,
                 "algorithmic_bytes_per_launch": work["bytes_per_stage"]}
