@@ -34,7 +34,12 @@ enum : int { kALinear = 0, kAPower = 1, kADeadzone = 2, kABL = 3, kARamp2 = 4 };
 template <class T>
 __device__ __forceinline__ T fast_rcp(T v)
 {
-    return T(1) / v;
+    // hardware reciprocal refined by two Newton-Raphson steps r += r (1 - v r)
+    T r = __builtin_amdgcn_rcp(v);
+    T e = fma(-v, r, T(1));
+    r = fma(r, e, r);
+    e = fma(-v, r, T(1));
+    return fma(r, e, r);
 }
 template <>
 __device__ __forceinline__ float fast_rcp<float>(float v)
