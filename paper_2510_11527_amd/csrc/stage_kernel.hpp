@@ -29,12 +29,14 @@ namespace af4 {
 enum : int { kFLinear = 0, kFQuad = 1, kFBL = 2, kFBLGrav = 3 };
 enum : int { kALinear = 0, kAPower = 1, kADeadzone = 2, kABL = 3, kARamp2 = 4 };
 
-// 1/v: an IEEE division in FP64; in FP32 the hardware reciprocal (within
-// 1 ulp), which spares the ten-instruction correctly rounded division
+// 1/v within about an ulp, sparing the ten-instruction correctly rounded
+// division: in FP64 the hardware estimate refined by two Newton-Raphson
+// steps r += r (1 - v r) (v = 0 gives NaN, which the only caller that can
+// see it, the limiter's ratio, turns into 1 through fmin); in FP32 the
+// hardware reciprocal
 template <class T>
 __device__ __forceinline__ T fast_rcp(T v)
 {
-    // hardware reciprocal refined by two Newton-Raphson steps r += r (1 - v r)
     T r = __builtin_amdgcn_rcp(v);
     T e = fma(-v, r, T(1));
     r = fma(r, e, r);
