@@ -126,9 +126,24 @@ def cpu_baseline(items, target_cells, integrator="ssprk3"):
         P = oracle.problem(s)
         oracle.run(P, U, nsteps=1, cfl=s["cfl"], integrator=integrator)
     el = time.perf_counter() - t0
-    return {"value": cells * dofs_per_cell * STAGES[integrator] / el, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    # one core: one forward-Euler stage of the first cells of the first
+    # instance (cell by cell, so the sample stays bounded for any grid)
+    s0, U0 = items[0]
+    P0 = oracle.problem(s0)
+    k = min(int(np.prod(s0["n"][:s0["dim"]])), 200_000)
+    dt0 = oracle.dt_cfl(P0, U0, s0["cfl"])
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.fe_cells(P0, U0, dt0, np.arange(k))
+    el1 = time.perf_counter() - t1
+    oracle.set_threads(cores)
+    return {"value": cells * dofs_per_cell * STAGES[integrator] / el, "unit": UNIT, "cores": cores, "kind": "oracle",
             "sample": "first %d instances of the workload (%d cells), 1 %s step (%d stages), %.1f s"
-                      % (len(sample), cells, integrator, STAGES[integrator], el)}
+                      % (len(sample), cells, integrator, STAGES[integrator], el),
+            "single_core": {"value": k * dofs_per_cell / el1, "unit": UNIT, "cores": 1,
+                            "sample": "one forward-Euler stage of the first %d cells of the first instance, %.1f s"
+                                      % (k, el1)}}
 
 
 def fp64_plain(items, steps, max_cells, integrator="ssprk3"):

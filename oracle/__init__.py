@@ -113,6 +113,8 @@ def lib():
         L.orc_ssprk54_step.argtypes = [PP, pp, ctypes.c_double, pp, pp, pp, pp, DG]
         L.orc_dt.argtypes = [PP, pp, ctypes.c_double]
         L.orc_dt.restype = ctypes.c_double
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         L.orc_limiter_probe.argtypes = [PP, pp, ctypes.c_double, ctypes.c_int, ctypes.c_long, dp]
         L.orc_eval.argtypes = [PP, ctypes.c_int, dp, ctypes.c_long, dp, dp, dp, dp]
         L.orc_alpha_L.argtypes = [PP, ctypes.c_int, ctypes.c_double, ctypes.c_double]
@@ -129,6 +131,11 @@ def lib():
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_threads(n):
+    """Threads of the following oracle calls (timing only)."""
+    lib().orc_set_threads(int(n))
 
 
 def problem(spec, theta_mode="computed"):

@@ -1156,5 +1156,15 @@ int orc_num_threads(void)
 #endif
 }
 
+/* threads of the following oracle calls (n >= 1; timing only) */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_sizeof_problem(void) { return (int)sizeof(orc_problem); }
 int orc_sizeof_diag(void) { return (int)sizeof(orc_diag); }
