@@ -375,6 +375,26 @@ def test_table3_sign_pattern():
                 assert dmin < 0 and ref[0] < 0, (N, dmin)
 
 
+def test_table3_unlimited_extrema_match_the_printed_digits():
+    """Example 6.2 (Table 3) without limiting: SSP-RK(5,4) to T = 1, CFL 0.05,
+    from initial cell averages given by Simpson's rule on the initial point
+    values (reading R21), reproduces every printed discrete (min - u_min,
+    max - u_max) to its four printed digits, N = 20 ... 320.  Exact cell
+    averages instead differ from the table by 0.1-0.5%."""
+    g = golden("mpp_tables.json")["table3"]
+    u0 = lambda s: 1.0 + np.sin(2 * np.pi * s) ** 4
+    for i, N in enumerate(g["N"]):
+        spec = W.sin4_advection(N)[0]
+        xc, xr = (np.arange(N) + 0.5) / N, (np.arange(N) + 1.0) / N
+        U = [(u0(xr - 1.0 / N) + 4 * u0(xc) + u0(xr)) / 6, u0(xr)]
+        P = oracle.problem(dict(spec, limiter=False))
+        V, t, _ = oracle.run(P, U, cfl=0.05, t_end=1.0, integrator="ssprk54")
+        assert abs(t - 1.0) < 1e-12
+        got = (min(v.min() for v in V) - 1.0, max(v.max() for v in V) - 2.0)
+        for a, b in zip(got, g["without"][i]):
+            assert abs(a - b) <= 5e-4 * abs(b), (N, got, g["without"][i])
+
+
 @pytest.mark.parametrize("m", [2, 5])
 def test_table4_barenblatt_minimum(m):
     """Example 6.3 (Table 4), 2D: negative minimum without limiting, exactly
