@@ -379,6 +379,30 @@ def test_limiter_activity_fp32_and_validation():
     ctx.close()
 
 
+def test_table3_unlimited_extrema_on_the_gpu():
+    """The HIP path itself reproduces Example 6.2's printed unlimited
+    extrema (Table 3) to their four digits: FP64, SSP-RK(5,4) to T = 1 at
+    CFL 0.05 from Simpson-rule initial averages, N = 20 ... 320."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mpp_tables.json")))["table3"]
+    u0 = lambda s: 1.0 + np.sin(2 * np.pi * s) ** 4
+    for i, N in enumerate(g["N"]):
+        spec = dict(W.sin4_advection(N)[0], limiter=False, cfl=0.05)
+        xc, xr = (np.arange(N) + 0.5) / N, (np.arange(N) + 1.0) / N
+        U = [(u0(xr - 1.0 / N) + 4 * u0(xc) + u0(xr)) / 6, u0(xr)]
+        ctx = af.Context(spec, integrator="ssprk54")
+        ctx.set_state(0, U)
+        ctx.step(20 * N + 20, t_end=1.0)
+        V, t = ctx.get_state(0)
+        ctx.close()
+        got = (min(v.min() for v in V) - 1.0, max(v.max() for v in V) - 2.0)
+        note("table 3 N=%d t=%.15f got %s printed %s" % (N, t, got, g["without"][i]))
+        assert abs(t - 1.0) < 1e-12
+        for a, b in zip(got, g["without"][i]):
+            assert abs(a - b) <= 5e-4 * abs(b), (N, got, g["without"][i])
+
+
 def test_graph_equals_eager_and_checkpoint_resume():
     spec, U = W.config2(n=64)
     ctx = af.Context(spec)
