@@ -403,6 +403,33 @@ def test_table3_unlimited_extrema_on_the_gpu():
             assert abs(a - b) <= 5e-4 * abs(b), (N, got, g["without"][i])
 
 
+def test_table4_unlimited_minimum_on_the_gpu():
+    """The 2D path reproduces Example 6.3's printed unlimited minimum at T
+    (Table 4, m = 2, N = 80, t from 1 to 2, SSP-RK(5,4) at CFL 0.1, Simpson
+    initial averages) to its four digits, in FP64."""
+    import json
+    import os
+    t4 = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mpp_tables.json")))["table4"]
+    m, d, n, L = 2, 2, 80, 8.0
+    spec, U = W.barenblatt(d, m, n=n, t=1.0, sub=2, limiter=False)
+    dx = 2 * L / n
+    xc = -L + (np.arange(n) + 0.5) * dx
+    pts = lambda xo, yo: W.barenblatt_value(m, d, np.add.outer((xc + yo) ** 2, (xc + xo) ** 2), 1.0).reshape(-1)
+    w = {-1: 1.0, 0: 4.0, 1: 1.0}
+    U = [sum(w[a] * w[b] * pts(a * dx / 2, b * dx / 2) for a in (-1, 0, 1) for b in (-1, 0, 1)) / 36] + U[1:]
+    ctx = af.Context(dict(spec, cfl=0.1), integrator="ssprk54")
+    ctx.set_state(0, U, 1.0)
+    ctx.step(2000, t_end=2.0)
+    V, t = ctx.get_state(0)
+    name = ctx.variant_name(ctx.variant())
+    ctx.close()
+    got = min(v.min() for v in V)
+    ref = t4["2d"]["without"][t4["m"].index(m)]
+    note("table 4 m=%d on %s: t=%.15f min %.6e printed %.4e" % (m, name, t, got, ref))
+    assert abs(t - 2.0) < 1e-12
+    assert abs(got - ref) <= 5e-4 * abs(ref), (got, ref)
+
+
 def test_graph_equals_eager_and_checkpoint_resume():
     spec, U = W.config2(n=64)
     ctx = af.Context(spec)
