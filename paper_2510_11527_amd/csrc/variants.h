@@ -19,8 +19,11 @@ namespace af4 {
     X(6, 16, 16, 1, 256, 0, "generic-16x16") X(7, 32, 32, 1, 512, 4, "2d-own-32x32")
 // the tile variant whose generic kernel also has the limiter-counting form
 // (af_limiter_activity)
-constexpr int count_variant(int dim) { return dim == 2 ? 5 : 0; }
+constexpr int count_variant(int dim) { return dim == 2 ? 5 : dim == 3 ? 1 : 0; }
 
-#define AF4_VARIANTS_D3(X) X(0, 8, 8, 4, 256, "generic-8x8x4") X(1, 8, 4, 4, 128, "generic-8x4x4") X(2, 4, 4, 4, 64, "generic-4x4x4")
+// 3D: the 8x8x8 tile (less halo per cell, 125 KiB of LDS with SI blending in
+// FP32) does not fit in FP64, where the first built one, 8x8x4, is the default
+#define AF4_VARIANTS_D3(X) X(0, 8, 8, 8, 512, "generic-8x8x8") X(1, 8, 8, 4, 256, "generic-8x8x4") \
+    X(2, 8, 4, 4, 128, "generic-8x4x4") X(3, 4, 4, 4, 64, "generic-4x4x4")
 
 }  // namespace af4
