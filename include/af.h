@@ -179,6 +179,28 @@ af_status af_residual(af_ctx *ctx, int inst, double *const *rhs);
 /* Norms and diagnostics of instance inst, reduced on the device in FP64. */
 af_status af_norms(af_ctx *ctx, int inst, af_norms_t *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture aside -- this call synchronizes -- tight serving loops, harnesses
+ * that forbid hipMalloc): the norms of af_norms for a state held in the
+ * caller's device memory, with no allocation at all.  dofs points to one
+ * device block of (2^dim - 1) * kind_stride + n0*..*n_{dim-1} values of the
+ * given precision (32: float, 64: double): DoF kind z (zeta order, average
+ * first) at dofs + z * kind_stride, x fastest; kind_stride >= the number of
+ * cells.  lo/hi give the cell volume.  The work is enqueued on stream
+ * (hipStream_t, NULL: the null stream), which is then synchronized; out gets
+ * mass, min/max of averages and point values, l1/l2/linf of the averages and
+ * nonfinite, all reduced in FP64 exactly as af_norms does (same kernels, same
+ * order: bit-identical results on the same data); t, dt_last, steps and
+ * max_clamp are 0.  Scratch: the block partials live in a static device
+ * array of the library (17,424 bytes, one per GPU, held until the process
+ * ends; its size does not depend on the grid, so no grid is too large for
+ * it).  Calls that overlap on one GPU (other host threads, other streams)
+ * share that array and race; serialize them.  Errors: AF_ERR_ARG for a bad
+ * dim, precision, grid, pointer or kind_stride; AF_ERR_DEVICE if a HIP call
+ * fails (message in af_last_error(NULL)). */
+af_status af_norms_noalloc(int dim, int precision, const int *n, const double *lo, const double *hi, const void *dofs,
+                           long long kind_stride, void *stream, af_norms_t *out);
+
 /* Message of the last error of the context (or of af_create if ctx is NULL). */
 const char *af_last_error(const af_ctx *ctx);
 

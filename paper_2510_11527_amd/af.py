@@ -25,7 +25,7 @@ INTEGRATORS = {"ssprk3": 0, "euler": 1, "ssprk54": 2}
 
 EXPORTS = ["af_create", "af_destroy", "af_set_state", "af_get_state", "af_step", "af_residual", "af_norms",
            "af_last_error", "af_set_stream", "af_set_variant", "af_num_variants", "af_variant_name",
-           "af_step_timed", "af_work", "af_get_variant", "af_autotune", "af_limiter_activity"]
+           "af_step_timed", "af_work", "af_get_variant", "af_autotune", "af_limiter_activity", "af_norms_noalloc"]
 
 
 class AfProblem(ctypes.Structure):
@@ -95,6 +95,9 @@ def lib():
         L.af_work.argtypes = [vp, dp, dp, dp]
         L.af_autotune.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
         L.af_limiter_activity.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.af_norms_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp, dp, vp, ctypes.c_longlong, vp,
+                                       ctypes.POINTER(AfNorms)]
         for name in EXPORTS:
             if name not in ("af_last_error", "af_num_variants", "af_variant_name", "af_get_variant"):
                 getattr(L, name).restype = ctypes.c_int
@@ -270,3 +273,21 @@ class Context:
         b, c, d = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         self._check(lib().af_work(self.h, ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
         return {"bytes_per_stage": b.value, "cells": c.value, "dofs": d.value}
+
+
+def norms_noalloc(dim, precision, n, lo, hi, dofs_ptr, kind_stride, stream_ptr=None):
+    """af_norms_noalloc: norms of a state in caller device memory (one block,
+    DoF kind z at dofs_ptr + z * kind_stride values), computed without any
+    allocation.  dofs_ptr and stream_ptr are device addresses / a stream
+    handle as integers (e.g. a torch tensor's data_ptr() and a torch
+    stream's cuda_stream)."""
+    nn = (ctypes.c_int * 3)(*[int(v) for v in (list(n) + [1, 1, 1])[:3]])
+    ll = (ctypes.c_double * 3)(*[float(v) for v in (list(lo) + [0.0, 0.0, 0.0])[:3]])
+    hh = (ctypes.c_double * 3)(*[float(v) for v in (list(hi) + [1.0, 1.0, 1.0])[:3]])
+    out = AfNorms()
+    st = lib().af_norms_noalloc(int(dim), int(precision), nn, ll, hh, ctypes.c_void_p(int(dofs_ptr)),
+                                int(kind_stride), ctypes.c_void_p(stream_ptr or None), ctypes.byref(out))
+    if st != AF_OK:
+        raise AFError(st, lib().af_last_error(None).decode())
+    return out.as_dict()
+

@@ -32,18 +32,31 @@ def flags():
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def _compile(src):
+def _compile(src, incremental=False):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) >= max(
+            os.path.getmtime(os.path.join(CSRC, src)), _deps_header_mtime(src)):
+        return src, obj, 0, ""
     cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l and l.strip())
     return src, obj, r.returncode, out
 
 
-def build(verbose=True):
+def _deps_header_mtime(src):
+    """Latest modification time of the headers (every translation unit is
+    taken to include all of them)."""
+    files = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".h", ".hpp"))]
+    files.append(os.path.join(ROOT, "include", "af.h"))
+    return max(os.path.getmtime(f) for f in files)
+
+
+def build(verbose=True, incremental=False):
+    """Compile every translation unit and link libaf4.so.  incremental=True
+    skips units whose object is newer than the unit and every header."""
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
-        results = list(ex.map(_compile, SOURCES))
+        results = list(ex.map(lambda f: _compile(f, incremental), SOURCES))
     failed = [r for r in results if r[2] != 0]
     for src, _, rc, out in results:
         if out and (verbose or rc):
@@ -58,4 +71,4 @@ def build(verbose=True):
 
 
 if __name__ == "__main__":
-    print(build())
+    print(build(incremental="--incremental" in sys.argv))

@@ -1025,6 +1025,23 @@ af_status af_residual(af_ctx *c, int inst, double *const *rhs)
     return AF_OK;
 }
 
+// af_norms_t from the nine FP64 reductions of norms_launch (sum u, sum |u|,
+// sum u^2, max |u|, min / max average, min / max point value, non-finite
+// count) and the cell volume; time, step and clamp fields zero.
+static void norms_from_sums(const double *r, double vol, af_norms_t *out)
+{
+    std::memset(out, 0, sizeof *out);
+    out->mass = r[0] * vol;
+    out->l1_avg = r[1] * vol;
+    out->l2_avg = std::sqrt(r[2] * vol);
+    out->linf_avg = r[3];
+    out->min_avg = r[4];
+    out->max_avg = r[5];
+    out->min_pv = r[6];
+    out->max_pv = r[7];
+    out->nonfinite = r[8] > 0 ? 1 : 0;
+}
+
 af_status af_norms(af_ctx *c, int inst, af_norms_t *out)
 {
     if (!c || inst < 0 || inst >= c->n_inst || !out) return fail(c, AF_ERR_ARG, "af_norms: bad arguments");
@@ -1036,20 +1053,42 @@ af_status af_norms(af_ctx *c, int inst, af_norms_t *out)
     HIPOK(c, hipMemcpyAsync(r, c->d_nout, sizeof r, hipMemcpyDeviceToHost, c->stream));
     HIPOK(c, hipMemcpyAsync(&st, c->d_st + inst, sizeof st, hipMemcpyDeviceToHost, c->stream));
     HIPOK(c, hipStreamSynchronize(c->stream));
-    std::memset(out, 0, sizeof *out);
+    norms_from_sums(r, I.vol, out);
     out->t = st.t;
     out->dt_last = st.dt;
-    out->mass = r[0] * I.vol;
-    out->l1_avg = r[1] * I.vol;
-    out->l2_avg = std::sqrt(r[2] * I.vol);
-    out->linf_avg = r[3];
-    out->min_avg = r[4];
-    out->max_avg = r[5];
-    out->min_pv = r[6];
-    out->max_pv = r[7];
-    out->nonfinite = (r[8] > 0 || (st.flags & 1u)) ? 1 : 0;
+    if (st.flags & 1u) out->nonfinite = 1;
     out->max_clamp = __builtin_bit_cast(double, st.clampmax);
     out->steps = st.steps;
+    return AF_OK;
+}
+
+af_status af_norms_noalloc(int dim, int precision, const int *n, const double *lo, const double *hi, const void *dofs,
+                           long long kind_stride, void *stream, af_norms_t *out)
+{
+    if (dim < 1 || dim > 3 || (precision != 32 && precision != 64) || !n || !lo || !hi || !dofs || !out)
+        return fail(nullptr, AF_ERR_ARG, "af_norms_noalloc: bad arguments");
+    long long ncell = 1;
+    double vol = 1.0;
+    for (int l = 0; l < dim; l++) {
+        if (n[l] < 1 || !(hi[l] > lo[l])) return fail(nullptr, AF_ERR_ARG, "af_norms_noalloc: bad grid");
+        ncell *= n[l];
+        vol *= (hi[l] - lo[l]) / n[l];
+    }
+    // the kinds of the block must not overlap, and every index of the block
+    // must fit the kernels' 64-bit element indexing
+    const long long kinds = 1ll << dim;
+    if (kind_stride < ncell || kind_stride > (1ll << 56) / kinds)
+        return fail(nullptr, AF_ERR_ARG, "af_norms_noalloc: kind_stride must be at least the number of cells");
+    double *scr = nullptr;
+    hipError_t e = af4::noalloc_scratch(&scr);
+    if (e != hipSuccess) return fail(nullptr, AF_ERR_DEVICE, std::string("af_norms_noalloc: scratch: ") + hipGetErrorString(e));
+    hipStream_t s = (hipStream_t)stream;
+    double r[9];
+    e = af4::norms_launch(precision, dofs, ncell, kind_stride, (int)kinds, scr, scr + 9 * af4::kNormBlocks, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(r, scr + 9 * af4::kNormBlocks, sizeof r, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(nullptr, AF_ERR_DEVICE, std::string("af_norms_noalloc: ") + hipGetErrorString(e));
+    norms_from_sums(r, vol, out);
     return AF_OK;
 }
 

@@ -1,5 +1,6 @@
 // aux_kernels.hip -- time-step, norm and copy kernels of the AF library.
 #include <cfloat>
+#include <mutex>
 #include "launch.h"
 #include "stage_kernel.hpp"
 
@@ -351,6 +352,37 @@ hipError_t norms_launch(int prec, const void *block, long long ncell, long long 
                            kstride, nkinds, partials);
     hipLaunchKernelGGL(norms_final_kernel, dim3(1), dim3(64), 0, s, partials, kNormBlocks, out);
     return hipGetLastError();
+}
+
+// Scratch of the norms reduction for callers that cannot allocate
+// (af_norms_noalloc): the block partials, then the nine results.  Each GPU
+// holds its own copy until the process ends; every call on a GPU shares it.
+// In host code `scratch` names a host-side stand-in, never device memory:
+// only the address hipGetSymbolAddress returns for the current device is
+// passed to kernels.
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(double **ptr)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = (double *)p;
+    }
+    *ptr = g_scratch_dev[dev];
+    return hipSuccess;
 }
 
 }  // namespace af4

@@ -96,4 +96,10 @@ constexpr int kNormBlocks = 240;
 hipError_t norms_launch(int prec, const void *block, long long ncell, long long kstride, int nkinds, double *partials,
                         double *out, hipStream_t s);
 
+// Device address, on the current device, of the library's static scratch
+// array of kNoallocScratchDoubles doubles (the partials and results of
+// norms_launch), looked up once per device.
+constexpr int kNoallocScratchDoubles = 9 * kNormBlocks + 16;
+hipError_t noalloc_scratch(double **ptr);
+
 }  // namespace af4
