@@ -155,7 +155,7 @@ def rescale_free_fourier_1d(spec, phi, t, c=1.0, k0=0.01):
     return [decay * x for x in fourier_dofs(spec, [((1,), 1.0, phi - 2 * math.pi * c * t)])]
 
 
-def config2(seed=SEED_BASE + 2, n=512, cfl=0.075):
+def config2(seed=SEED_BASE + 2, n=512, cfl=0.05):
     """2D strongly degenerate Burgers, f = (u^2/2, u^2/2),
     a = 0.05 max(0, u - 0.25) (eps = 0.1 scale on kappa = 0.5 above 0.25),
     u0 = union of 12 axis-aligned periodic blocks painted in order."""
@@ -184,7 +184,7 @@ def config2(seed=SEED_BASE + 2, n=512, cfl=0.075):
     return spec, dofs
 
 
-def config3(seed=SEED_BASE + 3, n=1024, precision=64, cfl=0.075):
+def config3(seed=SEED_BASE + 3, n=1024, precision=64, cfl=0.05):
     """2D Buckley-Leverett with gravity on [-1.5,1.5]^2, kappa = 0.04 u(1-u),
     u0 = 1 inside a union of 5 disks (minimum-image distance), else 0."""
     rng = np.random.default_rng(seed)
@@ -225,7 +225,7 @@ def _modes(rng, nmodes, d):
     return out
 
 
-def config4(seed=SEED_BASE + 4, n_inst=256, sizes=(64, 128, 256, 512), cfl=0.075, steps=200,
+def config4(seed=SEED_BASE + 4, n_inst=256, sizes=(64, 128, 256, 512), cfl=0.05, steps=200,
             with_dofs=True, limiter=True):
     """Batch of independent 2D porous-medium/Burgers instances of uneven
     size: f = (u^2/2, u^2/2), a = c u^m, u0 = random 8-mode Fourier sum
@@ -256,7 +256,7 @@ def config4_dofs(spec):
     return dofs
 
 
-def config5(seed=SEED_BASE + 5, n=256, cfl=0.05, steps=100):
+def config5(seed=SEED_BASE + 5, n=256, cfl=0.03, steps=100):
     """3D degenerate convection-diffusion, f = (u^2/2)x3,
     kappa = 0.1 max(0, u - 0.3), u0 = 6-mode Fourier sum rescaled to [0,1];
     FP32, limiter and smoothness-indicator blending (gamma = 1)."""

@@ -1268,3 +1268,227 @@ def test_open_x_ends_2d_y_reflection_symmetry():
     RR = oracle.rhs(mk(-0.7), [cell(U[0]), cell(U[1]), face(U[2]), face(U[3])])
     for got, want in zip(RR, [cell(R[0]), cell(R[1]), face(R[2]), face(R[3])]):
         np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# P17: the semi-discrete right-hand side written out from the printed
+# operators (numpy, FP64), nonlinear fluxes, tiny grids
+# ---------------------------------------------------------------------------
+
+def _flux_funcs(kind):
+    if kind == "quad":     # Burgers f = u^2 / 2
+        return (lambda u: 0.5 * u * u), (lambda u: np.abs(u))
+    # Buckley-Leverett f = u^2 / (u^2 + (1 - u)^2)
+    f = lambda u: u * u / (u * u + (1 - u) ** 2)
+    df = lambda u: np.abs(2 * u * (1 - u) / (u * u + (1 - u) ** 2) ** 2)
+    return f, df
+
+
+def _pv_rhs_line(z, f, df, a, h2, alpha_points=5):
+    """Right-hand side along one half-grid line at the centre point of the
+    five values z[0..4] (spacing dx/2): -(D+ f^+ + D- f^-) + D^{2,4th} a with
+    f^+- = (f +- alpha z)/2, alpha = max |f'| over the five points (Sec. 2.1,
+    Eqs. 1d_upwind_ops_4p/4m, 1d_diff_compact_a); h2 = dx.  alpha_points < 5
+    drops the far downwind points (a planted mistake)."""
+    alpha = max(df(v) for v in z[:alpha_points])
+    fp = [0.5 * (f(v) + alpha * v) for v in z]
+    fm = [0.5 * (f(v) - alpha * v) for v in z]
+    Dp = (fp[0] - 6 * fp[1] + 3 * fp[2] + 2 * fp[3]) / (3 * h2)
+    Dm = (-2 * fm[1] - 3 * fm[2] + 6 * fm[3] - fm[4]) / (3 * h2)
+    av = [a(v) for v in z]
+    D2 = (-av[0] / 3 + 16 * av[1] / 3 - 10 * av[2] + 16 * av[3] / 3 - av[4] / 3) / (h2 * h2)
+    return -(Dp + Dm) + D2
+
+
+def _rhs_1d_written_out(ub, up, dx, f, df, a, alpha_points=5):
+    N = ub.size
+    H = np.empty(2 * N)
+    H[1::2] = up
+    H[0::2] = (6 * ub - np.roll(up, 1) - up) / 4          # Simpson centre, Sec. 2.1
+    Rp = np.empty(N)
+    for i in range(N):
+        p = 2 * i + 1
+        Rp[i] = _pv_rhs_line([H[(p + s) % (2 * N)] for s in range(-2, 3)], f, df, a, dx, alpha_points)
+    # averages, Eq. (1d_af_av_dc): f(u_{i+1/2}) and D_c a at the faces
+    aH = lambda p: a(H[p % (2 * N)])
+    Dc = np.array([(aH(2 * i - 1) - 8 * aH(2 * i) + 8 * aH(2 * i + 2) - aH(2 * i + 3)) / (6 * dx) for i in range(N)])
+    F = f(up)
+    Ra = -(F - np.roll(F, 1)) / dx + (Dc - np.roll(Dc, 1)) / dx
+    return [Ra, Rp]
+
+
+def _rhs_2d_written_out(U, n, dx, fl, a, alpha_points=5):
+    nx, ny = n
+    A, X, Y, C = (np.asarray(u).reshape(ny, nx) for u in U)
+    H = np.empty((2 * ny, 2 * nx))                          # H[q, p]: x half index p, y half index q
+    H[0::2, 1::2] = X
+    H[1::2, 0::2] = Y
+    H[1::2, 1::2] = C
+    Xm = np.roll(X, 1, axis=1)
+    Ym = np.roll(Y, 1, axis=0)
+    Cxm = np.roll(C, 1, axis=1)
+    Cym = np.roll(C, 1, axis=0)
+    Cmm = np.roll(Cxm, 1, axis=0)
+    H[0::2, 0::2] = (36 * A - 4 * (Xm + X + Ym + Y) - (Cmm + Cym + Cxm + C)) / 16   # centre, Sec. 4
+    g = lambda q, p: H[q % (2 * ny), p % (2 * nx)]
+    R = [np.zeros((ny, nx)) for _ in range(4)]
+    for k, (oq, op) in enumerate([(0, 1), (1, 0), (1, 1)], start=1):
+        for j in range(ny):
+            for i in range(nx):
+                q, p = 2 * j + oq, 2 * i + op
+                r = 0.0
+                for l in range(2):
+                    f, df = fl[l]
+                    line = [g(q, p + s) if l == 0 else g(q + s, p) for s in range(-2, 3)]
+                    r += _pv_rhs_line(line, f, df, a, dx[l], alpha_points)
+                R[k][j, i] = r
+    # averages: Simpson face averages of f_l and of D_c^{(l)} a (Sec. 4)
+    for j in range(ny):
+        for i in range(nx):
+            tot = 0.0
+            for l in range(2):
+                f = fl[l][0]
+                for side, sgn in ((0, -1.0), (1, 1.0)):
+                    fs, ds = 0.0, 0.0
+                    for t, w in ((-1, 1.0), (0, 4.0), (1, 1.0)):
+                        if l == 0:
+                            q, p = 2 * j + t, 2 * i - 1 + 2 * side
+                            line = [a(g(q, p - 2)), a(g(q, p - 1)), a(g(q, p + 1)), a(g(q, p + 2))]
+                        else:
+                            q, p = 2 * j - 1 + 2 * side, 2 * i + t
+                            line = [a(g(q - 2, p)), a(g(q - 1, p)), a(g(q + 1, p)), a(g(q + 2, p))]
+                        fs += w * f(g(q, p))
+                        ds += w * (line[0] - 8 * line[1] + 8 * line[2] - line[3]) / (6 * dx[l])
+                    tot += sgn * (-fs / 6 + ds / 6) / dx[l]
+            R[0][j, i] = tot
+    return [r.reshape(-1) for r in R]
+
+
+@pytest.mark.parametrize("kind", ["quad", "bl"])
+def test_rhs_written_out_from_the_printed_operators_1d(kind):
+    """P17 (1D): the oracle's right-hand side equals the printed operators
+    written out in numpy -- Simpson centre, alpha = max |f'| over the whole
+    five-point stencil, the LLF splitting, D+ and D- as printed, the compact
+    D^{2,4th}, f(u_{i+1/2}) and D_c a at the faces -- for a nonlinear flux
+    and potential on random data, N = 7.  Alpha taken over four points (the
+    far downwind one dropped) does not match."""
+    rng = np.random.default_rng(17 + (kind == "bl"))
+    N, L = 7, 1.3
+    f, df = _flux_funcs(kind)
+    a = lambda u: 0.07 * u ** 2
+    U = [rng.uniform(0.05, 0.95, N) for _ in range(2)]
+    spec = spec1d(N, L, (kind, 0.5 if kind == "quad" else 0.0), ("power", 0.07, 2.0))
+    Ro = oracle.rhs(oracle.problem(spec), U)
+    Rn = _rhs_1d_written_out(U[0], U[1], L / N, f, df, a)
+    scale = max(np.abs(r).max() for r in Rn)
+    for x, y in zip(Ro, Rn):
+        assert np.max(np.abs(x - y)) <= 1e-13 * scale
+    R4 = _rhs_1d_written_out(U[0], U[1], L / N, f, df, a, alpha_points=4)
+    assert np.max(np.abs(Ro[1] - R4[1])) > 1e-6 * scale
+
+
+@pytest.mark.parametrize("kind", ["quad", "bl"])
+def test_rhs_written_out_from_the_printed_operators_2d(kind):
+    """P17 (2D): the same on a 4 x 5 grid with unequal spacings -- the
+    printed 2D centre formula, the x- and y-operators along half-grid lines,
+    Simpson face averages of f_l and of D_c^{(l)} a -- and the four-point
+    alpha does not match."""
+    rng = np.random.default_rng(27 + (kind == "bl"))
+    n, hi = (4, 5), (1.0, 1.4)
+    f, df = _flux_funcs(kind)
+    a = lambda u: 0.05 * u ** 2
+    spec = dict(dim=2, n=list(n), lo=[0.0, 0.0], hi=list(hi),
+                flux=[(kind, 0.5 if kind == "quad" else 0.0, 0.0)] * 2, diff=("power", 0.05, 2.0),
+                umin=-1e3, umax=1e3)
+    U = [rng.uniform(0.05, 0.95, n[0] * n[1]) for _ in range(4)]
+    Ro = oracle.rhs(oracle.problem(spec), U)
+    dx = (hi[0] / n[0], hi[1] / n[1])
+    Rn = _rhs_2d_written_out(U, n, dx, [(f, df), (f, df)], a)
+    scale = max(np.abs(r).max() for r in Rn)
+    for x, y in zip(Ro, Rn):
+        assert np.max(np.abs(x - y)) <= 1e-13 * scale
+    R4 = _rhs_2d_written_out(U, n, dx, [(f, df), (f, df)], a, alpha_points=4)
+    assert max(np.max(np.abs(x - y)) for x, y in zip(Ro[1:], R4[1:])) > 1e-6 * scale
+
+
+def test_ssprk54_nonlinear_order_four():
+    """SSP-RK(5,4) is fourth order on a nonlinear problem, not only on the
+    linear one its stability polynomial pins: smooth Burgers with linear
+    diffusion on a fixed 64-cell grid, unlimited, to T = 0.1 with dt = T/M
+    against M = 1280; the error ratios under halving dt give rates >= 3.7.
+    The same test separates a third-order integrator: SSP-RK3 gives rates
+    <= 3.2 there."""
+    N = 64
+    spec = dict(dim=1, n=[N], lo=[0.0], hi=[1.0], flux=[("quad", 0.5, 0.0)], diff=("linear", 0.01, 0.0),
+                umin=-1e3, umax=1e3, limiter=False)
+    U = [1.0 + x for x in W.fourier_dofs(spec, [((1,), 0.5, 0.3), ((2,), 0.2, 1.0)])]
+    P = oracle.problem(spec)
+    T = 0.1
+
+    def rates(integ, Ms):
+        ref, _, _ = oracle.run(P, U, dts=[T / 1280] * 1280, integrator=integ)
+        es = []
+        for M in Ms:
+            V, _, _ = oracle.run(P, U, dts=[T / M] * M, integrator=integ)
+            es.append(max(np.abs(a - b).max() for a, b in zip(V, ref)))
+        return [math.log2(es[i] / es[i + 1]) for i in range(len(es) - 1)]
+
+    r54 = rates("ssprk54", [20, 40, 80])
+    assert min(r54) >= 3.7, r54
+    r3 = rates("ssprk3", [40, 80, 160])
+    assert max(r3) <= 3.2, r3
+
+
+def _operator_matrix(d, N, kappa, cvel):
+    """The oracle's unlimited semi-discrete operator for f_l = cvel u,
+    a = kappa u on N^d periodic cells, as a matrix (one right-hand side per
+    unit DoF)."""
+    spec = dict(dim=d, n=[N] * d, lo=[0.0] * d, hi=[1.0] * d, flux=[("linear", cvel, 0.0)] * d,
+                diff=("linear", kappa, 0.0), umin=-1e9, umax=1e9, limiter=False)
+    P = oracle.problem(spec)
+    nc, nb = N ** d, 2 ** d
+    M = np.zeros((nb * nc, nb * nc))
+    for col in range(nb * nc):
+        U = [np.zeros(nc) for _ in range(nb)]
+        U[col // nc][col % nc] = 1.0
+        M[:, col] = np.concatenate(oracle.rhs(P, U))
+    return M
+
+
+def _max_stable_cfl(lam, R):
+    lo, hi = 0.0, 2.0
+    for _ in range(50):
+        c = 0.5 * (lo + hi)
+        if np.max(np.abs(R(c * lam))) <= 1 + 1e-12:
+            lo = c
+        else:
+            hi = c
+    return lo
+
+
+def test_multid_diffusion_stability_limits_and_workload_cfls():
+    """Linear stability of the 2D and 3D operators (Sec. 4) under the CFL
+    step of Eq. (multid_av_pp_dt), which takes the maximum over directions.
+    The spectrum of pure diffusion reaches -16/dx^2 in 1D (Table 1's SSP-RK3
+    limit 0.157 follows), but -40.78/dx^2 in 2D and -63.33/dx^2 in 3D: the
+    spatially uniform mode with zero averages and point values of alternating
+    sign across the half grid couples the directions through the
+    reconstructed centres.  So the pure-diffusion limits are 0.0616 (2D) and
+    0.0397 (3D) for SSP-RK3 and 0.131 / 0.084 for SSP-RK(5,4), below 1/d
+    times the 1D values.  The diffusion-dominated workloads run at
+    C = 0.05 (2D) and 0.03 (3D), inside them; Peclet 1 mixtures allow more."""
+    R3 = lambda z: 1 + z + z * z / 2 + z ** 3 / 6
+    eta = 0.004477718303076
+    R54 = lambda z: 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24 + eta * z ** 5
+    lim = {}
+    for d, N in ((1, 16), (2, 8), (3, 4)):
+        dx = 1.0 / N
+        lam = np.linalg.eigvals(_operator_matrix(d, N, 1.0, 0.0)) * dx * dx
+        lim[d] = (_max_stable_cfl(lam, R3), _max_stable_cfl(lam, R54), lam.real.min())
+    assert abs(lim[1][0] - 0.157) < 5e-4 and abs(lim[1][1] - 0.333) < 5e-4 and abs(lim[1][2] + 16) < 1e-9
+    assert abs(lim[2][2] + 40.777) < 1e-3 and abs(lim[3][2] + 63.335) < 1e-3
+    assert abs(lim[2][0] - 0.0616) < 1e-4 and abs(lim[3][0] - 0.0397) < 1e-4
+    assert abs(lim[2][1] - 0.1308) < 1e-3 and abs(lim[3][1] - 0.0842) < 1e-3
+    for spec, _ in (W.config2(n=16), W.config3(n=16), W.config4(n_inst=1, sizes=(16,))[0]):
+        assert spec["cfl"] <= 0.85 * lim[2][0], spec["cfl"]
+    assert W.config5(n=8)[0]["cfl"] <= 0.85 * lim[3][0]
