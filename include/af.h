@@ -5,9 +5,10 @@
  *
  *     u_t + div f(u) = Lap a(u),   a(u) = int kappa,  kappa >= 0,
  *
- * on periodic uniform Cartesian meshes in 1, 2 or 3 dimensions
- * (J. Duan, arXiv 2510.11527; the PDE is Eq. (cde_conservative), the
- * periodic maximum principle [u_min, u_max] is stated in Sec. 1).
+ * on uniform Cartesian meshes in 1, 2 or 3 dimensions, periodic or (1D, 2D)
+ * with Dirichlet or outflow ends (J. Duan, arXiv 2510.11527; the PDE is
+ * Eq. (cde_conservative), the maximum principle [u_min, u_max] is stated in
+ * Sec. 1 and its discrete form, for averages and point values, in Def. 5.1).
  *
  * Every call returns an af_status; no C++ exception crosses this boundary.
  * All host buffers are owned by the caller and copied by the library; the
@@ -152,10 +153,15 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out);
 af_status af_destroy(af_ctx *ctx);
 
 /* Copies the state of instance inst from the host: dofs[0..2^d-1] point to
- * n0*n1*n2 doubles each, in zeta order.  FP32 contexts round to nearest.
- * Validates before mutating: non-finite -> AF_ERR_NONFINITE; with the
- * limiter, a value outside [umin, umax] -> AF_ERR_BOUNDS.  If umin/umax were
- * NaN at creation they are set here, once, from the (rounded) DoFs. */
+ * n0*n1*n2 doubles each, in zeta order (the DoFs of Sec. 2 and Sec. 4: cell
+ * averages and the point values shared by neighbouring cells).  FP32
+ * contexts round to nearest.  Validates before mutating: non-finite ->
+ * AF_ERR_NONFINITE; with the limiter, a (rounded) value outside [umin, umax]
+ * -> AF_ERR_BOUNDS, since the MPP property of Def. 5.1 starts from DoFs
+ * inside the bounds.  If umin/umax were NaN at creation they are set here,
+ * once, to the min/max of the (rounded) DoFs and Dirichlet values -- the
+ * discrete form of the bounds of the initial data (Sec. 1).  In FP32 the
+ * kernels clamp and limit against the nearest floats inside [umin, umax]. */
 af_status af_set_state(af_ctx *ctx, int inst, const double *const *dofs, double t);
 
 /* Copies the state of instance inst to the host (widened to double). */
@@ -176,7 +182,14 @@ af_status af_step(af_ctx *ctx, int nsteps, double t_end, const double *dt_prescr
  * blending (Eq. (2d_af_dc); Eq. (1d_af_dc) in 1D), to rhs[0..2^d-1]. */
 af_status af_residual(af_ctx *ctx, int inst, double *const *rhs);
 
-/* Norms and diagnostics of instance inst, reduced on the device in FP64. */
+/* Norms and diagnostics of instance inst, reduced on the device in FP64
+ * over the stored DoFs: the mass (sum of averages times the cell volume,
+ * conserved to round-off by the locally and doubly conservative updates of
+ * Props 5.1/5.2 on periodic meshes), min/max of the averages and of the point
+ * values (the bounds of Def. 5.1), the l1/l2/linf norms of the averages, the
+ * time, last step and step count, the largest safeguard clamp and a
+ * non-finite flag.  Sums are reduced in a fixed order (bitwise
+ * reproducible).  Synchronizes the context stream. */
 af_status af_norms(af_ctx *ctx, int inst, af_norms_t *out);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -259,6 +272,15 @@ af_status af_limiter_activity(af_ctx *ctx, int inst, long long *counts);
  * the stages of one step: (2 + 1 for stages that read U^n) * 2^d * cells *
  * value size.  Grid cells and DoFs of the context in *cells, *dofs. */
 af_status af_work(const af_ctx *ctx, double *bytes_per_stage, double *cells, double *dofs);
+
+/* Attainable-bandwidth reference for the roofline: times reps launches of a
+ * streaming copy (16-byte elements) of `bytes` bytes between two buffers it
+ * allocates on the current device and frees before returning, with HIP
+ * events on a stream of its own, and returns the rate counting every byte
+ * read and written, in GB/s (1e9 bytes per second).  AF_ERR_ARG for
+ * bytes < 16, reps < 1 or a NULL result; AF_ERR_ALLOC if the buffers do not
+ * fit; AF_ERR_DEVICE if a HIP call fails (message in af_last_error(NULL)). */
+af_status af_copy_rate(long long bytes, int reps, double *gb_per_s);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,7 @@ INTEGRATORS = {"ssprk3": 0, "euler": 1, "ssprk54": 2}
 
 EXPORTS = ["af_create", "af_destroy", "af_set_state", "af_get_state", "af_step", "af_residual", "af_norms",
            "af_last_error", "af_set_stream", "af_set_variant", "af_num_variants", "af_variant_name",
-           "af_step_timed", "af_work", "af_get_variant", "af_autotune", "af_limiter_activity", "af_norms_noalloc"]
+           "af_step_timed", "af_work", "af_get_variant", "af_autotune", "af_limiter_activity", "af_norms_noalloc", "af_copy_rate"]
 
 
 class AfProblem(ctypes.Structure):
@@ -98,6 +98,7 @@ def lib():
         ip = ctypes.POINTER(ctypes.c_int)
         L.af_norms_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp, dp, vp, ctypes.c_longlong, vp,
                                        ctypes.POINTER(AfNorms)]
+        L.af_copy_rate.argtypes = [ctypes.c_longlong, ctypes.c_int, dp]
         for name in EXPORTS:
             if name not in ("af_last_error", "af_num_variants", "af_variant_name", "af_get_variant"):
                 getattr(L, name).restype = ctypes.c_int
@@ -290,4 +291,13 @@ def norms_noalloc(dim, precision, n, lo, hi, dofs_ptr, kind_stride, stream_ptr=N
     if st != AF_OK:
         raise AFError(st, lib().af_last_error(None).decode())
     return out.as_dict()
+
+
+def copy_rate(nbytes=1 << 30, reps=20):
+    """af_copy_rate: GB/s of a streaming device copy (read + write bytes)."""
+    r = ctypes.c_double()
+    st = lib().af_copy_rate(int(nbytes), int(reps), ctypes.byref(r))
+    if st != AF_OK:
+        raise AFError(st, lib().af_last_error(None).decode())
+    return r.value
 

@@ -148,12 +148,29 @@ double host_kappa_max(int kind, double p0, double p1, double lo, double hi)
     return 0.0;
 }
 
+// Bounds as FP32 values inside [umin, umax]: the nearest float at or above
+// umin, at or below umax, so that FP32 clamps and limiter gaps never admit a
+// value outside the FP64 bounds (a bound without an exact FP32 value would
+// otherwise round outwards half the time).
+float f32_at_least(double v)
+{
+    float f = (float)v;
+    if ((double)f < v) f = std::nextafter(f, std::numeric_limits<float>::infinity());
+    return f;
+}
+float f32_at_most(double v)
+{
+    float f = (float)v;
+    if ((double)f > v) f = std::nextafter(f, -std::numeric_limits<float>::infinity());
+    return f;
+}
+
 // FP32 copies of the parameters the FP32 kernels read (rounded to nearest,
-// as a device-side conversion would).
+// as a device-side conversion would; the bounds rounded inwards).
 void set_f32_params(InstDev &I)
 {
-    I.f_umin = (float)I.umin;
-    I.f_umax = (float)I.umax;
+    I.f_umin = f32_at_least(I.umin);
+    I.f_umax = f32_at_most(I.umax);
     I.f_pc[0] = (float)I.pc1;
     I.f_pc[1] = (float)I.pc2;
     I.f_pc[2] = (float)I.pc3;
@@ -1089,6 +1106,42 @@ af_status af_norms_noalloc(int dim, int precision, const int *n, const double *l
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(nullptr, AF_ERR_DEVICE, std::string("af_norms_noalloc: ") + hipGetErrorString(e));
     norms_from_sums(r, vol, out);
+    return AF_OK;
+}
+
+af_status af_copy_rate(long long bytes, int reps, double *gb_per_s)
+{
+    if (bytes < 16 || reps < 1 || !gb_per_s) return fail(nullptr, AF_ERR_ARG, "af_copy_rate: bad arguments");
+    const long long n16 = bytes / 16;
+    void *a = nullptr, *b = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&a, n16 * 16);
+    if (e == hipSuccess) e = hipMalloc(&b, n16 * 16);
+    if (e != hipSuccess) {
+        if (a) (void)hipFree(a);
+        (void)hipGetLastError();
+        return fail(nullptr, AF_ERR_ALLOC, "af_copy_rate: buffers");
+    }
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipMemsetAsync(a, 0, n16 * 16, s);
+    if (e == hipSuccess) e = af4::copy16_launch(a, b, n16, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; r++) e = af4::copy16_launch(a, b, n16, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    const std::string msg = e != hipSuccess ? std::string("af_copy_rate: ") + hipGetErrorString(e) : "";
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    if (e != hipSuccess) return fail(nullptr, AF_ERR_DEVICE, msg);
+    *gb_per_s = 2.0 * (double)n16 * 16.0 * reps / (ms * 1e-3) / 1e9;
     return AF_OK;
 }
 

@@ -239,19 +239,31 @@ __global__ void copy_kernel(const T *__restrict__ src, T *__restrict__ dst, long
 }
 
 // Block partials in fixed order, then one block reduces them in fixed order:
-// the result is bitwise reproducible.
+// the result is bitwise reproducible.  The three sums are compensated
+// (Neumaier) in each thread's loop, in the block's pairwise tree and in the
+// final pass over the block partials, so their rounding stays within a few
+// units in the last place of the sum of magnitudes whatever the grid size.
+__device__ __forceinline__ void neumaier_add(double &s, double &c, double v)
+{
+    const double t = s + v;
+    c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
+    s = t;
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) norms_kernel(const T *block, long long ncell, long long kstride, int nkinds,
                                                     double *partials)
 {
     __shared__ double sh[9][256];
-    double s1 = 0, sa = 0, s2 = 0, mx = 0, amin = DBL_MAX, amax = -DBL_MAX, pmin = DBL_MAX, pmax = -DBL_MAX, nbad = 0;
+    __shared__ double shc[3][256];  // compensations of the three sums
+    double s1 = 0, sa = 0, s2 = 0, c1 = 0, ca = 0, c2 = 0;
+    double mx = 0, amin = DBL_MAX, amax = -DBL_MAX, pmin = DBL_MAX, pmax = -DBL_MAX, nbad = 0;
     for (long long c = threadIdx.x + (long long)blockIdx.x * 256; c < ncell; c += (long long)gridDim.x * 256) {
         const double u = (double)block[c];
         if (!isfinite(u)) nbad += 1;
-        s1 += u;
-        sa += fabs(u);
-        s2 += u * u;
+        neumaier_add(s1, c1, u);
+        neumaier_add(sa, ca, fabs(u));
+        neumaier_add(s2, c2, u * u);
         mx = fmax(mx, fabs(u));
         amin = fmin(amin, u);
         amax = fmax(amax, u);
@@ -264,13 +276,18 @@ __global__ void __launch_bounds__(256) norms_kernel(const T *block, long long nc
     }
     double vals[9] = {s1, sa, s2, mx, amin, amax, pmin, pmax, nbad};
     for (int q = 0; q < 9; q++) sh[q][threadIdx.x] = vals[q];
+    shc[0][threadIdx.x] = c1;
+    shc[1][threadIdx.x] = ca;
+    shc[2][threadIdx.x] = c2;
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
         if ((int)threadIdx.x < w) {
             const int t = threadIdx.x;
-            sh[0][t] += sh[0][t + w];
-            sh[1][t] += sh[1][t + w];
-            sh[2][t] += sh[2][t + w];
+#pragma unroll
+            for (int q = 0; q < 3; q++) {
+                neumaier_add(sh[q][t], shc[q][t], sh[q][t + w]);
+                shc[q][t] += shc[q][t + w];
+            }
             sh[3][t] = fmax(sh[3][t], sh[3][t + w]);
             sh[4][t] = fmin(sh[4][t], sh[4][t + w]);
             sh[5][t] = fmax(sh[5][t], sh[5][t + w]);
@@ -280,18 +297,19 @@ __global__ void __launch_bounds__(256) norms_kernel(const T *block, long long nc
         }
         __syncthreads();
     }
-    if (threadIdx.x < 9) partials[blockIdx.x * 9 + threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x < 9) partials[blockIdx.x * 9 + threadIdx.x] = sh[threadIdx.x][0] + (threadIdx.x < 3 ? shc[threadIdx.x][0] : 0.0);
 }
 
 __global__ void norms_final_kernel(const double *partials, int nblocks, double *out)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double r[9] = {0, 0, 0, 0, DBL_MAX, -DBL_MAX, DBL_MAX, -DBL_MAX, 0};
+    double c[3] = {0, 0, 0};
     for (int b = 0; b < nblocks; b++) {
         const double *p = partials + 9 * b;
-        r[0] += p[0];
-        r[1] += p[1];
-        r[2] += p[2];
+        neumaier_add(r[0], c[0], p[0]);
+        neumaier_add(r[1], c[1], p[1]);
+        neumaier_add(r[2], c[2], p[2]);
         r[3] = fmax(r[3], p[3]);
         r[4] = fmin(r[4], p[4]);
         r[5] = fmax(r[5], p[5]);
@@ -299,6 +317,7 @@ __global__ void norms_final_kernel(const double *partials, int nblocks, double *
         r[7] = fmax(r[7], p[7]);
         r[8] += p[8];
     }
+    for (int q = 0; q < 3; q++) r[q] += c[q];
     for (int q = 0; q < 9; q++) out[q] = r[q];
 }
 
@@ -325,6 +344,23 @@ hipError_t finalize_launch(int n_inst, const InstDev *inst, const StepCtl *ctl, 
     else
         hipLaunchKernelGGL(finalize_kernel<256>, dim3(n_inst), dim3(256), 0, s, inst, ctl, dtp, st, dim, prec, mm,
                            waves_per_block);
+    return hipGetLastError();
+}
+
+// Streaming copy of 16-byte elements: the attainable-bandwidth reference the
+// stage kernels are compared with (every byte read once and written once).
+__global__ void __launch_bounds__(256) copy16_kernel(const float4 *__restrict__ src, float4 *__restrict__ dst,
+                                                     long long n)
+{
+    for (long long i = threadIdx.x + (long long)blockIdx.x * 256; i < n; i += (long long)gridDim.x * 256)
+        dst[i] = src[i];
+}
+
+hipError_t copy16_launch(const void *src, void *dst, long long n16, hipStream_t s)
+{
+    const long long want = (n16 + 255) / 256;
+    const int blocks = (int)(want < 8192 ? (want > 0 ? want : 1) : 8192);
+    hipLaunchKernelGGL(copy16_kernel, dim3(blocks), dim3(256), 0, s, (const float4 *)src, (float4 *)dst, n16);
     return hipGetLastError();
 }
 

@@ -89,6 +89,8 @@ hipError_t finalize_launch(int n_inst, const InstDev *inst, const StepCtl *ctl, 
 
 // dst = src over n values.
 hipError_t copy_launch(int prec, const void *src, void *dst, long long n, hipStream_t s);
+// dst = src over n16 16-byte elements (the copy-bandwidth reference).
+hipError_t copy16_launch(const void *src, void *dst, long long n16, hipStream_t s);
 
 // FP64 norms of one instance: out[0..9] = sum u, sum |u|, sum u^2, max |u|,
 // min avg, max avg, min pv, max pv, nonfinite count, (unused).

@@ -109,8 +109,14 @@ struct Phys {
         ppow = I.ppow != 0;
         a0 = (T)I.ap0;
         a1 = (T)I.ap1;
-        umin = (T)I.umin;
-        umax = (T)I.umax;
+        // FP32: the bounds rounded inwards on the host
+        if constexpr (sizeof(T) == 4) {
+            umin = I.f_umin;
+            umax = I.f_umax;
+        } else {
+            umin = I.umin;
+            umax = I.umax;
+        }
     }
 
     // f_l(u)

@@ -521,3 +521,33 @@ def test_cfl_from_last_stage_minmax_equals_wave_speed_pass(name, integ):
             assert np.array_equal(x, y)
     a.close()
     b.close()
+
+
+def test_fp32_bounds_without_an_exact_float_hold_exactly():
+    """Bounds [0.7, 1.1] have no exact FP32 values and round outwards to
+    nearest; the FP32 kernels clamp and limit against the nearest floats
+    inside them, so every DoF stays inside the FP64 bounds the context was
+    given, and the run still matches the oracle."""
+    spec, U = W.config4(n_inst=1, sizes=(48,))[0]
+    lo, hi = 0.7, 1.1
+    flo = np.nextafter(np.float32(lo), np.float32(1)) if float(np.float32(lo)) < lo else np.float32(lo)
+    fhi = np.nextafter(np.float32(hi), np.float32(-1)) if float(np.float32(hi)) > hi else np.float32(hi)
+    assert float(np.float32(lo)) < lo and float(np.float32(hi)) > hi   # both round outwards
+    U = [np.clip(np.float32(lo + (hi - lo) * u), flo, fhi).astype(np.float64) for u in U]
+    s = dict(spec, umin=lo, umax=hi, precision=32)
+    P = oracle.problem(s)
+    Uo, t, dts = oracle.run(P, U, nsteps=20, cfl=s["cfl"])
+    V, tg, used, nrm = gpu_run(s, U, dts=dts)
+    note("fp32 bounds: min %.10g max %.10g" % (min(v.min() for v in V), max(v.max() for v in V)))
+    assert min(v.min() for v in V) >= lo and max(v.max() for v in V) <= hi
+    assert nrm["min_avg"] >= lo and nrm["max_avg"] <= hi and nrm["min_pv"] >= lo and nrm["max_pv"] <= hi
+    check(V, Uo, 32, 3 * len(dts), "fp32 bounds")
+
+
+def test_copy_rate_reference():
+    """af_copy_rate, the attainable-bandwidth reference of the roofline: a
+    plausible HBM rate (above 1 TB/s, not above the 8 TB/s peak by more than
+    timing noise) for a 1 GiB streaming copy."""
+    r = af.copy_rate(1 << 30, 10)
+    note("copy rate %.1f GB/s" % r)
+    assert 1000.0 < r < 8400.0
