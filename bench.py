@@ -109,6 +109,18 @@ def make_ctx(items, precision=None, variant=None, integrator="ssprk3"):
 STAGES = {"ssprk3": 3, "ssprk54": 5, "euler": 1}
 
 
+def cpu_model():
+    """Host CPU model name (first processor of /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(items, target_cells, integrator="ssprk3"):
     """The FP64 oracle on a bounded sample, on all host cores: the first
     instances of the same workload up to target_cells cells, one SSP-RK3 step
@@ -156,37 +168,121 @@ def cpu_baseline(items, target_cells, integrator="ssprk3"):
     oracle.fe_cells(P0, U0, dt0, np.arange(k))
     el1 = time.perf_counter() - t1
     oracle.set_threads(cores)
-    return {"value": value, "unit": UNIT, "cores": cores, "kind": "oracle", "sample": what,
+    return {"value": value, "unit": UNIT, "cores": cores, "kind": "oracle", "sample": what, "cpu": cpu_model(),
             "single_core": {"value": k * dofs_per_cell / el1, "unit": UNIT, "cores": 1,
                             "sample": "one forward-Euler stage of the first %d cells of the first instance, %.1f s"
                                       % (k, el1)}}
 
 
-def fp64_plain(items, steps, max_cells, integrator="ssprk3"):
-    """Same instances in FP64, one context per instance, stepped one after
-    the other (no batching): the 'plain' form."""
+def fp64_plain(items, steps, integrator="ssprk3"):
+    """The same instances in FP64, one context per instance, stepped one after
+    the other (no batching): the 'plain' form.  Each context is warmed up like
+    the batched one (one step, then one K-step graph launch, which captures
+    the graph) before the timed K-step launches."""
     from paper_2510_11527_amd import af
-    sample, cells = [], 0
-    for s, U in items:
-        sample.append((s, U))
-        cells += int(np.prod(s["n"][:s["dim"]]))
-        if cells >= max_cells:
-            break
     ctxs = []
-    for s, U in sample:
+    for s, U in items:
         c = af.Context(dict(s, precision=64), integrator=integrator)
         c.set_state(0, U)
-        c.step(2)  # warm up (graph build)
+        c.step(1)
+        c.step(steps)
         ctxs.append(c)
     t0 = time.perf_counter()
     for c in ctxs:
         c.step(steps)
     el = time.perf_counter() - t0
-    for c in ctxs:
-        c.close()
+    cells = sum(int(np.prod(s["n"][:s["dim"]])) for s, _ in items)
     dpc = 2 ** items[0][0]["dim"]
-    return {"value": cells * dpc * STAGES[integrator] * steps / el, "unit": UNIT, "dtype": "f64", "instances": len(sample),
-            "cells": cells, "steps": steps, "seconds": el}
+    return ctxs, {"value": cells * dpc * STAGES[integrator] * steps / el, "unit": UNIT, "dtype": "f64",
+                  "instances": len(items), "cells": cells, "steps": steps, "seconds": el}
+
+
+def rel_l1(a, b):
+    """max over DoF kinds of ||a - b||_1 / ||b||_1 (uniform cells)."""
+    return max(float(np.abs(np.asarray(x) - np.asarray(y)).sum() / max(np.abs(y).sum(), 1e-300))
+               for x, y in zip(a, b))
+
+
+def restrict(spec, U):
+    """DoFs of a fine grid on the grid of half as many cells per axis: an
+    average is the mean of the 2^d fine averages it covers; every point value
+    of the coarse grid is a fine corner point value (all coarse DoF points lie
+    on fine faces along every axis)."""
+    d = spec["dim"]
+    n = spec["n"][:d]
+    shp = tuple(reversed(n))
+    A = np.asarray(U[0]).reshape(shp)
+    for ax in range(d):
+        A = A.reshape(A.shape[:ax] + (A.shape[ax] // 2, 2) + A.shape[ax + 1:]).mean(axis=ax + 1)
+    C = np.asarray(U[-1]).reshape(shp)   # the corner kind (all axes on faces)
+    from paper_2510_11527_amd import workloads as W
+    out = [A.reshape(-1)]
+    for mask in W.ZETA_MASKS[d][1:]:
+        sl = tuple(slice(1 if (mask >> (d - 1 - a)) & 1 else 0, None, 2) for a in range(d))
+        out.append(C[sl].reshape(-1))
+    return out
+
+
+def coarse_fourier(spec, U):
+    """The instance's Fourier initial data on half as many cells per axis,
+    rescaled with the fine grid's map to [0, 1] (so that both grids sample one
+    and the same function)."""
+    from paper_2510_11527_amd import workloads as W
+    d = spec["dim"]
+    g = W.fourier_dofs(spec, spec["modes"])
+    g0, g1 = min(float(x.min()) for x in g), max(float(x.max()) for x in g)
+    sc = dict(spec, n=[v // 2 for v in spec["n"][:d]] + list(spec["n"][d:]), precision=64)
+    gc = W.fourier_dofs(sc, spec["modes"])
+    return sc, [(x - g0) / (g1 - g0) for x in gc]
+
+
+def run_to(ctx, t_end, chunk=500):
+    """Steps every instance of ctx to t_end (CFL steps, the last one clipped)."""
+    while True:
+        ctx.step(chunk, t_end=t_end)
+        if all(ctx.norms(i)["t"] >= t_end * (1 - 1e-12) for i in range(len(ctx.specs))):
+            return
+
+
+def c4_accuracy(items, fp64_ctxs, steps, fp32_ctx, n_coarse=16):
+    """Equal stated accuracy of the FP32 batched and FP64 plain forms on the
+    batched workload: both from the initial state for `steps` CFL steps;
+    max over instances of the relative l1 difference, against the
+    discretisation error estimated on a subset by the same run on half as
+    many cells per axis to the same time (relative l1 of the restricted fine
+    FP64 solution against the coarse one)."""
+    from paper_2510_11527_amd import af
+    for i, (s, U) in enumerate(items):
+        fp32_ctx.set_state(i, U)
+        fp64_ctxs[i].set_state(0, U)
+    fp32_ctx.step(steps)
+    worst, tdiff = 0.0, 0.0
+    u64s, t64s = [], []
+    for i, c in enumerate(fp64_ctxs):
+        c.step(steps)
+        V64, t64 = c.get_state(0)
+        V32, t32 = fp32_ctx.get_state(i)
+        worst = max(worst, rel_l1(V32, V64))
+        tdiff = max(tdiff, abs(t32 - t64) / t64)
+        t64s.append(t64)
+        u64s.append(V64 if i < 4 * n_coarse else None)
+    # discretisation error on a subset: instances of >= 128^2 cells
+    sub = [i for i, (s, _) in enumerate(items) if s["n"][0] >= 128 and u64s[i] is not None][:n_coarse]
+    disc = []
+    for i in sub:
+        s, U = items[i]
+        sc, Uc = coarse_fourier(s, U)
+        cc = af.Context(sc)
+        cc.set_state(0, Uc)
+        run_to(cc, t64s[i], chunk=64)
+        Vc, _ = cc.get_state(0)
+        cc.close()
+        disc.append(rel_l1(restrict(s, u64s[i]), Vc))
+    dmin = min(disc) if disc else None
+    return {"steps": steps, "fp32_vs_fp64_rel_l1_max": worst, "time_rel_diff_max": tdiff,
+            "disc_err_n_vs_half_n_rel_l1_min": dmin, "disc_err_n_vs_half_n_rel_l1_median":
+                float(np.median(disc)) if disc else None, "disc_subset": len(disc),
+            "fp32_within_0p1_disc": (worst <= 0.1 * dmin) if disc else None}
 
 
 def main():
@@ -248,14 +344,17 @@ def main():
         # the context stream, over K more steps of the same workload
         ms, nl = ctx.step_timed(args.steps)
         achieved = work["bytes_per_stage"] / (ms * 1e-3) / 1e9
+        copy_gbs = af.copy_rate(1 << 30, 20)
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wname, variant_name),
+                "frac": achieved / HBM_PEAK_GBS, "attainable_copy": copy_gbs,
+                "frac_of_attainable": achieved / copy_gbs,
+                "traffic": measured_traffic(wname, variant_name),
                 "valu_busy_pct": measured_valu_busy(wname, variant_name),
                 "kernel": "stage kernel %s (%s)" % (variant_name, "fp32" if prec == 32 else "fp64"),
                 "mean_launch_ms": ms, "launches": nl,
                 "algorithmic_bytes_per_launch": work["bytes_per_stage"]}
-        log("stage kernel mean %.4f ms over %d launches -> %.1f GB/s" % (ms, nl, achieved))
-    ctx.close()
+        log("stage kernel mean %.4f ms over %d launches -> %.1f GB/s (copy kernel %.1f GB/s)" % (
+            ms, nl, achieved, copy_gbs))
 
     line = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
@@ -272,11 +371,23 @@ def main():
     if tuned:
         line["autotune_stage_ms"] = tuned
     if not args.no_fp64_plain and prec == 32:
+        ctxs = []
         try:
-            line["fp64_plain"] = fp64_plain(items, max(10, args.steps // 10), 4_000_000, args.integrator)
+            ctxs, line["fp64_plain"] = fp64_plain(items, args.steps, args.integrator)
             line["fp32_batched_over_fp64_plain"] = value / line["fp64_plain"]["value"]
+            log("fp64 plain: %.3e cell-DoF updates/s per stage (%d instances, %.3f s)" % (
+                line["fp64_plain"]["value"], len(items), line["fp64_plain"]["seconds"]))
         except Exception as e:  # reported, not fatal
             line["fp64_plain"] = {"error": str(e)}
+        if ctxs and args.workload == "c4" and args.integrator == "ssprk3":
+            try:
+                line["accuracy"] = c4_accuracy(items, ctxs, items[0][0]["steps"], ctx)
+                log("accuracy: %s" % line["accuracy"])
+            except Exception as e:  # reported, not fatal
+                line["accuracy"] = {"error": str(e)}
+        for c in ctxs:
+            c.close()
+    ctx.close()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(items, 12_000_000 if items[0][0]["dim"] == 2 else 2_000_000,
                                               args.integrator)
