@@ -349,18 +349,32 @@ hipError_t finalize_launch(int n_inst, const InstDev *inst, const StepCtl *ctl, 
 
 // Streaming copy of 16-byte elements: the attainable-bandwidth reference the
 // stage kernels are compared with (every byte read once and written once).
-__global__ void __launch_bounds__(256) copy16_kernel(const float4 *__restrict__ src, float4 *__restrict__ dst,
+// Four independent 16-byte loads per thread are in flight before their
+// stores; non-temporal accesses keep the copy from thrashing the caches.
+typedef float copy_v4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) copy16_kernel(const copy_v4 *__restrict__ src, copy_v4 *__restrict__ dst,
                                                      long long n)
 {
-    for (long long i = threadIdx.x + (long long)blockIdx.x * 256; i < n; i += (long long)gridDim.x * 256)
-        dst[i] = src[i];
+    const long long stride = (long long)gridDim.x * 256;
+    long long i = threadIdx.x + (long long)blockIdx.x * 256;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const copy_v4 a = __builtin_nontemporal_load(src + i);
+        const copy_v4 b = __builtin_nontemporal_load(src + i + stride);
+        const copy_v4 c = __builtin_nontemporal_load(src + i + 2 * stride);
+        const copy_v4 d = __builtin_nontemporal_load(src + i + 3 * stride);
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + stride);
+        __builtin_nontemporal_store(c, dst + i + 2 * stride);
+        __builtin_nontemporal_store(d, dst + i + 3 * stride);
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
 }
 
 hipError_t copy16_launch(const void *src, void *dst, long long n16, hipStream_t s)
 {
-    const long long want = (n16 + 255) / 256;
-    const int blocks = (int)(want < 8192 ? (want > 0 ? want : 1) : 8192);
-    hipLaunchKernelGGL(copy16_kernel, dim3(blocks), dim3(256), 0, s, (const float4 *)src, (float4 *)dst, n16);
+    const long long want = (n16 + 1023) / 1024;
+    const int blocks = (int)(want < 4096 ? (want > 0 ? want : 1) : 4096);
+    hipLaunchKernelGGL(copy16_kernel, dim3(blocks), dim3(256), 0, s, (const copy_v4 *)src, (copy_v4 *)dst, n16);
     return hipGetLastError();
 }
 
@@ -434,7 +448,7 @@ int stage_num_variants(int dim)
 #define AF4_COUNT2(V, TX, TY, TZ, NT, KIND, NAME) n++;
     if (dim == 1) { AF4_VARIANTS_D1(AF4_COUNT) }
     if (dim == 2) { AF4_VARIANTS_D2(AF4_COUNT2) }
-    if (dim == 3) { AF4_VARIANTS_D3(AF4_COUNT) }
+    if (dim == 3) { AF4_VARIANTS_D3(AF4_COUNT2) }
 #undef AF4_COUNT
 #undef AF4_COUNT2
     return n;
@@ -449,7 +463,7 @@ VariantInfo stage_variant(int dim, int v)
     if (v == V) r = VariantInfo{{TX, TY, TZ}, NT, NAME};
     if (dim == 1) { AF4_VARIANTS_D1(AF4_INFO) }
     if (dim == 2) { AF4_VARIANTS_D2(AF4_INFO2) }
-    if (dim == 3) { AF4_VARIANTS_D3(AF4_INFO) }
+    if (dim == 3) { AF4_VARIANTS_D3(AF4_INFO2) }
 #undef AF4_INFO
 #undef AF4_INFO2
     for (int l = dim; l < 3; l++) r.tile[l] = 1;
@@ -460,7 +474,7 @@ bool stage_supported(int dim, int prec, bool lim, bool si, unsigned caps, int va
 {
     if (dim == 1) return stage_supported_d1(prec, lim, si, variant);
     if (dim == 2) return stage_supported_d2(prec, lim, si, caps, variant);
-    if (dim == 3) return stage_supported_d3(prec, lim, si, variant);
+    if (dim == 3) return stage_supported_d3(prec, lim, si, caps, variant);
     return false;
 }
 

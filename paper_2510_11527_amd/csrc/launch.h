@@ -33,7 +33,7 @@ hipError_t stage_launch(int dim, int prec, bool lim, bool si, unsigned caps, int
 bool stage_supported(int dim, int prec, bool lim, bool si, unsigned caps, int variant);
 bool stage_supported_d1(int prec, bool lim, bool si, int variant);
 bool stage_supported_d2(int prec, bool lim, bool si, unsigned caps, int variant);
-bool stage_supported_d3(int prec, bool lim, bool si, int variant);
+bool stage_supported_d3(int prec, bool lim, bool si, unsigned caps, int variant);
 hipError_t stage_launch_d1(int prec, bool lim, bool si, unsigned caps, int variant, int nblocks, const void *params, hipStream_t s);
 hipError_t stage_launch_d2(int prec, bool lim, bool si, unsigned caps, int variant, int nblocks, const void *params,
                            hipStream_t s);
