@@ -81,11 +81,23 @@ constexpr long stage3m_lds_bytes()
     return n * (long)sizeof(T);
 }
 
-template <class T, bool LIM, bool SI, int TX, int TY, int LZ>
-__global__ void __launch_bounds__(TX * TY) stage3m_kernel(StageParams<T> p)
+// Phase 6 work of a column split among NH threads (twice the waves on the
+// same LDS with NH = 2): the part of the thread that updates point value zk
+// (zk = 0: the average) -- NH = 2: the even half plane's three point values
+// and the average, the odd half plane's four.
+template <int NH>
+__device__ __forceinline__ constexpr int m3_part(int zk)
+{
+    return NH == 1 ? 0 : (zeta_mask<3>(zk) >> 2) & 1;
+}
+
+// NT = NH TX TY threads, NH in {1, 2} per column
+template <class T, bool LIM, bool SI, int TX, int TY, int LZ, int NT>
+__global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
 {
     using G = MGeo<TX, TY, SI>;
-    constexpr int NT = TX * TY;
+    constexpr int NH = NT / (TX * TY);
+    static_assert(NT == NH * TX * TY && (NH == 1 || NH == 2), "one or two threads per column");
     constexpr int HZ = G::HZ;
 
     __shared__ T sUB[4][G::NUB];   // averages of planes k .. k+3 (slot: plane & 3)
@@ -567,7 +579,7 @@ __global__ void __launch_bounds__(TX * TY) stage3m_kernel(StageParams<T> p)
         // ---- 6: point values of half planes 2k, 2k+1 and averages of plane k
         if (k >= z0) {
             const T *ub0 = sUB[s4(k)], *ub1 = sUB[s4(k + 1)];
-            box_loop<TX, TY, 1, NT>([&](int u, int v, int) {
+            box_loop<TX, TY, NH, NT>([&](int u, int v, int half) {
                 const bool own = ox + u < n0 && oy + v < n1;
                 const long long gi = own ? (ox + u) + (long long)n0 * (oy + v) + plane * k : 0;
                 // the seven point values: mask bits (x, y, z) and zeta index
@@ -575,6 +587,7 @@ __global__ void __launch_bounds__(TX * TY) stage3m_kernel(StageParams<T> p)
                 for (int zk = 1; zk < 8; zk++) {
                     const int m = zeta_mask<3>(zk);
                     const int bx = m & 1, by = (m >> 1) & 1, bz = (m >> 2) & 1;
+                    if (m3_part<NH>(zk) != half) continue;
                     const int pp = 2 * u + bx, qq = 2 * v + by, hh = 2 * k + bz;
                     const T *hrow = sH[s6(hh)];
                     const T u0 = hrow[G::hp(pp, qq)];
@@ -658,7 +671,7 @@ __global__ void __launch_bounds__(TX * TY) stage3m_kernel(StageParams<T> p)
                     if constexpr (LIM) val = clampb(val, P.umin, P.umax);
                     out[zk * kst + gi] = val;
                 }
-                if (!own) return;
+                if (!own || half != m3_part<NH>(0)) return;
                 // the average
                 const T uc = ub0[G::ub(u, v)];
                 const T Fxp = sXF[(u + 2) + G::FXW * v], Fxm = sXF[(u + 1) + G::FXW * v];

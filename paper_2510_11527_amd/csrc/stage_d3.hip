@@ -28,7 +28,7 @@ hipError_t launch_one(int nblocks, const void *params, hipStream_t s)
 }
 
 // the kernel marching along z (fluxes c1 u + c2 u^2 only)
-template <class T, bool LIM, bool SI, int TX, int TY, int TZ>
+template <class T, bool LIM, bool SI, int TX, int TY, int TZ, int NT>
 hipError_t launch_march(int nblocks, const void *params, hipStream_t s)
 {
     const StageParams<T> &p = *(const StageParams<T> *)params;
@@ -36,7 +36,7 @@ hipError_t launch_march(int nblocks, const void *params, hipStream_t s)
         return hipErrorInvalidValue;
     } else {
         if (p.lact) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((stage3m_kernel<T, LIM, SI, TX, TY, TZ>), dim3(nblocks), dim3(TX * TY), 0, s, p);
+        hipLaunchKernelGGL((stage3m_kernel<T, LIM, SI, TX, TY, TZ, NT>), dim3(nblocks), dim3(NT), 0, s, p);
         return hipGetLastError();
     }
 }
@@ -48,10 +48,10 @@ hipError_t launch_tq(bool lim, bool si, int nblocks, const void *params, hipStre
         if constexpr (!QF) {
             return hipErrorInvalidValue;
         } else {
-            if (lim) return si ? launch_march<T, true, true, TX, TY, TZ>(nblocks, params, s)
-                               : launch_march<T, true, false, TX, TY, TZ>(nblocks, params, s);
-            return si ? launch_march<T, false, true, TX, TY, TZ>(nblocks, params, s)
-                      : launch_march<T, false, false, TX, TY, TZ>(nblocks, params, s);
+            if (lim) return si ? launch_march<T, true, true, TX, TY, TZ, NT>(nblocks, params, s)
+                               : launch_march<T, true, false, TX, TY, TZ, NT>(nblocks, params, s);
+            return si ? launch_march<T, false, true, TX, TY, TZ, NT>(nblocks, params, s)
+                      : launch_march<T, false, false, TX, TY, TZ, NT>(nblocks, params, s);
         }
     } else {
         if (lim) return si ? launch_one<T, true, true, QF, TX, TY, TZ, NT, CV>(nblocks, params, s)

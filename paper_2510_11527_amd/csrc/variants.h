@@ -19,20 +19,18 @@ namespace af4 {
     X(6, 16, 16, 1, 256, 0, "generic-16x16") X(7, 32, 32, 1, 512, 4, "2d-own-32x32")
 // the tile variant whose generic kernel also has the limiter-counting form
 // (af_limiter_activity)
-constexpr int count_variant(int dim) { return dim == 2 ? 5 : dim == 3 ? 1 : 0; }
+constexpr int count_variant(int dim) { return dim == 2 ? 5 : dim == 3 ? 6 : 0; }
 
-// 3D: KIND 0 = generic kernel (any flux), 1 = the kernel that marches along
-// z (fluxes c1 u + c2 u^2; TZ is the number of cell planes a workgroup
-// walks).  The generic 8x8x8 tile (less halo per cell, 125 KiB of LDS with SI
-// blending in FP32) does not fit in FP64, where 8x8x4 is the first built one.
-// The marching kernels recompute nothing across z but hold one wave per SIMD
-// (LDS rings of about 36-120 KiB); on the 3D workload they measure 4.3 ms per
-// stage against 3.3 ms for generic-8x8x8, so the default stays generic and
-// the autotuner times both.
+// 3D: KIND 1 = the kernel that marches along z (fluxes c1 u + c2 u^2; TZ is
+// the number of cell planes a workgroup walks; two threads per (x, y)
+// column), 0 = generic kernel (any flux).  The generic 8x8x8 tile (125 KiB of
+// LDS with SI blending in FP32) does not fit in FP64, where 8x8x4 is the
+// first generic tile built.
 #define AF4_VARIANTS_D3(X)                                                                            \
-    X(0, 8, 8, 8, 512, 0, "generic-8x8x8") X(1, 8, 8, 4, 256, 0, "generic-8x8x4")                      \
-    X(2, 8, 4, 4, 128, 0, "generic-8x4x4") X(3, 4, 4, 4, 64, 0, "generic-4x4x4")                       \
-    X(4, 16, 16, 32, 256, 1, "3d-march-16x16x32") X(5, 16, 8, 32, 128, 1, "3d-march-16x8x32")          \
-    X(6, 32, 8, 32, 256, 1, "3d-march-32x8x32") X(7, 8, 8, 32, 64, 1, "3d-march-8x8x32")
+    X(0, 16, 8, 32, 256, 1, "3d-march-16x8x32") X(1, 16, 8, 64, 256, 1, "3d-march-16x8x64")            \
+    X(2, 8, 8, 32, 128, 1, "3d-march-8x8x32") X(3, 16, 16, 32, 512, 1, "3d-march-16x16x32")            \
+    X(4, 32, 8, 32, 512, 1, "3d-march-32x8x32") X(5, 8, 8, 8, 512, 0, "generic-8x8x8")                  \
+    X(6, 8, 8, 4, 256, 0, "generic-8x8x4") X(7, 8, 4, 4, 128, 0, "generic-8x4x4")                       \
+    X(8, 4, 4, 4, 64, 0, "generic-4x4x4")
 
 }  // namespace af4
