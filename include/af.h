@@ -167,6 +167,25 @@ af_status af_set_state(af_ctx *ctx, int inst, const double *const *dofs, double 
 /* Copies the state of instance inst to the host (widened to double). */
 af_status af_get_state(af_ctx *ctx, int inst, double *const *dofs, double *t);
 
+/* af_set_state for DoFs in device memory: dofs (a host array of 2^d
+ * pointers) points to 2^d device arrays of n0*n1*n2 doubles each, in zeta
+ * order, readable by the context's device.  The arrays must be ready once
+ * the work queued on `stream` (a hipStream_t of the HIP runtime this library
+ * is linked against; NULL: the null stream) is done: the call waits for that
+ * stream first.  Rounding (FP32 contexts: to nearest), the non-finite check
+ * (after rounding) and the bounds of Def. 5.1 are those of af_set_state,
+ * evaluated on the device; a rejected state leaves the context as it was.
+ * Synchronizes the context stream before returning: the caller's arrays may
+ * be reused or freed at once.  No host copy of the state is made. */
+af_status af_set_state_dev(af_ctx *ctx, int inst, const double *const *dofs, double t, void *stream);
+
+/* af_get_state to device memory: writes the state of instance inst, widened
+ * to double, to the 2^d device arrays dofs[0..2^d-1] of n0*n1*n2 doubles
+ * (zeta order), and the time to *t when t is not NULL.  Waits for `stream`
+ * first (as af_set_state_dev) and synchronizes the context stream before
+ * returning, so the arrays hold the state when the call returns. */
+af_status af_get_state_dev(af_ctx *ctx, int inst, double *const *dofs, double *t, void *stream);
+
 /* Advances every instance by nsteps steps.  Per step and instance, dt is
  * the CFL value computed on the device from the averages (FP64 reduction of
  * the interval maximum of |f_l'|, Eq. (1d_local_wave_speed)), or

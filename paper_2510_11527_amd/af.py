@@ -25,7 +25,8 @@ INTEGRATORS = {"ssprk3": 0, "euler": 1, "ssprk54": 2}
 
 EXPORTS = ["af_create", "af_destroy", "af_set_state", "af_get_state", "af_step", "af_residual", "af_norms",
            "af_last_error", "af_set_stream", "af_set_variant", "af_num_variants", "af_variant_name",
-           "af_step_timed", "af_work", "af_get_variant", "af_autotune", "af_limiter_activity", "af_norms_noalloc", "af_copy_rate"]
+           "af_step_timed", "af_work", "af_get_variant", "af_autotune", "af_limiter_activity", "af_norms_noalloc", "af_copy_rate",
+           "af_set_state_dev", "af_get_state_dev"]
 
 
 class AfProblem(ctypes.Structure):
@@ -99,6 +100,8 @@ def lib():
         L.af_norms_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp, dp, vp, ctypes.c_longlong, vp,
                                        ctypes.POINTER(AfNorms)]
         L.af_copy_rate.argtypes = [ctypes.c_longlong, ctypes.c_int, dp]
+        L.af_set_state_dev.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.c_double, vp]
+        L.af_get_state_dev.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), dp, vp]
         for name in EXPORTS:
             if name not in ("af_last_error", "af_num_variants", "af_variant_name", "af_get_variant"):
                 getattr(L, name).restype = ctypes.c_int
@@ -201,6 +204,20 @@ class Context:
         t = ctypes.c_double()
         self._check(lib().af_get_state(self.h, int(inst), _pp(out), ctypes.byref(t)))
         return out, t.value
+
+    def set_state_dev(self, inst, ptrs, t=0.0, stream_ptr=None):
+        """af_set_state_dev: ptrs holds 2^d device addresses (integers) of
+        FP64 arrays of ncells[inst] values, in zeta order."""
+        a = (ctypes.c_void_p * len(ptrs))(*[int(p) for p in ptrs])
+        self._check(lib().af_set_state_dev(self.h, int(inst), a, float(t), stream_ptr))
+
+    def get_state_dev(self, inst, ptrs, stream_ptr=None):
+        """af_get_state_dev: the state, widened to FP64, to the device arrays
+        at ptrs; returns the time."""
+        a = (ctypes.c_void_p * len(ptrs))(*[int(p) for p in ptrs])
+        t = ctypes.c_double()
+        self._check(lib().af_get_state_dev(self.h, int(inst), a, ctypes.byref(t), stream_ptr))
+        return t.value
 
     def step(self, nsteps=1, t_end=0.0, dt=None):
         n = len(self.specs)

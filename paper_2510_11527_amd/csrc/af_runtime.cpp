@@ -723,28 +723,24 @@ af_status af_set_variant(af_ctx *c, int v)
     return build_work(c);
 }
 
-af_status af_set_state(af_ctx *c, int inst, const double *const *dofs, double t)
+}  // extern "C"
+
+namespace {
+
+// The bounds part of setting a state, shared by the host and the device
+// setters: lo / hi are the min / max of the DoFs rounded to the storage
+// precision.  Derives [umin, umax] on the first call when they were NaN at
+// creation, then checks the DoFs and the Dirichlet values against them when
+// the limiter is on.  Mutates nothing before every check has passed.
+af_status accept_bounds(af_ctx *c, int inst, double lo, double hi, const char *who)
 {
-    if (!c || inst < 0 || inst >= c->n_inst || !dofs) return fail(c, AF_ERR_ARG, "af_set_state: bad arguments");
     InstDev &I = c->ih[inst];
     const af_problem &P = c->prob[inst];
-    const int nk = nkinds(c);
-    const long long n = I.ncell;
-    // round to the storage precision first: bounds and checks see what is stored
-    std::vector<double> r((size_t)n * nk);
-    for (int z = 0; z < nk; z++) {
-        if (!dofs[z]) return fail(c, AF_ERR_ARG, "af_set_state: null DoF array");
-        for (long long k = 0; k < n; k++) {
-            double v = dofs[z][k];
-            if (!std::isfinite(v)) return fail(c, AF_ERR_NONFINITE, "af_set_state: non-finite DoF");
-            r[(size_t)z * n + k] = c->prec == 32 ? (double)(float)v : v;
-        }
-    }
     double umin = I.umin, umax = I.umax;
-    const bool derive = std::isnan(P.umin) || std::isnan(P.umax);
-    if (derive && !c->have_state[inst]) {
-        umin = *std::min_element(r.begin(), r.end());
-        umax = *std::max_element(r.begin(), r.end());
+    const bool derive = (std::isnan(P.umin) || std::isnan(P.umax)) && !c->have_state[inst];
+    if (derive) {
+        umin = lo;
+        umax = hi;
         for (int l = 0; l < 3; l++)  // Dirichlet data bound the solution too
             for (int e = 0; e < 2; e++)
                 if (P.bc[l][e] == AF_BC_DIRICHLET) {
@@ -754,22 +750,68 @@ af_status af_set_state(af_ctx *c, int inst, const double *const *dofs, double t)
                 }
     }
     if (c->lim) {
-        for (double v : r)
-            if (v < umin || v > umax) return fail(c, AF_ERR_BOUNDS, "af_set_state: DoF outside [umin, umax]");
+        if (lo < umin || hi > umax) return fail(c, AF_ERR_BOUNDS, std::string(who) + ": DoF outside [umin, umax]");
         for (int l = 0; l < 3; l++)
             for (int e = 0; e < 2; e++) {
                 const double g = c->prec == 32 ? (double)(float)P.bc_value[l][e] : P.bc_value[l][e];
                 if (P.bc[l][e] == AF_BC_DIRICHLET && !(g >= umin && g <= umax))
-                    return fail(c, AF_ERR_BOUNDS, "af_set_state: Dirichlet value outside [umin, umax]");
+                    return fail(c, AF_ERR_BOUNDS, std::string(who) + ": Dirichlet value outside [umin, umax]");
             }
     }
-    if (derive && !c->have_state[inst]) {
+    if (derive) {
         I.umin = umin;
         I.umax = umax;
         derive_bounds_params(I, P, c->dim);
         set_f32_params(I);
         HIPOK(c, hipMemcpy(c->d_inst + inst, &I, sizeof I, hipMemcpyHostToDevice));
     }
+    return AF_OK;
+}
+
+// The last part of setting a state: time t, step count and flags cleared.
+af_status commit_state(af_ctx *c, int inst, double t)
+{
+    InstState st;
+    std::memset(&st, 0, sizeof st);
+    st.t = t;
+    HIPOK(c, hipMemcpyAsync(c->d_st + inst, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
+    HIPOK(c, hipStreamSynchronize(c->stream));
+    c->have_state[inst] = 1;
+    c->keys_fresh = false;  // the new state's min / max are not reduced yet
+    return AF_OK;
+}
+
+// Orders the context's work after the caller's: the caller's arrays are
+// ready (and free to overwrite) once the work queued on `stream` is done.
+af_status after_caller(af_ctx *c, void *stream)
+{
+    if ((hipStream_t)stream != c->stream) HIPOK(c, hipStreamSynchronize((hipStream_t)stream));
+    return AF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+af_status af_set_state(af_ctx *c, int inst, const double *const *dofs, double t)
+{
+    if (!c || inst < 0 || inst >= c->n_inst || !dofs) return fail(c, AF_ERR_ARG, "af_set_state: bad arguments");
+    const InstDev &I = c->ih[inst];
+    const int nk = nkinds(c);
+    const long long n = I.ncell;
+    // round to the storage precision first: bounds and checks see what is stored
+    std::vector<double> r((size_t)n * nk);
+    for (int z = 0; z < nk; z++) {
+        if (!dofs[z]) return fail(c, AF_ERR_ARG, "af_set_state: null DoF array");
+        for (long long k = 0; k < n; k++) {
+            const double v = c->prec == 32 ? (double)(float)dofs[z][k] : dofs[z][k];
+            if (!std::isfinite(v)) return fail(c, AF_ERR_NONFINITE, "af_set_state: non-finite DoF");
+            r[(size_t)z * n + k] = v;
+        }
+    }
+    const auto mm = std::minmax_element(r.begin(), r.end());
+    const af_status bs = accept_bounds(c, inst, *mm.first, *mm.second, "af_set_state");
+    if (bs != AF_OK) return bs;
     std::vector<char> stage((size_t)n * vbytes(c));
     char *base = (char *)c->buf[0] + (size_t)I.off * vbytes(c);
     for (int z = 0; z < nk; z++) {
@@ -779,14 +821,37 @@ af_status af_set_state(af_ctx *c, int inst, const double *const *dofs, double t)
                                 hipMemcpyHostToDevice, c->stream));
         HIPOK(c, hipStreamSynchronize(c->stream));
     }
-    InstState st;
-    std::memset(&st, 0, sizeof st);
-    st.t = t;
-    HIPOK(c, hipMemcpyAsync(c->d_st + inst, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
+    return commit_state(c, inst, t);
+}
+
+af_status af_set_state_dev(af_ctx *c, int inst, const double *const *dofs, double t, void *stream)
+{
+    if (!c || inst < 0 || inst >= c->n_inst || !dofs) return fail(c, AF_ERR_ARG, "af_set_state_dev: bad arguments");
+    const InstDev &I = c->ih[inst];
+    const int nk = nkinds(c);
+    const size_t vb = vbytes(c);
+    for (int z = 0; z < nk; z++)
+        if (!dofs[z]) return fail(c, AF_ERR_ARG, "af_set_state_dev: null DoF array");
+    const af_status os = after_caller(c, stream);
+    if (os != AF_OK) return os;
+    // the rounded DoFs go to the instance's part of state buffer 1 (free
+    // between steps) and are checked there, so a rejected state leaves the
+    // context's state as it was
+    char *stg = (char *)c->buf[1] + (size_t)I.off * vb;
+    for (int z = 0; z < nk; z++)
+        HIPOK(c, af4::convert_launch(c->prec, true, dofs[z], stg + (size_t)z * I.kstride * vb, I.ncell, c->stream));
+    HIPOK(c, af4::norms_launch(c->prec, stg, I.ncell, I.kstride, nk, c->d_npart, c->d_nout, c->stream));
+    double r[9];
+    HIPOK(c, hipMemcpyAsync(r, c->d_nout, sizeof r, hipMemcpyDeviceToHost, c->stream));
     HIPOK(c, hipStreamSynchronize(c->stream));
-    c->have_state[inst] = 1;
-    c->keys_fresh = false;  // the new state's min / max are not reduced yet
-    return AF_OK;
+    if (r[8] > 0) return fail(c, AF_ERR_NONFINITE, "af_set_state_dev: non-finite DoF");
+    const af_status bs = accept_bounds(c, inst, std::min(r[4], r[6]), std::max(r[5], r[7]), "af_set_state_dev");
+    if (bs != AF_OK) return bs;
+    char *base = (char *)c->buf[0] + (size_t)I.off * vb;
+    for (int z = 0; z < nk; z++)
+        HIPOK(c, af4::copy_launch(c->prec, stg + (size_t)z * I.kstride * vb, base + (size_t)z * I.kstride * vb, I.ncell,
+                                  c->stream));
+    return commit_state(c, inst, t);
 }
 
 af_status af_get_state(af_ctx *c, int inst, double *const *dofs, double *t)
@@ -810,6 +875,25 @@ af_status af_get_state(af_ctx *c, int inst, double *const *dofs, double *t)
         HIPOK(c, hipStreamSynchronize(c->stream));
         *t = st.t;
     }
+    return AF_OK;
+}
+
+af_status af_get_state_dev(af_ctx *c, int inst, double *const *dofs, double *t, void *stream)
+{
+    if (!c || inst < 0 || inst >= c->n_inst || !dofs) return fail(c, AF_ERR_ARG, "af_get_state_dev: bad arguments");
+    const InstDev &I = c->ih[inst];
+    const size_t vb = vbytes(c);
+    for (int z = 0; z < nkinds(c); z++)
+        if (!dofs[z]) return fail(c, AF_ERR_ARG, "af_get_state_dev: null DoF array");
+    const af_status os = after_caller(c, stream);
+    if (os != AF_OK) return os;
+    const char *base = (const char *)c->buf[0] + (size_t)I.off * vb;
+    for (int z = 0; z < nkinds(c); z++)
+        HIPOK(c, af4::convert_launch(c->prec, false, base + (size_t)z * I.kstride * vb, dofs[z], I.ncell, c->stream));
+    InstState st;
+    if (t) HIPOK(c, hipMemcpyAsync(&st, c->d_st + inst, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    HIPOK(c, hipStreamSynchronize(c->stream));
+    if (t) *t = st.t;
     return AF_OK;
 }
 

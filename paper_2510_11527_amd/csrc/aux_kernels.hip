@@ -238,6 +238,14 @@ __global__ void copy_kernel(const T *__restrict__ src, T *__restrict__ dst, long
         dst[i] = src[i];
 }
 
+// dst = src converted to D (round to nearest) over n values.
+template <class S, class D>
+__global__ void convert_kernel(const S *__restrict__ src, D *__restrict__ dst, long long n)
+{
+    for (long long i = threadIdx.x + (long long)blockIdx.x * blockDim.x; i < n; i += (long long)blockDim.x * gridDim.x)
+        dst[i] = (D)src[i];
+}
+
 // Block partials in fixed order, then one block reduces them in fixed order:
 // the result is bitwise reproducible.  The three sums are compensated
 // (Neumaier) in each thread's loop, in the block's pairwise tree and in the
@@ -387,6 +395,21 @@ hipError_t copy_launch(int prec, const void *src, void *dst, long long n, hipStr
         hipLaunchKernelGGL(copy_kernel<float>, dim3((unsigned)nb), dim3(256), 0, s, (const float *)src, (float *)dst, n);
     else
         hipLaunchKernelGGL(copy_kernel<double>, dim3((unsigned)nb), dim3(256), 0, s, (const double *)src,
+                           (double *)dst, n);
+    return hipGetLastError();
+}
+
+hipError_t convert_launch(int prec, bool to_storage, const void *src, void *dst, long long n, hipStream_t s)
+{
+    if (prec == 64) return copy_launch(64, src, dst, n, s);
+    long long nb = (n + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    if (nb < 1) nb = 1;
+    if (to_storage)
+        hipLaunchKernelGGL((convert_kernel<double, float>), dim3((unsigned)nb), dim3(256), 0, s, (const double *)src,
+                           (float *)dst, n);
+    else
+        hipLaunchKernelGGL((convert_kernel<float, double>), dim3((unsigned)nb), dim3(256), 0, s, (const float *)src,
                            (double *)dst, n);
     return hipGetLastError();
 }

@@ -89,6 +89,9 @@ hipError_t finalize_launch(int n_inst, const InstDev *inst, const StepCtl *ctl, 
 
 // dst = src over n values.
 hipError_t copy_launch(int prec, const void *src, void *dst, long long n, hipStream_t s);
+// FP64 values to the storage precision (to_storage) or back, over n values
+// (round to nearest; a plain copy for FP64 storage).
+hipError_t convert_launch(int prec, bool to_storage, const void *src, void *dst, long long n, hipStream_t s);
 // dst = src over n16 16-byte elements (the copy-bandwidth reference).
 hipError_t copy16_launch(const void *src, void *dst, long long n16, hipStream_t s);
 

@@ -18,6 +18,7 @@ import pytest
 
 from paper_2510_11527_amd import af
 from paper_2510_11527_amd import workloads as W
+from hip_mem import DeviceBlock, hip
 
 pytestmark = pytest.mark.gpu
 
@@ -27,46 +28,6 @@ FIELDS = ["mass", "min_avg", "max_avg", "min_pv", "max_pv", "l1_avg", "l2_avg", 
 def note(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-_hip = None
-
-
-def hip():
-    """The HIP runtime libaf4.so uses (loaded with it)."""
-    global _hip
-    if _hip is None:
-        af.lib()
-        H = ctypes.CDLL("libamdhip64.so.7")
-        vp = ctypes.c_void_p
-        H.hipMalloc.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t]
-        H.hipFree.argtypes = [vp]
-        H.hipMemcpy.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int]
-        H.hipStreamCreate.argtypes = [ctypes.POINTER(vp)]
-        H.hipStreamDestroy.argtypes = [vp]
-        for f in ("hipMalloc", "hipFree", "hipMemcpy", "hipStreamCreate", "hipStreamDestroy", "hipDeviceSynchronize"):
-            getattr(H, f).restype = ctypes.c_int
-        _hip = H
-    return _hip
-
-
-class DeviceBlock:
-    """The DoFs as one device block with kind stride ncell + pad; the padding
-    holds NaN, which the reduction must never read."""
-
-    def __init__(self, U, precision, pad):
-        ncell = U[0].size
-        host = np.full((len(U), ncell + pad), np.nan, dtype=np.float32 if precision == 32 else np.float64)
-        for z, u in enumerate(U):
-            host[z, :ncell] = u
-        self.kstride = ncell + pad
-        self.ptr = ctypes.c_void_p()
-        assert hip().hipMalloc(ctypes.byref(self.ptr), host.nbytes) == 0
-        assert hip().hipMemcpy(self.ptr, host.ctypes.data, host.nbytes, 1) == 0   # host to device
-        assert hip().hipDeviceSynchronize() == 0
-
-    def free(self):
-        assert hip().hipFree(self.ptr) == 0
 
 
 def cases():
