@@ -35,6 +35,7 @@ struct InstDev {
     double pu0, plo, phi, pc1, pc2, pc3;
     int pabs, ppow;
     int wstart, wcount;  // the instance's range in the work list of the stage kernels
+    int cstart, ccount;  // the instance's range of wave-speed chunks (and their slots)
     int nodc, pad0;      // 1: diffusion in the form of App. A (no double conservation; 1D)
     int bc[3][2];        // af_bc of the low / high end of each axis (both periodic or neither)
     double bcv[3][2];    // Dirichlet values
@@ -60,7 +61,6 @@ struct StepCtl {
 struct InstState {
     double dt;           // step of the current step
     double t;            // time at the end of the current step
-    unsigned long long wmax;      // bits of the FP64 max wave speed (non-negative)
     unsigned long long clampmax;  // bits of the largest average clamp (non-negative)
     unsigned int flags;  // bit 0: non-finite / divergent value produced
     unsigned int pad;

@@ -41,6 +41,8 @@ struct af_ctx {
     unsigned long long *d_lact = nullptr;  // limiter-activity counters (2 per instance), on demand
     bool lact_on = false;                  // stage launches count limited faces / potentials
     int nchunks = 0;
+    unsigned long long *d_wslot = nullptr;  // one wave-speed slot per chunk
+    long long max_chunks = 0;               // most chunks of one instance
     void *buf[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // state buffers (A = U^n)
     long long total = 0;     // elements per state buffer
     double *d_npart = nullptr, *d_nout = nullptr;
@@ -455,11 +457,13 @@ hipError_t enqueue_step(af_ctx *c, bool ws, std::vector<hipEvent_t> *events, siz
 {
     hipError_t e;
     if (ws) {
-        e = af4::wavespeed_launch(c->dim, c->prec, c->d_inst, c->d_chunks, c->nchunks, c->buf[0], c->d_st, c->stream);
+        e = af4::wavespeed_launch(c->dim, c->prec, c->d_inst, c->d_chunks, c->nchunks, c->buf[0], c->d_st, c->d_wslot,
+                                  c->stream);
         if (e != hipSuccess) return e;
     }
     e = af4::finalize_launch(c->n_inst, c->d_inst, c->d_ctl, c->d_dtp, c->d_st, c->dim, c->prec,
-                             ws ? nullptr : c->d_mm, c->waves_per_block, c->max_slots, c->stream);
+                             ws ? nullptr : c->d_mm, ws ? c->d_wslot : nullptr, c->waves_per_block,
+                             ws ? c->max_chunks : c->max_slots, c->stream);
     if (e != hipSuccess) return e;
     const bool mm = cfl_from_keys(c);
     const StageSpec *sp = stages_of(c->integ);
@@ -654,12 +658,20 @@ af_status af_create(int n_inst, const af_problem *probs, af_ctx **out)
     std::vector<int2> chunks;
     for (int i = 0; i < n_inst; i++) {
         // rows, or segments of long rows, per chunk (af4::wave_chunk)
-        const InstDev &I = c->ih[i];
+        InstDev &I = c->ih[i];
         const long long nch = af4::wave_chunk_count(I.n[0], (long long)I.n[1] * I.n[2]);
+        if ((long long)chunks.size() + nch > (1ll << 30)) {
+            af_destroy(c);
+            return fail(nullptr, AF_ERR_ARG, "af_create: too many cells");
+        }
+        I.cstart = (int)chunks.size();
+        I.ccount = (int)nch;
+        c->max_chunks = std::max(c->max_chunks, nch);
         for (long long k = 0; k < nch; k++) chunks.push_back(make_int2(i, (int)k));
     }
     c->nchunks = (int)chunks.size();
-    if (!alloc((void **)&c->d_chunks, sizeof(int2) * chunks.size()) ||
+    if (!alloc((void **)&c->d_wslot, sizeof(unsigned long long) * chunks.size()) ||
+        !alloc((void **)&c->d_chunks, sizeof(int2) * chunks.size()) ||
         hipMemcpy(c->d_chunks, chunks.data(), sizeof(int2) * chunks.size(), hipMemcpyHostToDevice) != hipSuccess) {
         af_destroy(c);
         return AF_ERR_DEVICE;
@@ -682,7 +694,7 @@ af_status af_destroy(af_ctx *c)
     for (int b = 0; b < 5; b++)  // SSP-RK(5,4) contexts hold five state buffers
         if (c->buf[b]) (void)hipFree(c->buf[b]);
     void *ptrs[] = {c->d_inst, c->d_st,     c->d_ctl,  c->d_dtp, c->d_work,
-                    c->d_chunks, c->d_npart, c->d_nout, c->d_mm,  c->d_lact};
+                    c->d_chunks, c->d_npart, c->d_nout, c->d_mm,  c->d_lact, c->d_wslot};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -1075,10 +1087,11 @@ af_status af_limiter_activity(af_ctx *c, int inst, long long *counts)
     // the CFL step of the current state, then one forward-Euler stage into
     // the scratch buffer B with counting on
     if (e == hipSuccess && s == AF_OK)
-        e = af4::wavespeed_launch(c->dim, c->prec, c->d_inst, c->d_chunks, c->nchunks, c->buf[0], c->d_st, c->stream);
+        e = af4::wavespeed_launch(c->dim, c->prec, c->d_inst, c->d_chunks, c->nchunks, c->buf[0], c->d_st, c->d_wslot,
+                                  c->stream);
     if (e == hipSuccess && s == AF_OK)
         e = af4::finalize_launch(c->n_inst, c->d_inst, c->d_ctl, c->d_dtp, c->d_st, c->dim, c->prec, nullptr,
-                                 c->waves_per_block, c->max_slots, c->stream);
+                                 c->d_wslot, c->waves_per_block, c->max_chunks, c->stream);
     if (e == hipSuccess && s == AF_OK) {
         const StageSpec fe = {0, 1, -1, af4::kCombFE, 1.0, 0, 0, 0, 1.0, false};
         c->lact_on = true;

@@ -8,9 +8,11 @@ namespace af4 {
 
 // Max over the faces of the MPP CFL quantity alpha_l / dx_l + kappa_max /
 // dx_l^2 (Eqs. 1d_av_pp_dt, multid_av_pp_dt), in FP64 from the stored
-// averages, reduced per wave and merged per instance by an integer atomic max
-// on the bit pattern (valid for non-negative doubles).  A block covers whole
-// grid rows, or a segment of one long row, of one instance (wave_chunk).
+// averages.  A block covers whole grid rows, or a segment of one long row, of
+// one instance (wave_chunk) and writes its maximum to its own slot (the bit
+// pattern, ordered as integers for non-negative doubles); the finalize kernel
+// reduces the slots of an instance.  No atomics: many small blocks keep the
+// loads of the whole grid in flight.
 //
 // alpha_l of a face is the max of |f_l'| at its two averages and at the
 // interior maxima of |f_l'| between them.  Since x -> x / dx_l + kappa_max /
@@ -20,86 +22,93 @@ namespace af4 {
 // value, and of every interior maximum lying inside some face's interval.
 // Each value is evaluated exactly as per face, so the step is the same to
 // the bit, with half the FP64 evaluations of |f'|.
-template <class T>
+template <class T, int D>
 __global__ void __launch_bounds__(kWaveThreads) wavespeed_kernel(const InstDev *inst, const int2 *chunks, const T *U,
-                                                        InstState *st, int dim)
+                                                        InstState *st, unsigned long long *slots)
 {
     const int2 ch = chunks[blockIdx.x];
     const InstDev &I = inst[ch.x];
     Phys<double> P;
-    P.load(I, dim);
-    const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2];
-    const WaveChunk wc = wave_chunk(n0, (long long)n1 * n2, ch.y);
-    const T *u = U + I.off;
+    P.load(I, D);
     double idx[3], kdx2[3];
+#pragma unroll
     for (int l = 0; l < 3; l++) {
         idx[l] = I.idx1[l];
         kdx2[l] = I.kmax * I.idx2[l];
     }
+    // the interior maxima of |f_l'| and their terms |f_l'(c)| / dx_l +
+    // kappa_max / dx_l^2, evaluated once per block
+    __shared__ double scv[3][kMaxCrit], scw[3][kMaxCrit];
+    if ((int)threadIdx.x < 3 * kMaxCrit) {
+        const int l = threadIdx.x / kMaxCrit, c = threadIdx.x % kMaxCrit;
+        if (l < D && c < P.nc[l]) {
+            const double cv = I.crit[l][c];
+            scv[l][c] = cv;
+            scw[l][c] = P.adf(l, cv) * idx[l] + kdx2[l];
+        }
+    }
+    __syncthreads();
+    const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2];
+    const WaveChunk wc = wave_chunk(n0, (long long)n1 * n2, ch.y);
+    const T *u = U + I.off;
     const double big = 1e6 * fmax(fmax(fabs(I.umin), fabs(I.umax)), 1.0);
     // non-periodic ends (1D, 2D): the faces at the ends see a ghost cell whose
     // average is the Dirichlet value or (outflow) the boundary cell's average
-    const bool open0 = dim <= 2 && I.bc[0][0] != 0, open1 = dim == 2 && I.bc[1][0] != 0;
-    // |f_l'| at the interior maxima lying in [min(a, b), max(a, b)] (0 if none)
-    auto crit_in = [&](int l, double a, double b) -> double {
-        const double lo = fmin(a, b), hi = fmax(a, b);
-        double r = 0.0;
-        for (int c = 0; c < P.nc[l]; c++) {
-            const double cv = I.crit[l][c];
-            if (cv >= lo && cv <= hi) r = fmax(r, P.adf(l, cv));
-        }
-        return r;
-    };
-    // a face between averages a and b beyond the cell's own |f_l'|: the
-    // other end if it is a ghost value (g), and the interior maxima
+    const bool open0 = D <= 2 && I.bc[0][0] != 0, open1 = D == 2 && I.bc[1][0] != 0;
+    // a face between averages a and b beyond the cell's own term: the other
+    // end if it is a ghost value (g), and the interior maxima in [min, max]
+    // (the term is monotone in |f_l'|, so this is the per-face maximum)
     auto face = [&](int l, double a, double b, bool ghost, double w) -> double {
         if (ghost) w = fmax(w, P.adf(l, b) * idx[l] + kdx2[l]);
-        if (P.nc[l] > 0) w = fmax(w, crit_in(l, a, b) * idx[l] + kdx2[l]);
+        const double lo = fmin(a, b), hi = fmax(a, b);
+        for (int c = 0; c < P.nc[l]; c++)
+            if (scv[l][c] >= lo && scv[l][c] <= hi) w = fmax(w, scw[l][c]);
         return w;
     };
     double w = 0.0;
     bool bad = false;
-    for (int r = wc.r0; r < wc.r1; r++) {
+    const int width = wc.i1 - wc.i0;
+    const int ncells = width * (wc.r1 - wc.r0);
+    for (int q = (int)threadIdx.x; q < ncells; q += kWaveThreads) {
+        const int r = wc.r0 + q / width, i = wc.i0 + q % width;
         const int j = r % n1, k = r / n1;
         const long long row = (long long)n0 * r;
-        const long long rowy = (long long)n0 * ((j + 1 == n1 ? 0 : j + 1) + (long long)n1 * k);
-        const long long rowz = (long long)n0 * (j + (long long)n1 * (k + 1 == n2 ? 0 : k + 1));
-        for (int i = wc.i0 + (int)threadIdx.x; i < wc.i1; i += blockDim.x) {
-            const double uc = (double)u[row + i];
-            if (!(fabs(uc) <= big)) bad = true;  // also catches NaN
-            // the cell's own |f_l'| (constant axes: Phys stays in registers)
-            w = fmax(w, P.adf(0, uc) * idx[0] + kdx2[0]);
-            if (dim >= 2) w = fmax(w, P.adf(1, uc) * idx[1] + kdx2[1]);
-            if (dim >= 3) w = fmax(w, P.adf(2, uc) * idx[2] + kdx2[2]);
-            double ux = (double)u[row + (i + 1 == n0 ? 0 : i + 1)];
-            bool gx = false;
-            if (open0 && i + 1 == n0) {
-                gx = I.bc[0][1] == 1;
-                ux = gx ? (double)(T)I.bcv[0][1] : uc;
-            }
-            if (open0 && i == 0) {
-                const bool g = I.bc[0][0] == 1;
-                w = face(0, uc, g ? (double)(T)I.bcv[0][0] : uc, g, w);
-            }
-            w = face(0, uc, ux, gx, w);
-            if (dim >= 2) {
-                double uy = (double)u[rowy + i];
-                bool gy = false;
-                if (open1 && j + 1 == n1) {
-                    gy = I.bc[1][1] == 1;
-                    uy = gy ? (double)(T)I.bcv[1][1] : uc;
-                }
-                if (open1 && j == 0) {
-                    const bool g = I.bc[1][0] == 1;
-                    w = face(1, uc, g ? (double)(T)I.bcv[1][0] : uc, g, w);
-                }
-                w = face(1, uc, uy, gy, w);
-            }
-            if (dim >= 3) w = face(2, uc, (double)u[rowz + i], false, w);
+        // every load of the cell first
+        const double uc = (double)u[row + i];
+        double ux = (double)u[row + (i + 1 == n0 ? 0 : i + 1)];
+        double uy = 0.0, uz = 0.0;
+        if constexpr (D >= 2) uy = (double)u[(long long)n0 * ((j + 1 == n1 ? 0 : j + 1) + (long long)n1 * k) + i];
+        if constexpr (D >= 3) uz = (double)u[(long long)n0 * (j + (long long)n1 * (k + 1 == n2 ? 0 : k + 1)) + i];
+        if (!(fabs(uc) <= big)) bad = true;  // also catches NaN
+        // the cell's own |f_l'| (every cell is an end of a face along each axis)
+        w = fmax(w, P.adf(0, uc) * idx[0] + kdx2[0]);
+        if constexpr (D >= 2) w = fmax(w, P.adf(1, uc) * idx[1] + kdx2[1]);
+        if constexpr (D >= 3) w = fmax(w, P.adf(2, uc) * idx[2] + kdx2[2]);
+        bool gx = false;
+        if (open0 && i + 1 == n0) {
+            gx = I.bc[0][1] == 1;
+            ux = gx ? (double)(T)I.bcv[0][1] : uc;
         }
+        if (open0 && i == 0) {
+            const bool g = I.bc[0][0] == 1;
+            w = face(0, uc, g ? (double)(T)I.bcv[0][0] : uc, g, w);
+        }
+        w = face(0, uc, ux, gx, w);
+        if constexpr (D >= 2) {
+            bool gy = false;
+            if (open1 && j + 1 == n1) {
+                gy = I.bc[1][1] == 1;
+                uy = gy ? (double)(T)I.bcv[1][1] : uc;
+            }
+            if (open1 && j == 0) {
+                const bool g = I.bc[1][0] == 1;
+                w = face(1, uc, g ? (double)(T)I.bcv[1][0] : uc, g, w);
+            }
+            w = face(1, uc, uy, gy, w);
+        }
+        if constexpr (D >= 3) w = face(2, uc, uz, false, w);
     }
-    // one atomic per block (the blocks of an instance all update one
-    // address): the waves' maxima meet in LDS first
+    // the waves' maxima meet in LDS, then the block's goes to its slot
     constexpr int NW = kWaveThreads / 64;
     __shared__ double wb[NW];
     __shared__ int bb[NW];
@@ -119,12 +128,13 @@ __global__ void __launch_bounds__(kWaveThreads) wavespeed_kernel(const InstDev *
             m = fmax(m, wb[q]);
             anybad |= bb[q];
         }
-        if (m > 0.0) atomicMax(&st[ch.x].wmax, (unsigned long long)__double_as_longlong(m));
+        slots[blockIdx.x] = (unsigned long long)__double_as_longlong(m);
         if (anybad) atomicOr(&st[ch.x].flags, 1u);
     }
 }
 
-// One block per instance.  mm != nullptr: the wave speed comes from the min /
+// One block per instance.  wslots != nullptr: the wave speed is the max of
+// the instance's slots written by the wave-speed kernel.  mm != nullptr: the wave speed comes from the min /
 // max average written by the previous step's last stage, reduced here from
 // the per-wave slots of the instance's work items.  Valid when every |f_l'|
 // is convex on the bounds interval (linear and quadratic fluxes, no interior
@@ -138,7 +148,7 @@ __global__ void __launch_bounds__(kWaveThreads) wavespeed_kernel(const InstDev *
 template <int NT>
 __global__ void __launch_bounds__(NT) finalize_kernel(const InstDev *inst, const StepCtl *ctl, const double *dtp,
                                                       InstState *st, int dim, int prec, const unsigned long long *mm,
-                                                      int waves_per_block)
+                                                      const unsigned long long *wslots, int waves_per_block)
 {
     const int i = blockIdx.x;
     const InstDev &I = inst[i];
@@ -146,8 +156,30 @@ __global__ void __launch_bounds__(NT) finalize_kernel(const InstDev *inst, const
     // load latencies overlap
     const double te = ctl->t_end, dpre = dtp[i], t0 = st[i].t, cfl = I.cfl;
     const int prescribed = ctl->prescribed;
-    double w = __longlong_as_double((long long)st[i].wmax);
+    double w = 0.0;
     double lo = 0.0, hi = 0.0;
+    if (wslots) {
+        constexpr int NW = NT / 64;
+        __shared__ unsigned long long kw[NW];
+        unsigned long long b = 0ull;
+        const int n = I.ccount;
+        const unsigned long long *m = wslots + I.cstart;
+        for (int k0 = threadIdx.x; k0 < n; k0 += 4 * NT) {
+            unsigned long long v[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) v[j] = k0 + NT * j < n ? m[k0 + NT * j] : 0ull;
+#pragma unroll
+            for (int j = 0; j < 4; j++) b = max(b, v[j]);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) b = max(b, (unsigned long long)__shfl_xor((long long)b, o));
+        if ((threadIdx.x & 63) == 0) kw[threadIdx.x >> 6] = b;
+        __syncthreads();
+        b = kw[0];
+#pragma unroll
+        for (int q = 1; q < NW; q++) b = max(b, kw[q]);
+        w = __longlong_as_double((long long)b);
+    }
     if (mm) {
         // slot pairs of the instance: four independent loads in flight per
         // thread, then a wave and a block reduction
@@ -212,7 +244,6 @@ __global__ void __launch_bounds__(NT) finalize_kernel(const InstDev *inst, const
     } else {
         dt = w > 0.0 ? cfl / w : (te > 0.0 ? te - t0 : 0.0);
     }
-    st[i].wmax = 0ull;
     if (te > 0.0) {
         const double rem = te - t0;
         if (rem <= 1e-12 * te) dt = 0.0;  // remainder is rounding, not a step
@@ -330,28 +361,34 @@ __global__ void norms_final_kernel(const double *partials, int nblocks, double *
 }
 
 hipError_t wavespeed_launch(int dim, int prec, const InstDev *inst, const int2 *chunks, int nchunks, const void *U,
-                            InstState *st, hipStream_t s)
+                            InstState *st, unsigned long long *slots, hipStream_t s)
 {
     if (nchunks <= 0) return hipSuccess;
-    if (prec == 32)
-        hipLaunchKernelGGL(wavespeed_kernel<float>, dim3(nchunks), dim3(kWaveThreads), 0, s, inst, chunks, (const float *)U, st,
-                           dim);
-    else
-        hipLaunchKernelGGL(wavespeed_kernel<double>, dim3(nchunks), dim3(kWaveThreads), 0, s, inst, chunks, (const double *)U,
-                           st, dim);
+    const dim3 g(nchunks), b(kWaveThreads);
+    if (prec == 32) {
+        const float *u = (const float *)U;
+        if (dim == 1) hipLaunchKernelGGL((wavespeed_kernel<float, 1>), g, b, 0, s, inst, chunks, u, st, slots);
+        else if (dim == 2) hipLaunchKernelGGL((wavespeed_kernel<float, 2>), g, b, 0, s, inst, chunks, u, st, slots);
+        else hipLaunchKernelGGL((wavespeed_kernel<float, 3>), g, b, 0, s, inst, chunks, u, st, slots);
+    } else {
+        const double *u = (const double *)U;
+        if (dim == 1) hipLaunchKernelGGL((wavespeed_kernel<double, 1>), g, b, 0, s, inst, chunks, u, st, slots);
+        else if (dim == 2) hipLaunchKernelGGL((wavespeed_kernel<double, 2>), g, b, 0, s, inst, chunks, u, st, slots);
+        else hipLaunchKernelGGL((wavespeed_kernel<double, 3>), g, b, 0, s, inst, chunks, u, st, slots);
+    }
     return hipGetLastError();
 }
 
 hipError_t finalize_launch(int n_inst, const InstDev *inst, const StepCtl *ctl, const double *dtp, InstState *st,
-                           int dim, int prec, const unsigned long long *mm, int waves_per_block, long long max_slots,
-                           hipStream_t s)
+                           int dim, int prec, const unsigned long long *mm, const unsigned long long *wslots,
+                           int waves_per_block, long long max_slots, hipStream_t s)
 {
-    if (mm && max_slots > 16384)
+    if (max_slots > 16384)
         hipLaunchKernelGGL(finalize_kernel<1024>, dim3(n_inst), dim3(1024), 0, s, inst, ctl, dtp, st, dim, prec, mm,
-                           waves_per_block);
+                           wslots, waves_per_block);
     else
         hipLaunchKernelGGL(finalize_kernel<256>, dim3(n_inst), dim3(256), 0, s, inst, ctl, dtp, st, dim, prec, mm,
-                           waves_per_block);
+                           wslots, waves_per_block);
     return hipGetLastError();
 }
 

@@ -40,8 +40,9 @@ hipError_t stage_launch_d2(int prec, bool lim, bool si, unsigned caps, int varia
 hipError_t stage_launch_d3(int prec, bool lim, bool si, unsigned caps, int variant, int nblocks, const void *params, hipStream_t s);
 
 // FP64 max over faces of alpha_l/dx_l + kappa_max/dx_l^2 of the averages of
-// U (per instance, into InstState::wmax), plus the divergence check.
-constexpr int kWaveChunk = 2048;  // cells per wave-speed block (about)
+// U, one slot per chunk (the bits of the chunk's max), plus the divergence
+// check.
+constexpr int kWaveChunk = 512;   // cells per wave-speed block (about)
 constexpr int kWaveThreads = 256;  // threads per wave-speed block (four waves)
 // Cells of wave-speed chunk k of an instance whose rows hold n0 cells
 // (nrows rows): whole rows [r0, r1) when a row holds at most kWaveChunk
@@ -75,17 +76,19 @@ __host__ __device__ inline WaveChunk wave_chunk(int n0, long long nrows, long lo
     return c;
 }
 hipError_t wavespeed_launch(int dim, int prec, const InstDev *inst, const int2 *chunks, int nchunks, const void *U,
-                            InstState *st, hipStream_t s);
+                            InstState *st, unsigned long long *slots, hipStream_t s);
 
 // dt and t of every instance from the wave speeds (or the prescribed steps);
-// mm != nullptr: from the min / max average slots written by the previous
-// step's last stage (waves_per_block slot pairs per work item) instead of the
-// wave-speed kernel (fluxes with convex |f'| only); prec: storage precision
+// wslots != nullptr: from the chunk slots of the wave-speed kernel
+// (InstDev::cstart / ccount); mm != nullptr: from the min / max average slots
+// written by the previous step's last stage (waves_per_block slot pairs per
+// work item) instead (fluxes with convex |f'| only); prec: storage precision
 // (the Dirichlet ghost values enter the min / max as stored); max_slots: the
-// largest number of slot pairs of one instance (sizes the reduction).
+// largest number of slots of one instance on the path taken (sizes the
+// reduction).
 hipError_t finalize_launch(int n_inst, const InstDev *inst, const StepCtl *ctl, const double *dtp, InstState *st,
-                           int dim, int prec, const unsigned long long *mm, int waves_per_block, long long max_slots,
-                           hipStream_t s);
+                           int dim, int prec, const unsigned long long *mm, const unsigned long long *wslots,
+                           int waves_per_block, long long max_slots, hipStream_t s);
 
 // dst = src over n values.
 hipError_t copy_launch(int prec, const void *src, void *dst, long long n, hipStream_t s);
