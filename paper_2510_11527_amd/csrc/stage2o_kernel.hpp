@@ -150,12 +150,17 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     };
     auto st = [&](int z, unsigned gi, T v) { buf_store<T>(rout, gi * (unsigned)sizeof(T), (unsigned)z * kb, v); };
     // periodic indices: one fold when the grid is wider than a tile plus its
-    // halo (the usual case), a remainder otherwise
+    // halo (the usual case); narrower grids fold on in a loop behind a
+    // uniform branch (no integer division: its expansion, if-converted, cost
+    // every thread some 25 instructions per index)
     const bool fold0 = n0 >= TX + 4, fold1 = n1 >= TY + 4;
     auto wrap = [&](int v, int n, bool fold) -> int {
-        if (fold) return v < 0 ? v + n : (v >= n ? v - n : v);
-        const int r = v % n;
-        return r < 0 ? r + n : r;
+        int r = v < 0 ? v + n : (v >= n ? v - n : v);
+        if (!fold) {
+            while (r < 0) r += n;
+            while (r >= n) r -= n;
+        }
+        return r;
     };
     // own cells: region column x, rows y and y + 1
     const int ci = tid % TX, cj = 2 * (tid / TX);
