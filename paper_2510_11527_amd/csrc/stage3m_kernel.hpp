@@ -66,7 +66,14 @@ struct MGeo {
 
     __device__ static __forceinline__ int ub(int u, int v) { return (u + HZ) + RX * (v + HZ); }
     // half-plane point at tile-local half indices p = 2u + bx, q = 2v + by
-    __device__ static __forceinline__ int hp(int p, int q) { return (p + 4) + HX * (q + 4); }
+    // (p, q >= -4), stored in the cell-indexed sub-grid of its parity (bx,
+    // by): the points that a wave reads at one stencil offset are then
+    // consecutive words, not every other one (LDS bank conflicts)
+    static constexpr int SW = TX + 3, SUB = SW * (TY + 3);
+    __device__ static __forceinline__ int hp(int p, int q)
+    {
+        return ((p & 1) + 2 * (q & 1)) * SUB + ((p + 4) >> 1) + SW * ((q + 4) >> 1);
+    }
 };
 
 // LDS bytes of a marching-kernel instantiation
