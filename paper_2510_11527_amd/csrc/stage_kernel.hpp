@@ -399,9 +399,11 @@ __device__ __forceinline__ void minmax_slot(unsigned long long *mm, int item, T 
     }
 }
 
-// Wave-wide max of a non-negative double, then one atomic per wave.
+// Wave-wide max of a non-negative double, then one atomic per wave; a wave
+// whose lanes all hold 0 (the usual case: no safeguard clamp) skips both.
 __device__ __forceinline__ void atomic_max_wave(unsigned long long *dst, double v)
 {
+    if (!__any(v > 0.0)) return;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     if ((threadIdx.x & 63) == 0 && v > 0.0) atomicMax(dst, (unsigned long long)__double_as_longlong(v));
@@ -413,6 +415,7 @@ template <class T>
 __device__ __forceinline__ void atomic_max_wave_t(unsigned long long *dst, T v)
 {
     if constexpr (sizeof(T) == 4) {
+        if (!__any(v > T(0))) return;
         const unsigned m = wave_umax(__float_as_uint(v));
         if ((threadIdx.x & 63) == 0 && m != 0u)
             atomicMax(dst, (unsigned long long)__double_as_longlong((double)__uint_as_float(m)));
