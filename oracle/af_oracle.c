@@ -26,9 +26,10 @@
  *
  * Smoothness-indicator blending (Sec. 5.1.3) of the point values defers its
  * low-order scheme to other work; the one here is a reading (LLF on the
- * half grid, a cell average for a cell centre).  Its gamma -> inf limit and
- * its 1D weight are pinned by the tests; the multi-D point weights at finite
- * gamma > 0 (means of s over 2 to 8 cells) are parity unpinned.
+ * half grid, a cell average for a cell centre).  Its gamma -> inf limit, its
+ * 1D weight and, by reduction to 1D, the weights of the face points in 2D
+ * and 3D are pinned by the tests; the edge and corner point weights at
+ * finite gamma > 0 (means of s over 4 to 8 cells) are parity unpinned.
  *
  * Half-grid reading (used by the paper's "half-index shifts", Sec. 4): along
  * axis l, the points x_{i-1/2}, x_i, x_{i+1/2}, x_{i+1}, ... form a uniform

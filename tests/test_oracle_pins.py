@@ -1170,6 +1170,62 @@ def test_si_1d_point_value_weight_is_the_printed_face_coefficient(gamma):
     np.testing.assert_allclose((Vg - Vi)[use] / span[use], want[use], rtol=1e-7)
 
 
+def _embed_along(d, a, shape, ub, up, ctr):
+    """Multi-D DoFs (zeta order) of data varying along axis a only: averages
+    ub, points on the faces normal to a (mask bit a set) up, every other
+    point at the cell centre along a (ctr, the Simpson inversion)."""
+    masks = [0, 1, 2, 3] if d == 2 else [0, 1, 2, 4, 3, 5, 6, 7]
+    bshape = [1] * d
+    bshape[d - 1 - a] = shape[a]   # arrays are x fastest: numpy axes are (z, y, x)
+    full = tuple(shape[d - 1 - k] for k in range(d))
+    out = []
+    for m in masks:
+        v = ub if m == 0 else (up if (m >> a) & 1 else ctr)
+        out.append(np.broadcast_to(v.reshape(bshape), full).reshape(-1).copy())
+    return out
+
+
+@pytest.mark.parametrize("gamma", [0.7, 5.0])
+@pytest.mark.parametrize("d,a", [(2, 0), (2, 1), (3, 0), (3, 1), (3, 2)])
+def test_si_multid_data_along_one_axis_reproduces_1d(d, a, gamma):
+    """Reading R12 in several dimensions: for data that vary along one axis
+    only, the blended and limited multi-D stage reproduces the 1D one for the
+    averages and for the point values on the faces normal to that axis.  The
+    1D stage's point weight is pinned to the printed face coefficient
+    (test_si_1d_point_value_weight_is_the_printed_face_coefficient); this
+    test carries it to the face points of 2D and 3D, where the weight's mean
+    runs over the cells whose closure holds the point and the low-order
+    neighbours are found on the multi-D half grid.  A weight taken from
+    another direction's indicator fails it (checked by planting that mistake
+    in the oracle).  Edge and corner points keep reconstructed centres as
+    their low-order neighbours, so they are not the 1D face points: their
+    weights at finite gamma stay unpinned."""
+    n = 11
+    rng = np.random.default_rng(50 + 10 * d + a)
+    ub, up = rng.uniform(0.15, 0.85, n), rng.uniform(0.15, 0.85, n)
+    ctr = (6 * ub - np.roll(up, 1) - up) / 4
+    flux, diff = ("quad", 0.5, 0.0), ("power", 0.02, 2.0)
+    L = 1.0
+    s1 = spec1d(n, L, flux, diff, umin=0.0, umax=1.0, limiter=True, si=True, si_gamma=gamma)
+    shape = [5, 6, 4][:d]
+    shape[a] = n
+    lo, hi = [0.0] * d, [0.7, 0.9, 0.8][:d]
+    hi[a] = L
+    sd = dict(dim=d, n=shape, lo=lo, hi=hi, flux=[flux] * d, diff=diff, umin=0.0, umax=1.0, limiter=True,
+              si=True, si_gamma=gamma)
+    dt = 0.02 / n
+    V1, _ = oracle.fe(oracle.problem(s1), [ub, up], dt)
+    Ud = _embed_along(d, a, shape, ub, up, ctr)
+    Vd, _ = oracle.fe(oracle.problem(sd), Ud, dt)
+    face_kind = {0: 1, 1: 2, 2: 3}[a]
+    ref = _embed_along(d, a, shape, V1[0], V1[1], V1[1])
+    np.testing.assert_allclose(Vd[0], ref[0], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(Vd[face_kind], ref[face_kind], rtol=0, atol=1e-14)
+    # the blending is active: the same data at gamma = 0 give other face values
+    V0, _ = oracle.fe(oracle.problem(dict(sd, si_gamma=0.0)), Ud, dt)
+    assert np.abs(V0[face_kind] - Vd[face_kind]).max() > 1e-6
+
+
 # ---------------------------------------------------------------------------
 # Open ends in 2D (the rule is the 1D one applied along each axis; corners
 # and edges take the mean of the boundary cells around the clamped point)
