@@ -22,14 +22,15 @@ namespace af4 {
 constexpr int count_variant(int dim) { return dim == 2 ? 5 : dim == 3 ? 6 : 0; }
 
 // 3D: KIND 1 = the kernel that marches along z (fluxes c1 u + c2 u^2; TZ is
-// the number of cell planes a workgroup walks; two threads per (x, y)
-// column), 0 = generic kernel (any flux).  The generic 8x8x8 tile (125 KiB of
-// LDS with SI blending in FP32) does not fit in FP64, where 8x8x4 is the
-// first generic tile built.
+// the number of cell planes a workgroup walks: longer walks re-read fewer
+// planes below their first, shorter ones give small grids more workgroups;
+// two threads per (x, y) column), 0 = generic kernel (any flux).  The
+// generic 8x8x8 tile (125 KiB of LDS with SI blending in FP32) does not fit
+// in FP64, where 8x8x4 is the first generic tile built.
 #define AF4_VARIANTS_D3(X)                                                                            \
     X(0, 16, 8, 32, 256, 1, "3d-march-16x8x32") X(1, 16, 8, 64, 256, 1, "3d-march-16x8x64")            \
-    X(2, 8, 8, 32, 128, 1, "3d-march-8x8x32") X(3, 16, 16, 32, 512, 1, "3d-march-16x16x32")            \
-    X(4, 32, 8, 32, 512, 1, "3d-march-32x8x32") X(5, 8, 8, 8, 512, 0, "generic-8x8x8")                  \
+    X(2, 8, 8, 32, 128, 1, "3d-march-8x8x32") X(3, 16, 8, 128, 256, 1, "3d-march-16x8x128")            \
+    X(4, 16, 8, 256, 256, 1, "3d-march-16x8x256") X(5, 8, 8, 8, 512, 0, "generic-8x8x8")                  \
     X(6, 8, 8, 4, 256, 0, "generic-8x8x4") X(7, 8, 4, 4, 128, 0, "generic-8x4x4")                       \
     X(8, 4, 4, 4, 64, 0, "generic-4x4x4")
 
