@@ -225,12 +225,13 @@ def test_argument_validation():
     ctx.close()
 
 
-@pytest.mark.parametrize("d,fl", [(1, 2), (2, 0), (2, 2), (3, 0)])
-def test_tile_variants_agree(d, fl):
+@pytest.mark.parametrize("d,fl,n", [(1, 2, 300), (2, 0, 70), (2, 2, 70), (3, 0, 20), (3, 0, 36)])
+def test_tile_variants_agree(d, fl, n):
     """Tile shapes of one kernel family compute the same per-cell arithmetic
-    (identical bits); different families agree to the parity tolerance."""
-    rng = np.random.default_rng(d + 10 * fl)
-    n = {1: 300, 2: 70, 3: 20}[d]
+    (identical bits); different families agree to the parity tolerance.  In
+    3D, 20 cells per axis fit one z walk of every marching tile; 36 give the
+    32-plane walks a ragged last walk and every tile ragged x and y edges."""
+    rng = np.random.default_rng(d + 10 * fl + n)
     spec = small_spec(d, n, FLUXES[fl], DIFFS[1], limiter=True, precision=32)
     U = state_for(spec, rng)
     s, U = prepare(spec, U, 32)
