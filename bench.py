@@ -384,7 +384,7 @@ def main():
                     help="comma-separated workloads (c2,c3,c5): end-of-run accuracy report instead of the benchmark")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("bench.py: the library drives one GPU; --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     from paper_2510_11527_amd import af

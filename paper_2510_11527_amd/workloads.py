@@ -385,7 +385,7 @@ def barenblatt_value(m, d, x2, t):
 def barenblatt(d, m, n=80, t=1.0, sub=8, limiter=True):
     """Example 6.3 on [-L, L]^d (L = 6, 8, 10), initial data B_m(., t),
     averages by sub^d midpoint sub-sampling, point values sampled.  The
-    support stays well inside the box for t <= 2, so periodic wrap-around
+    support stays well inside the domain for t <= 2, so periodic wrap-around
     does not interact with it."""
     Lh = {1: 6.0, 2: 8.0, 3: 10.0}[d]
     spec = dict(name="ex63_barenblatt_%dd_m%d" % (d, m), dim=d, n=[n] * d, lo=[-Lh] * d, hi=[Lh] * d,

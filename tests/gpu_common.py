@@ -8,7 +8,7 @@ from paper_2510_11527_amd import workloads as W
 
 TOL = {64: 1e-12, 32: 1e-5}   # relative l1 over all DoFs, vs the FP64 oracle
 
-# Element-wise bar next to the relative l1 (derivation in the design notes):
+# Element-wise bar next to the relative l1:
 # FP64 |gpu - oracle| <= 1e-12 max(1, |u|max); FP32 <= K_STAGE * stages *
 # 2^-23 max(1, |u|max): one stage rounds each output along a chain of at most
 # ~30 operations whose terms sum to at most ~7.5 max|u| (CFL <= 1/(2d)), i.e.
