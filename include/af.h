@@ -207,8 +207,8 @@ af_status af_residual(af_ctx *ctx, int inst, double *const *rhs);
  * Props 5.1/5.2 on periodic meshes), min/max of the averages and of the point
  * values (the bounds of Def. 5.1), the l1/l2/linf norms of the averages, the
  * time, last step and step count, the largest safeguard clamp and a
- * non-finite flag.  Sums are reduced in a fixed order (bitwise
- * reproducible).  Synchronizes the context stream. */
+ * non-finite flag.  Sums are compensated (Neumaier) and reduced in a fixed
+ * order (bitwise reproducible).  Synchronizes the context stream. */
 af_status af_norms(af_ctx *ctx, int inst, af_norms_t *out);
 
 /* For callers that cannot allocate device memory (code under HIP graph
