@@ -23,7 +23,12 @@ def hip():
         H.hipMemcpy.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int]
         H.hipStreamCreate.argtypes = [ctypes.POINTER(vp)]
         H.hipStreamDestroy.argtypes = [vp]
-        for f in ("hipMalloc", "hipFree", "hipMemcpy", "hipStreamCreate", "hipStreamDestroy", "hipDeviceSynchronize"):
+        H.hipHostMalloc.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t, ctypes.c_uint]
+        H.hipHostFree.argtypes = [vp]
+        H.hipMemcpyAsync.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int, vp]
+        H.hipStreamSynchronize.argtypes = [vp]
+        for f in ("hipMalloc", "hipFree", "hipMemcpy", "hipStreamCreate", "hipStreamDestroy", "hipDeviceSynchronize",
+                  "hipHostMalloc", "hipHostFree", "hipMemcpyAsync", "hipStreamSynchronize"):
             getattr(H, f).restype = ctypes.c_int
         _hip = H
     return _hip
@@ -59,3 +64,19 @@ class DeviceBlock:
 
     def free(self):
         assert hip().hipFree(self.ptr) == 0
+
+
+class PinnedBuffer:
+    """Page-locked host memory (hipHostMalloc) seen as a numpy array."""
+
+    def __init__(self, nbytes):
+        self.ptr = ctypes.c_void_p()
+        assert hip().hipHostMalloc(ctypes.byref(self.ptr), nbytes, 0) == 0
+        self.nbytes = nbytes
+
+    def array(self, dtype, count):
+        buf = (ctypes.c_char * self.nbytes).from_address(self.ptr.value)
+        return np.frombuffer(buf, dtype=dtype, count=count)
+
+    def free(self):
+        assert hip().hipHostFree(self.ptr) == 0

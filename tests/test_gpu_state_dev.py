@@ -13,7 +13,9 @@ import sys
 import numpy as np
 import pytest
 
-from hip_mem import DeviceBlock
+import ctypes
+
+from hip_mem import D2H, H2D, DeviceBlock, PinnedBuffer, hip
 from paper_2510_11527_amd import af
 from paper_2510_11527_amd import workloads as W
 
@@ -111,3 +113,39 @@ def test_fp32_rounding_overflow_is_rejected_on_both_paths():
     B.free()
     assert e.value.status == af.AF_ERR_NONFINITE
     ctx.close()
+
+
+def test_device_state_waits_for_the_callers_stream():
+    """The DoFs reach the device arrays by an asynchronous copy on the
+    caller's stream (from page-locked memory), and af_set_state_dev is
+    called right after it without any synchronization: the call must wait
+    for that stream.  The read-back by af_get_state_dev goes to arrays the
+    caller then copies on the same stream."""
+    spec, U = W.config2(n=96)
+    ref = af.Context(spec)
+    ref.set_state(0, U)
+    Vref, _ = ref.get_state(0)
+    ref.close()
+    n, k = U[0].size, len(U)
+    stream = ctypes.c_void_p()
+    assert hip().hipStreamCreate(ctypes.byref(stream)) == 0
+    pin = PinnedBuffer(8 * n * k)
+    host = pin.array(np.float64, n * k)
+    host[:] = np.concatenate([np.asarray(u, dtype=np.float64) for u in U])
+    B = DeviceBlock([np.zeros(n)] * k, 64, pad=0)
+    assert hip().hipMemcpyAsync(B.ptr, pin.ptr, 8 * n * k, H2D, stream) == 0
+    ctx = af.Context(spec)
+    ctx.set_state_dev(0, B.kinds(), t=0.0, stream_ptr=stream.value)
+    V, _ = ctx.get_state(0)
+    assert states_equal(V, Vref)
+    host[:] = np.nan
+    assert hip().hipMemcpyAsync(B.ptr, pin.ptr, 8 * n * k, H2D, stream) == 0   # NaN in the arrays
+    ctx.get_state_dev(0, B.kinds(), stream_ptr=stream.value)                   # ordered after that copy
+    assert hip().hipMemcpyAsync(pin.ptr, B.ptr, 8 * n * k, D2H, stream) == 0
+    assert hip().hipStreamSynchronize(stream) == 0
+    got = [host[z * n:(z + 1) * n].copy() for z in range(k)]
+    assert states_equal(got, Vref)
+    ctx.close()
+    B.free()
+    pin.free()
+    assert hip().hipStreamDestroy(stream) == 0
