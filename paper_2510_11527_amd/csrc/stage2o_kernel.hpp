@@ -237,13 +237,15 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
         mu[l] = prm(Sc->mu[l], Sc->f_mu[l]) * p.dts;
         nu[l] = prm(Sc->nu[l], Sc->f_nu[l]) * p.dts;
     }
-    // K = 2 d = 4: the LLF states use K mu, theta^c and theta^d 3 K mu and 3 K nu
-    T kmu[2], k3mu[2], k3nu[2];
+    // K = 2 d = 4: the LLF states use K mu; theta^c and theta^d move their
+    // states by 3 K mu and 3 K nu times the correction (their reciprocals,
+    // once per thread, scale the gaps)
+    T kmu[2], ik3mu[2], ik3nu[2];
 #pragma unroll
     for (int l = 0; l < 2; l++) {
         kmu[l] = T(4) * mu[l];
-        k3mu[l] = T(12) * mu[l];
-        k3nu[l] = T(12) * nu[l];
+        ik3mu[l] = fast_rcp(T(12) * mu[l]);
+        ik3nu[l] = fast_rcp(T(12) * nu[l]);
     }
 
     // the stage's combination (stage_combine): a forward-Euler stage is the
@@ -592,10 +594,9 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
             if (!residual) {
                 if constexpr (BQ) fL = c2[l] * (A.x * A.x) - D * gmh;
                 const T df = fH - fL;
-                const T s3 = k3mu[l] * df;
-                // up moves by -s3, um by +s3
-                const T gap = gap2<T>(s3, um, up, umin, umax);
-                F = fL + theta_from_gap<T>(gap, (T)fabs(s3)) * df;
+                // up moves by -3 K mu theta df, um by +3 K mu theta df
+                const T gap = gap2<T>(df, um, up, umin, umax);
+                F = fL + limited_part<T>(gap, df, ik3mu[l]);
             }
         }
         if constexpr (!LIM) fl[id] = F;
@@ -642,10 +643,9 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
                 const int f1 = l == 0 ? FG::fx(b) : FG::fy(b);
                 const T pL = ulp[f0], mC = ulm[f0], pC = ulp[f1], mR = ulm[f1];
                 const T da = aH - aL;
-                const T s = k3nu[l] * da;
-                // pL, mR move by +s; pC, mC by -s
-                const T gap = gap4<T>(s, pL, mR, pC, mC, umin, umax);
-                Pv = aL + theta_from_gap<T>(gap, (T)fabs(s)) * da;
+                // pL, mR move by +3 K nu theta da; pC, mC by -3 K nu theta da
+                const T gap = gap4<T>(da, pL, mR, pC, mC, umin, umax);
+                Pv = aL + limited_part<T>(gap, da, ik3nu[l]);
             }
         }
         const int id = l == 0 ? FG::px(b) : FG::py(b);

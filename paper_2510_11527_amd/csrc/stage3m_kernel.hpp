@@ -183,6 +183,14 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
         mu[l] = (T)p.st[wk.x].mu[l] * p.dts;
         nu[l] = (T)p.st[wk.x].nu[l] * p.dts;
     }
+    // theta^c and theta^d move their states by 3 K mu and 3 K nu times the
+    // correction; their reciprocals scale the gaps
+    T ik3mu[3], ik3nu[3];
+#pragma unroll
+    for (int l = 0; l < 3; l++) {
+        ik3mu[l] = fast_rcp(T(3) * K * mu[l]);
+        ik3nu[l] = fast_rcp(T(3) * K * nu[l]);
+    }
     const bool use_si = SI && !residual;
     const bool lim = LIM && !residual;
     const T gam8 = (T)I.si_gamma * T(0.125);
@@ -388,9 +396,8 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
                 T Pv = aH;
                 if (lim) {
                     const T da = aH - aL;
-                    const T s3v = T(3) * K * nu[2] * da;
-                    const T gap = gap4<T>(s3v, sZP[fl][o], sZM[fu][o], sZP[fu][o], sZM[fl][o], P.umin, P.umax);
-                    Pv = aL + theta_from_gap<T>(gap, (T)fabs(s3v)) * da;
+                    const T gap = gap4<T>(da, sZP[fl][o], sZM[fu][o], sZP[fu][o], sZM[fl][o], P.umin, P.umax);
+                    Pv = aL + limited_part<T>(gap, da, ik3nu[2]);
                 }
                 sPZ[s3(k + 1)][o] = Pv;
             });
@@ -417,9 +424,8 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
                 T F = fH;
                 if (lim) {
                     const T df = fH - fL;
-                    const T s3v = T(3) * K * mu[2] * df;
-                    const T gap = gap2<T>(s3v, sZM[fs][o], sZP[fs][o], P.umin, P.umax);
-                    F = fL + theta_from_gap<T>(gap, (T)fabs(s3v)) * df;
+                    const T gap = gap2<T>(df, sZM[fs][o], sZP[fs][o], P.umin, P.umax);
+                    F = fL + limited_part<T>(gap, df, ik3mu[2]);
                 }
                 sFZ[fs][o] = F;
             });
@@ -464,8 +470,7 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
                 T F = fH;
                 if (lim) {
                     const T df = fH - fL;
-                    const T s3v = T(3) * K * mu[0] * df;
-                    F = fL + theta_from_gap<T>(gap2<T>(s3v, um, up, P.umin, P.umax), (T)fabs(s3v)) * df;
+                    F = fL + limited_part<T>(gap2<T>(df, um, up, P.umin, P.umax), df, ik3mu[0]);
                 }
                 sXF[fi] = F;
             });
@@ -505,8 +510,7 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
                 T F = fH;
                 if (lim) {
                     const T df = fH - fL;
-                    const T s3v = T(3) * K * mu[1] * df;
-                    F = fL + theta_from_gap<T>(gap2<T>(s3v, um, up, P.umin, P.umax), (T)fabs(s3v)) * df;
+                    F = fL + limited_part<T>(gap2<T>(df, um, up, P.umin, P.umax), df, ik3mu[1]);
                 }
                 sYF[fi] = F;
             });
@@ -543,9 +547,8 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
                     // faces u -+ 1/2 (left cells u-1, u)
                     const int f0 = (u + 1) + G::FXW * v;
                     const T da = aH - aL;
-                    const T s3v = T(3) * K * nu[0] * da;
-                    const T gap = gap4<T>(s3v, sXP[f0], sXM[f0 + 1], sXP[f0 + 1], sXM[f0], P.umin, P.umax);
-                    Pv = aL + theta_from_gap<T>(gap, (T)fabs(s3v)) * da;
+                    const T gap = gap4<T>(da, sXP[f0], sXM[f0 + 1], sXP[f0 + 1], sXM[f0], P.umin, P.umax);
+                    Pv = aL + limited_part<T>(gap, da, ik3nu[0]);
                 }
                 sPX[x + G::PXW * v] = Pv;
             });
@@ -574,9 +577,8 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
                 if (lim) {
                     const int f0 = u + G::FYW * (v + 1);
                     const T da = aH - aL;
-                    const T s3v = T(3) * K * nu[1] * da;
-                    const T gap = gap4<T>(s3v, sYP[f0], sYM[f0 + G::FYW], sYP[f0 + G::FYW], sYM[f0], P.umin, P.umax);
-                    Pv = aL + theta_from_gap<T>(gap, (T)fabs(s3v)) * da;
+                    const T gap = gap4<T>(da, sYP[f0], sYM[f0 + G::FYW], sYP[f0 + G::FYW], sYM[f0], P.umin, P.umax);
+                    Pv = aL + limited_part<T>(gap, da, ik3nu[1]);
                 }
                 sPY[u + G::PYW * y] = Pv;
             });

@@ -210,8 +210,25 @@ __device__ __forceinline__ T theta_from_gap(T gap, T s)
     return fmin(fmax(gap, T(0)) * fast_rcp(s), T(1));
 }
 
+// theta d of a limited correction d whose states move by k theta d (k > 0):
+// theta = min(1, max(gap, 0) / (k |d|)) gives
+//   theta d = sign(d) min(|d|, max(gap, 0) / k),
+// evaluated with ik = 1/k of the block, so no reciprocal per item (the gap
+// scaled by ik is clamped into [0, |d|], then takes the sign of d).  The
+// states then move by at most gap (k ik), i.e. within an ulp of the gap.
+// k = 0 (no step) gives 0 or |d|; a stage without a step does not use it.
+template <class T>
+__device__ __forceinline__ T limited_part(T gap, T d, T ik)
+{
+    T m;
+    if constexpr (sizeof(T) == 4) m = __builtin_amdgcn_fmed3f(gap * ik, 0.0f, __builtin_fabsf(d));
+    else m = fmin(fmax(gap * ik, T(0)), fabs(d));
+    return copysign(m, d);
+}
+
 // smallest distance to the bound that a correction of sign(s) moves the
-// states z+ (moved by +s) and z- (moved by -s) towards
+// states z+ (moved by +s) and z- (moved by -s) towards (only the sign of s
+// is used: any positive multiple of the correction will do)
 template <class T>
 __device__ __forceinline__ T gap2(T s, T zp, T zm, T umin, T umax)
 {
