@@ -88,8 +88,11 @@ struct Own2Geo {
     __device__ static __forceinline__ int py(int b) { return NXC + b - 2 - SX; }
 };
 
-template <class T, bool LIM, int FL, int TX, int TY, int NT>
-__global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
+// WPE: the waves per SIMD the register allocation must allow (1: the
+// compiler's choice; a higher target trades registers, and possibly spills,
+// for occupancy)
+template <class T, bool LIM, int FL, int TX, int TY, int NT, int WPE = 1>
+__global__ void __launch_bounds__(NT, WPE) stage2o_kernel(StageParams<T> p)
 {
     // GEN: Buckley-Leverett fluxes f_l = q (1 - g_l (1-u)^2), q = u^2 / (u^2 +
     // (1-u)^2) (g_l = 0 without gravity), one branch-free form with the
