@@ -255,8 +255,9 @@ __global__ void __launch_bounds__(NT, WPE) stage2o_kernel(StageParams<T> p)
     // blend with X0 = 0 (empty range above) and w = 1, exactly v
     const T wb = p.mode == kCombFE ? T(1) : p.w;
     const bool summing = p.mode == kCombSum;
-    auto combine = [&](T v, T x0, T x1, T vin) -> T {
-        if (summing) return ((p.c0 * x0 + p.c1 * x1) + p.cin * vin) + p.w * v;
+    // (X1 of DoF kind z at global cell gi is read here, by summing stages)
+    auto combine = [&](T v, T x0, int z, unsigned gi, T vin) -> T {
+        if (summing) return ((p.c0 * x0 + p.c1 * ld(rx1, z, gi)) + p.cin * vin) + p.w * v;
         return x0 + wb * (v - x0);
     };
 
@@ -373,25 +374,16 @@ __global__ void __launch_bounds__(NT, WPE) stage2o_kernel(StageParams<T> p)
 #pragma unroll
         for (int z = 0; z < 4; z++) halo[k][z] = ld(rin, z, gi);
     }
-    // X0 (U^n) and X1 of the own cells for the stage's combination (a stage
-    // that does not combine reads X0 too, from cache: the load sequence up to
-    // here stays free of branches, so the waits above stay exact; X1, needed
-    // by summing stages only, comes last)
-    T unv[2][4], x1v[2][4];
+    // X0 (U^n) of the own cells for the stage's combination (a stage that
+    // does not combine reads X0 too, from cache: the load sequence up to here
+    // stays free of branches, so the waits above stay exact).  X1, needed by
+    // summing stages only, is loaded where it is combined, so that no
+    // registers hold it through the point-value phase.
+    T unv[2][4];
 #pragma unroll
     for (int z = 0; z < 4; z++) {
         unv[0][z] = ld(run, z, g0);
         unv[1][z] = ld(run, z, g1);
-    }
-    if (p.x1) {
-#pragma unroll
-        for (int z = 0; z < 4; z++) {
-            x1v[0][z] = ld(rx1, z, g0);
-            x1v[1][z] = ld(rx1, z, g1);
-        }
-    } else {
-#pragma unroll
-        for (int z = 0; z < 4; z++) x1v[0][z] = x1v[1][z] = T(0);
     }
     if (open) {
         // values on or beyond open ends (own cells past a partial tile's
@@ -541,7 +533,7 @@ __global__ void __launch_bounds__(NT, WPE) stage2o_kernel(StageParams<T> p)
                 }
                 if (!isfinite(v)) bad = true;
                 if constexpr (LIM) v = clampb(v, umin, umaxv);
-                v = combine(v, unv[c][z], x1v[c][z], vin);
+                v = combine(v, unv[c][z], z, gi, vin);
                 if constexpr (LIM) v = clampb(v, umin, umaxv);
                 st(z, gi, v);
             }
@@ -712,7 +704,7 @@ __global__ void __launch_bounds__(NT, WPE) stage2o_kernel(StageParams<T> p)
             clamp_mag = fmax(clamp_mag, (T)fabs(cl - v));
             v = cl;
         }
-        v = combine(v, unv[c][0], x1v[c][0], u);
+        v = combine(v, unv[c][0], 0, gi, u);
         if constexpr (LIM) {
             const T cl = clampb(v, umin, umaxv);
             clamp_mag = fmax(clamp_mag, (T)fabs(cl - v));

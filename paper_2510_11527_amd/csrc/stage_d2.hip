@@ -59,8 +59,9 @@ hipError_t launch_own_lim(bool lim, int nblocks, const void *params, hipStream_t
 }
 
 // waves per SIMD that the occupancy-targeted own-items tiles (KIND 5) ask of
-// the register allocation: four in FP32, two in FP64 (the Buckley-Leverett
-// instantiations otherwise take 149 and 290 registers: three waves and one)
+// the register allocation: four in FP32, two in FP64 (left to the compiler,
+// the Buckley-Leverett instantiations take registers for three waves per
+// SIMD in FP32 and for one in FP64)
 template <class T>
 constexpr int own_wpe() { return sizeof(T) == 4 ? 4 : 2; }
 
@@ -73,6 +74,7 @@ hipError_t launch_kind(bool lim, bool si, unsigned caps, int nblocks, const void
     if constexpr (KIND == 4 || KIND == 5) {
         constexpr int WPE = KIND == 5 ? own_wpe<T>() : 1;
         if (si || !(caps & kCapI32) || !(qf || (caps & kCapBLF))) return hipErrorInvalidValue;
+        if (KIND == 5 && qf) return hipErrorInvalidValue;  // fits the target already
         const int fl = (!qf ? kOwnGen : 0) | ((caps & kCapPP) ? kOwnPP : 0) | ((qf && (caps & kCapBQ)) ? kOwnBQ : 0) |
                        ((caps & kCapOpen) ? kOwnOpen : 0);
         switch (fl) {
@@ -114,6 +116,10 @@ bool fits_kind(bool lim, bool si, unsigned caps)
     if (KIND != 0 && KIND != 4 && KIND != 5 && (caps & kCapOpen)) return false;
     if constexpr (KIND == 4 || KIND == 5) {
         if (si || !(caps & kCapI32) || !(qf || (caps & kCapBLF))) return false;
+        // the occupancy target matters for the Buckley-Leverett fluxes only:
+        // the quadratic-flux kernels meet it without it (101 registers in
+        // FP32, 192 in FP64: four and two waves per SIMD)
+        if (KIND == 5 && qf) return false;
         return stage2o_lds_bytes<T, true, TX, TY>() <= kLdsCap && stage2o_lds_bytes<T, false, TX, TY>() <= kLdsCap;
     } else if constexpr (KIND == 0) {
         if (lim) return si ? stage_lds_bytes<2, T, true, true, TX, TY, 1>() <= kLdsCap

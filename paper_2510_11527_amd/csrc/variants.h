@@ -8,9 +8,10 @@ namespace af4 {
 #define AF4_VARIANTS_D1(X) X(0, 512, 1, 1, 256, "generic-512") X(1, 256, 1, 1, 256, "generic-256") \
     X(2, 128, 1, 1, 128, "generic-128")
 // 2D: KIND 4 = thread-owned-items kernel for fluxes c1 u + c2 u^2 and
-// Buckley-Leverett fluxes (periodic or open ends), 5 = the same with the
-// register allocation held to four waves per SIMD in FP32 and two in FP64
-// (more workgroups per CU where registers, not LDS, limit them), 1 = tuned kernel with a
+// Buckley-Leverett fluxes (periodic or open ends), 5 = the same for
+// Buckley-Leverett fluxes with the register allocation held to four waves
+// per SIMD in FP32 and two in FP64 (more workgroups per CU where registers,
+// not LDS, limit them), 1 = tuned kernel with a
 // {u,a,f_x,f_y} half-grid table (any flux, periodic), 2 = tuned kernel with a
 // {u,a} table (fluxes c1 u + c2 u^2, periodic), 0 = generic kernel (the only
 // one with SI blending)
