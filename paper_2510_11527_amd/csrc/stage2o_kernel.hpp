@@ -157,7 +157,11 @@ __global__ void __launch_bounds__(NT, WPE) stage2o_kernel(StageParams<T> p)
     // uniform branch (no integer division: its expansion, if-converted, cost
     // every thread some 25 instructions per index)
     const bool fold0 = n0 >= TX + 4, fold1 = n1 >= TY + 4;
+    // a tile whose halo lies inside the grid needs no wrap at all (most
+    // tiles of large grids; uniform, so a scalar branch)
+    const bool inner = ox >= 2 && oy >= 2 && ox + TX + 2 <= n0 && oy + TY + 2 <= n1;
     auto wrap = [&](int v, int n, bool fold) -> int {
+        if (inner) return v;
         int r = v < 0 ? v + n : (v >= n ? v - n : v);
         if (!fold) {
             while (r < 0) r += n;
