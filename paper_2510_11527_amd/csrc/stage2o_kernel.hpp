@@ -88,11 +88,8 @@ struct Own2Geo {
     __device__ static __forceinline__ int py(int b) { return NXC + b - 2 - SX; }
 };
 
-// WPE: the waves per SIMD the register allocation must allow (1: the
-// compiler's choice; a higher target trades registers, and possibly spills,
-// for occupancy)
-template <class T, bool LIM, int FL, int TX, int TY, int NT, int WPE = 1>
-__global__ void __launch_bounds__(NT, WPE) stage2o_kernel(StageParams<T> p)
+template <class T, bool LIM, int FL, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
 {
     // GEN: Buckley-Leverett fluxes f_l = q (1 - g_l (1-u)^2), q = u^2 / (u^2 +
     // (1-u)^2) (g_l = 0 without gravity), one branch-free form with the
@@ -495,28 +492,10 @@ __global__ void __launch_bounds__(NT, WPE) stage2o_kernel(StageParams<T> p)
             return (acc + kc[l] * t) + kd[l] * d;
         };
         T R[2][3];  // per own cell: x-face, y-face, corner point value (or du/dt)
-#pragma unroll
-        for (int c = 0; c < 2; c++) {
-            const int b = c == 0 ? b0 : b1;
-            const bool z0 = residual;
-            // x-face point (x+1/2, y)
-            T r = kd30 * Sa(SXF, b) + (z0 ? T(0) : Su(SXF, b));
-            r = pv_dir(0, S(SXF, b - 1), S(SC, b), S(SXF, b), S(SC, b + 1), S(SXF, b + 1), r);
-            R[c][0] = pv_dir(1, S(SXF, b - SX), S(SK, b - SX), S(SXF, b), S(SK, b), S(SXF, b + SX), r);
-            // y-face point (x, y+1/2)
-            r = kd30 * Sa(SYF, b) + (z0 ? T(0) : Su(SYF, b));
-            r = pv_dir(0, S(SYF, b - 1), S(SK, b - 1), S(SYF, b), S(SK, b), S(SYF, b + 1), r);
-            R[c][1] = pv_dir(1, S(SYF, b - SX), S(SC, b), S(SYF, b), S(SC, b + SX), S(SYF, b + SX), r);
-            // corner point (x+1/2, y+1/2)
-            r = kd30 * Sa(SK, b) + (z0 ? T(0) : Su(SK, b));
-            r = pv_dir(0, S(SK, b - 1), S(SYF, b), S(SK, b), S(SYF, b + 1), S(SK, b + 1), r);
-            R[c][2] = pv_dir(1, S(SK, b - SX), S(SXF, b), S(SK, b), S(SXF, b + SX), S(SK, b + SX), r);
-        }
-#pragma unroll
-        for (int c = 0; c < 2; c++) {
+        auto store_cell = [&](int c) {
             const bool own = c == 0 ? own0 : own1;
             const unsigned gi = c == 0 ? g0 : g1;
-            if (!own) continue;
+            if (!own) return;
 #pragma unroll
             for (int z = 1; z < 4; z++) {
                 // stored points on a high open end: right-hand side 0; a stage
@@ -541,6 +520,33 @@ __global__ void __launch_bounds__(NT, WPE) stage2o_kernel(StageParams<T> p)
                 if constexpr (LIM) v = clampb(v, umin, umaxv);
                 st(z, gi, v);
             }
+        };
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            const int b = c == 0 ? b0 : b1;
+            const bool z0 = residual;
+            // x-face point (x+1/2, y)
+            T r = kd30 * Sa(SXF, b) + (z0 ? T(0) : Su(SXF, b));
+            r = pv_dir(0, S(SXF, b - 1), S(SC, b), S(SXF, b), S(SC, b + 1), S(SXF, b + 1), r);
+            R[c][0] = pv_dir(1, S(SXF, b - SX), S(SK, b - SX), S(SXF, b), S(SK, b), S(SXF, b + SX), r);
+            // y-face point (x, y+1/2)
+            r = kd30 * Sa(SYF, b) + (z0 ? T(0) : Su(SYF, b));
+            r = pv_dir(0, S(SYF, b - 1), S(SK, b - 1), S(SYF, b), S(SK, b), S(SYF, b + 1), r);
+            R[c][1] = pv_dir(1, S(SYF, b - SX), S(SC, b), S(SYF, b), S(SC, b + SX), S(SYF, b + SX), r);
+            // corner point (x+1/2, y+1/2)
+            r = kd30 * Sa(SK, b) + (z0 ? T(0) : Su(SK, b));
+            r = pv_dir(0, S(SK, b - 1), S(SYF, b), S(SK, b), S(SYF, b + 1), S(SK, b + 1), r);
+            R[c][2] = pv_dir(1, S(SK, b - SX), S(SXF, b), S(SK, b), S(SXF, b + SX), S(SK, b + SX), r);
+            // Buckley-Leverett fluxes store each cell before computing the
+            // next: the two cells share stencil points, but holding both
+            // cells' results and the shared flux terms at once costs more
+            // registers than recomputing them (the kernels spilled, or ran at
+            // one wave per SIMD in FP64)
+            if constexpr (GEN) store_cell(c);
+        }
+        if constexpr (!GEN) {
+            store_cell(0);
+            store_cell(1);
         }
     }
 

@@ -39,47 +39,38 @@ hipError_t launch_tuned(int nblocks, const void *params, hipStream_t s)
     }
 }
 
-template <class T, bool LIM, int FL, int TX, int TY, int NT, int WPE>
+template <class T, bool LIM, int FL, int TX, int TY, int NT>
 hipError_t launch_own(int nblocks, const void *params, hipStream_t s)
 {
     if constexpr (stage2o_lds_bytes<T, LIM, TX, TY>() > kLdsCap) {
         return hipErrorInvalidValue;
     } else {
-        hipLaunchKernelGGL((stage2o_kernel<T, LIM, FL, TX, TY, NT, WPE>), dim3(nblocks), dim3(NT), 0, s,
+        hipLaunchKernelGGL((stage2o_kernel<T, LIM, FL, TX, TY, NT>), dim3(nblocks), dim3(NT), 0, s,
                            *(const StageParams<T> *)params);
         return hipGetLastError();
     }
 }
 
-template <class T, int FL, int TX, int TY, int NT, int WPE>
+template <class T, int FL, int TX, int TY, int NT>
 hipError_t launch_own_lim(bool lim, int nblocks, const void *params, hipStream_t s)
 {
-    return lim ? launch_own<T, true, FL, TX, TY, NT, WPE>(nblocks, params, s)
-               : launch_own<T, false, FL, TX, TY, NT, WPE>(nblocks, params, s);
+    return lim ? launch_own<T, true, FL, TX, TY, NT>(nblocks, params, s)
+               : launch_own<T, false, FL, TX, TY, NT>(nblocks, params, s);
 }
-
-// waves per SIMD that the occupancy-targeted own-items tiles (KIND 5) ask of
-// the register allocation: four in FP32, two in FP64 (left to the compiler,
-// the Buckley-Leverett instantiations take registers for three waves per
-// SIMD in FP32 and for one in FP64)
-template <class T>
-constexpr int own_wpe() { return sizeof(T) == 4 ? 4 : 2; }
 
 template <class T, int TX, int TY, int NT, int KIND, bool CV>
 hipError_t launch_kind(bool lim, bool si, unsigned caps, int nblocks, const void *params, hipStream_t s)
 {
     const bool qf = (caps & kCapQF) != 0;
     if (KIND != 0 && ((const StageParams<T> *)params)->lact) return hipErrorInvalidValue;  // counting: generic only
-    if (KIND != 0 && KIND != 4 && KIND != 5 && (caps & kCapOpen)) return hipErrorInvalidValue;  // ghosts: generic, own-items
-    if constexpr (KIND == 4 || KIND == 5) {
-        constexpr int WPE = KIND == 5 ? own_wpe<T>() : 1;
+    if (KIND != 0 && KIND != 4 && (caps & kCapOpen)) return hipErrorInvalidValue;  // ghosts: generic, own-items
+    if constexpr (KIND == 4) {
         if (si || !(caps & kCapI32) || !(qf || (caps & kCapBLF))) return hipErrorInvalidValue;
-        if (KIND == 5 && qf) return hipErrorInvalidValue;  // fits the target already
         const int fl = (!qf ? kOwnGen : 0) | ((caps & kCapPP) ? kOwnPP : 0) | ((qf && (caps & kCapBQ)) ? kOwnBQ : 0) |
                        ((caps & kCapOpen) ? kOwnOpen : 0);
         switch (fl) {
 #define AF4_OWN_FL(F) \
-    case F: return launch_own_lim<T, F, TX, TY, NT, WPE>(lim, nblocks, params, s);
+    case F: return launch_own_lim<T, F, TX, TY, NT>(lim, nblocks, params, s);
             AF4_OWN_FL(0) AF4_OWN_FL(kOwnPP) AF4_OWN_FL(kOwnBQ) AF4_OWN_FL(kOwnPP | kOwnBQ) AF4_OWN_FL(kOwnGen)
             AF4_OWN_FL(kOwnGen | kOwnPP) AF4_OWN_FL(kOwnOpen) AF4_OWN_FL(kOwnOpen | kOwnPP) AF4_OWN_FL(kOwnOpen | kOwnBQ)
             AF4_OWN_FL(kOwnOpen | kOwnPP | kOwnBQ) AF4_OWN_FL(kOwnOpen | kOwnGen) AF4_OWN_FL(kOwnOpen | kOwnGen | kOwnPP)
@@ -113,13 +104,9 @@ template <class T, int TX, int TY, int KIND>
 bool fits_kind(bool lim, bool si, unsigned caps)
 {
     const bool qf = (caps & kCapQF) != 0;
-    if (KIND != 0 && KIND != 4 && KIND != 5 && (caps & kCapOpen)) return false;
-    if constexpr (KIND == 4 || KIND == 5) {
+    if (KIND != 0 && KIND != 4 && (caps & kCapOpen)) return false;
+    if constexpr (KIND == 4) {
         if (si || !(caps & kCapI32) || !(qf || (caps & kCapBLF))) return false;
-        // the occupancy target matters for the Buckley-Leverett fluxes only:
-        // the quadratic-flux kernels meet it without it (101 registers in
-        // FP32, 192 in FP64: four and two waves per SIMD)
-        if (KIND == 5 && qf) return false;
         return stage2o_lds_bytes<T, true, TX, TY>() <= kLdsCap && stage2o_lds_bytes<T, false, TX, TY>() <= kLdsCap;
     } else if constexpr (KIND == 0) {
         if (lim) return si ? stage_lds_bytes<2, T, true, true, TX, TY, 1>() <= kLdsCap

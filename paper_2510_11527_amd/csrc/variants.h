@@ -8,10 +8,7 @@ namespace af4 {
 #define AF4_VARIANTS_D1(X) X(0, 512, 1, 1, 256, "generic-512") X(1, 256, 1, 1, 256, "generic-256") \
     X(2, 128, 1, 1, 128, "generic-128")
 // 2D: KIND 4 = thread-owned-items kernel for fluxes c1 u + c2 u^2 and
-// Buckley-Leverett fluxes (periodic or open ends), 5 = the same for
-// Buckley-Leverett fluxes with the register allocation held to four waves
-// per SIMD in FP32 and two in FP64 (more workgroups per CU where registers,
-// not LDS, limit them), 1 = tuned kernel with a
+// Buckley-Leverett fluxes (periodic or open ends), 1 = tuned kernel with a
 // {u,a,f_x,f_y} half-grid table (any flux, periodic), 2 = tuned kernel with a
 // {u,a} table (fluxes c1 u + c2 u^2, periodic), 0 = generic kernel (the only
 // one with SI blending)
@@ -19,8 +16,7 @@ namespace af4 {
     X(0, 32, 16, 1, 256, 4, "2d-own-32x16") X(1, 32, 8, 1, 128, 4, "2d-own-32x8")                    \
     X(2, 32, 16, 1, 256, 1, "2d-table4-32x16") X(3, 32, 8, 1, 128, 1, "2d-table4-32x8")              \
     X(4, 32, 16, 1, 256, 2, "2d-table2-32x16") X(5, 32, 8, 1, 256, 0, "generic-32x8")                \
-    X(6, 16, 16, 1, 256, 0, "generic-16x16") X(7, 32, 32, 1, 512, 4, "2d-own-32x32")                \
-    X(8, 32, 16, 1, 256, 5, "2d-ownocc-32x16")
+    X(6, 16, 16, 1, 256, 0, "generic-16x16") X(7, 32, 32, 1, 512, 4, "2d-own-32x32")
 // the tile variant whose generic kernel also has the limiter-counting form
 // (af_limiter_activity)
 constexpr int count_variant(int dim) { return dim == 2 ? 5 : dim == 3 ? 6 : 0; }
