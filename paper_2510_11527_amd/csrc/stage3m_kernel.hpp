@@ -97,6 +97,24 @@ __device__ __forceinline__ constexpr int m3_part(int zk)
 {
     return NH == 1 ? 0 : (zeta_mask<3>(zk) >> 2) & 1;
 }
+// position of DoF kind zk among the 8 / NH kinds of its part (in zk order),
+// and the kind at position j of part h
+template <int NH>
+__device__ __forceinline__ constexpr int m3_slot(int zk)
+{
+    int s = 0;
+    for (int j = 0; j < zk; j++) s += m3_part<NH>(j) == m3_part<NH>(zk) ? 1 : 0;
+    return s;
+}
+template <int NH>
+__device__ __forceinline__ int m3_kind(int h, int j)
+{
+    int r = 0;
+#pragma unroll
+    for (int zk = 7; zk >= 0; zk--)
+        if (m3_part<NH>(zk) == h && m3_slot<NH>(zk) == j) r = zk;
+    return r;
+}
 
 // NT = NH TX TY threads, NH in {1, 2} per column
 template <class T, bool LIM, bool SI, int TX, int TY, int LZ, int NT>
@@ -164,6 +182,18 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
 
     Phys<T> P;
     P.load(I, 3);
+    {
+        // the bounds as scalar loads: a vector load of them stayed pending
+        // into the loop, where the first clamp waited for every load in flight
+        const auto Ic = as_constant(&p.inst[wk.x]);
+        if constexpr (sizeof(T) == 4) {
+            P.umin = Ic->f_umin;
+            P.umax = Ic->f_umax;
+        } else {
+            P.umin = Ic->umin;
+            P.umax = Ic->umax;
+        }
+    }
     T qc1[3], qc2[3];  // f_l = qc1 u + qc2 u^2
 #pragma unroll
     for (int l = 0; l < 3; l++) {
@@ -212,7 +242,22 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
     constexpr int NP = (NPC + NT - 1) / NT;
     const int tid = (int)threadIdx.x;
     T pu[NU], pv[NP][8];
+    // U^n of the DoFs this thread updates in phase 6 (its column and part of
+    // the column's kinds), loaded with the other loads of the iteration
+    // before: a load issued in phase 6 itself made the wait for it also wait
+    // for those prefetches (the memory counter is in order)
+    constexpr int NK = 8 / NH;
+    const int pu6 = tid % TX, pv6 = (tid / TX) % TY, ph6 = tid / (TX * TY);
+    const bool own6 = ox + pu6 < n0 && oy + pv6 < n1;
+    T unn[NK], unc[NK];
+#pragma unroll
+    for (int j = 0; j < NK; j++) unn[j] = unc[j] = T(0);
     auto issue = [&](int k) {
+        if (k >= z0) {
+            const long long g6 = own6 ? (ox + pu6) + (long long)n0 * (oy + pv6) + plane * k : 0;
+#pragma unroll
+            for (int j = 0; j < NK; j++) unn[j] = un[m3_kind<NH>(ph6, j) * kst + g6];
+        }
 #pragma unroll
         for (int i = 0; i < NU; i++) {
             const int idx = tid + i * NT;
@@ -228,7 +273,24 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
             }
         }
     };
+    // the stage's combination (stage_combine) with the prefetched U^n; X1,
+    // read by summing stages only, is loaded and used inside their branch, so
+    // that the other stages wait for no load in phase 6
+    auto combine6 = [&](T v, T x0, int z, long long g, T vin) -> T {
+        if (p.mode == kCombSum) return ((p.c0 * x0 + p.c1 * x1[z * kst + g]) + p.cin * vin) + p.w * v;
+        if (p.mode == kCombBlend) return x0 + p.w * (v - x0);
+        return v;
+    };
     auto commit = [&](int k) {
+        // the empty asm reads each loaded value here, where the loads of the
+        // iteration before are waited for anyway; a first read in phase 6,
+        // behind the next iteration's loads, would wait for those too
+#pragma unroll
+        for (int j = 0; j < NK; j++) {
+            T v = unn[j];
+            asm volatile("" : "+v"(v));
+            unc[j] = v;
+        }
         T *ubk = sUB[s4(k + 3)];
 #pragma unroll
         for (int i = 0; i < NU; i++) {
@@ -676,7 +738,7 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
                     T val = u0 + dt * R;
                     if (!isfinite(val)) bad = true;
                     if constexpr (LIM) val = clampb(val, P.umin, P.umax);
-                    val = stage_combine(p, val, un[zk * kst + gi], x1 ? x1[zk * kst + gi] : T(0), u0);
+                    val = combine6(val, unc[m3_slot<NH>(zk)], zk, gi, u0);
                     if constexpr (LIM) val = clampb(val, P.umin, P.umax);
                     out[zk * kst + gi] = val;
                 }
@@ -707,7 +769,7 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
                     clamp_mag = fmax(clamp_mag, (double)fabs(c - val));
                     val = c;
                 }
-                val = stage_combine(p, val, un[gi], x1 ? x1[gi] : T(0), uc);
+                val = combine6(val, unc[m3_slot<NH>(0)], 0, gi, uc);
                 if constexpr (LIM) {
                     const T c = clampb(val, P.umin, P.umax);
                     clamp_mag = fmax(clamp_mag, (double)fabs(c - val));
