@@ -84,38 +84,41 @@ struct Phys {
     T a0, a1;
     T umin, umax;
     int nc[3];
-    const InstDev *ip;   // critical points are read from here (uniform loads)
+    const_ptr<InstDev> ip;   // critical points are read from here (scalar loads)
     T pu0, plo, phi, pc1, pc2, pc3;
     bool pabs, ppow;
 
-    __device__ void load(const InstDev &I, int D)
+    // the instance's parameters through the constant address space: scalar
+    // loads, whose waits do not hold up the vector loads in flight
+    __device__ void load(const InstDev &Iref, int D) { load(as_constant(&Iref), D); }
+    __device__ void load(const_ptr<InstDev> I, int D)
     {
-        ip = &I;
+        ip = I;
         for (int l = 0; l < 3; l++) {
-            fk[l] = I.fk[l];
-            fc[l] = (T)I.fp0[l];
-            fg[l] = (T)I.fp1[l];
-            nc[l] = l < D ? I.ncrit[l] : 0;
+            fk[l] = I->fk[l];
+            fc[l] = (T)I->fp0[l];
+            fg[l] = (T)I->fp1[l];
+            nc[l] = l < D ? I->ncrit[l] : 0;
         }
-        ak = I.ak;
-        am = I.am;
-        pu0 = (T)I.pu0;
-        plo = (T)I.plo;
-        phi = (T)I.phi;
-        pc1 = (T)I.pc1;
-        pc2 = (T)I.pc2;
-        pc3 = (T)I.pc3;
-        pabs = I.pabs != 0;
-        ppow = I.ppow != 0;
-        a0 = (T)I.ap0;
-        a1 = (T)I.ap1;
+        ak = I->ak;
+        am = I->am;
+        pu0 = (T)I->pu0;
+        plo = (T)I->plo;
+        phi = (T)I->phi;
+        pc1 = (T)I->pc1;
+        pc2 = (T)I->pc2;
+        pc3 = (T)I->pc3;
+        pabs = I->pabs != 0;
+        ppow = I->ppow != 0;
+        a0 = (T)I->ap0;
+        a1 = (T)I->ap1;
         // FP32: the bounds rounded inwards on the host
         if constexpr (sizeof(T) == 4) {
-            umin = I.f_umin;
-            umax = I.f_umax;
+            umin = I->f_umin;
+            umax = I->f_umax;
         } else {
-            umin = I.umin;
-            umax = I.umax;
+            umin = I->umin;
+            umax = I->umax;
         }
     }
 
@@ -334,6 +337,22 @@ __device__ __forceinline__ void box_loop(F &&fn)
     }
 }
 
+// box_loop with the thread's round c in [0, ceil(E0 E1 E2 / NT)) passed on
+// (unrolled, so that per-round registers are indexed at compile time)
+template <int E0, int E1, int E2, int NT, class F>
+__device__ __forceinline__ void box_loop_r(F &&fn)
+{
+    constexpr int N = E0 * E1 * E2, C = (N + NT - 1) / NT;
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        const int idx = (int)threadIdx.x + c * NT;
+        if (N % NT == 0 || idx < N) {
+            const int x = idx % E0, r = idx / E0;
+            fn(x, r % E1, r / E1, c);
+        }
+    }
+}
+
 __device__ __forceinline__ int wrap_index(int v, int n)
 {
     while (v < 0) v += n;
@@ -487,19 +506,20 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
     const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
     const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3);
     const int4 wk = p.work[logical];
-    const InstDev &I = p.inst[wk.x];
-    const int n0 = I.n[0], n1 = I.n[1], n2 = I.n[2];
+    // the instance's parameters: scalar loads (see Phys::load)
+    const auto I = as_constant(&p.inst[wk.x]);
+    const int n0 = I->n[0], n1 = I->n[1], n2 = I->n[2];
     const int tx = wk.y, ty = wk.z, tz = wk.w;
     const int ox = tx * G::T0, oy = ty * G::T1, oz = tz * G::T2;
-    const long long kst = I.kstride;
-    const T *__restrict__ in = p.in + I.off;
-    const T *__restrict__ un = p.un + I.off;
-    const T *__restrict__ x1 = p.x1 ? p.x1 + I.off : nullptr;
-    T *__restrict__ out = p.out + I.off;
+    const long long kst = I->kstride;
+    const T *__restrict__ in = p.in + I->off;
+    const T *__restrict__ un = p.un + I->off;
+    const T *__restrict__ x1 = p.x1 ? p.x1 + I->off : nullptr;
+    T *__restrict__ out = p.out + I->off;
     const bool residual = p.stage == kStageRHS;
     const double dtd = p.st[wk.x].dt;
     // the 1D variant without double conservation (App. A)
-    const bool nodc = D == 1 && I.nodc != 0;
+    const bool nodc = D == 1 && I->nodc != 0;
     // PA: a(u) at the half-grid points is evaluated once, where the point is
     // staged (App. A's form uses kappa instead)
     const bool pa = PA && !nodc;
@@ -509,18 +529,18 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
     // (outflow) the mean average of the domain cells around the point moved
     // onto the boundary; the stored point values on the high ends are not
     // evolved (Dirichlet value, or the input passed through).
-    const bool open = D <= 2 && (I.bc[0][0] != 0 || (D == 2 && I.bc[1][0] != 0));
+    const bool open = D <= 2 && (I->bc[0][0] != 0 || (D == 2 && I->bc[1][0] != 0));
     auto ends = [&](int q0, int q1) -> int {
         int m = 0;
-        if (I.bc[0][0] != 0 && (q0 <= -1 || q0 >= 2 * n0 - 1)) m |= 1;
-        if (D == 2 && I.bc[1][0] != 0 && (q1 <= -1 || q1 >= 2 * n1 - 1)) m |= 2;
+        if (I->bc[0][0] != 0 && (q0 <= -1 || q0 >= 2 * n0 - 1)) m |= 1;
+        if (D == 2 && I->bc[1][0] != 0 && (q1 <= -1 || q1 >= 2 * n1 - 1)) m |= 2;
         return m;
     };
     auto bc_point = [&](int q0, int q1, int m) -> T {
 #pragma unroll
         for (int l = 0; l < 2; l++) {
             const int q = l == 0 ? q0 : q1, side = q <= -1 ? 0 : 1;
-            if ((m >> l & 1) && I.bc[l][side] == 1) return (T)I.bcv[l][side];
+            if ((m >> l & 1) && I->bc[l][side] == 1) return (T)I->bcv[l][side];
         }
         int lo[2], hi[2];
 #pragma unroll
@@ -565,8 +585,8 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
     T qc1[3], qc2[3];  // QF: f_l = qc1 u + qc2 u^2
 #pragma unroll
     for (int l = 0; l < 3; l++) {
-        qc1[l] = I.fk[l] == kFLinear ? (T)I.fp0[l] : T(0);
-        qc2[l] = I.fk[l] == kFQuad ? (T)I.fp0[l] : T(0);
+        qc1[l] = I->fk[l] == kFLinear ? (T)I->fp0[l] : T(0);
+        qc2[l] = I->fk[l] == kFQuad ? (T)I->fp0[l] : T(0);
     }
     auto Ff = [&](int l, T u) -> T {
         if constexpr (QF) return u * (qc1[l] + qc2[l] * u);
@@ -585,9 +605,9 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
     T idx1[3], idx2[3], i6dx[3], mu[3], nu[3];
 #pragma unroll
     for (int l = 0; l < 3; l++) {
-        idx1[l] = (T)I.idx1[l];
-        idx2[l] = (T)I.idx2[l];
-        i6dx[l] = (T)I.i6dx[l];
+        idx1[l] = (T)I->idx1[l];
+        idx2[l] = (T)I->idx2[l];
+        i6dx[l] = (T)I->i6dx[l];
         mu[l] = (T)p.st[wk.x].mu[l] * p.dts;
         nu[l] = (T)p.st[wk.x].nu[l] * p.dts;
     }
@@ -632,6 +652,25 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
             if (pa) ah[G::hidx(hx, hy, hz)] = P.a(v[zk]);
         }
     });
+    // U^n of the own DoFs for the stage's combination, loaded after the
+    // stage's own loads and used in phases C and D3: the load latency overlaps
+    // phases B to D2 instead of stalling every store (cells outside the grid
+    // read cell 0)
+    constexpr int NRND = (G::T0 * G::T1 * G::T2 + NT - 1) / NT;
+    T unp[NRND][NB];
+    box_loop_r<G::T0, G::T1, G::T2, NT>([&](int i, int j, int k, int c) {
+        const bool own = ox + i < n0 && oy + j < n1 && oz + k < n2;
+        const long long gi = own ? (ox + i) + (long long)n0 * ((oy + j) + (long long)n1 * (oz + k)) : 0;
+#pragma unroll
+        for (int zk = 0; zk < NB; zk++) unp[c][zk] = un[zk * kst + gi];
+    });
+    // the stage's combination (stage_combine) with the prefetched U^n; X1,
+    // read by summing stages only, is loaded inside their branch
+    auto combine_g = [&](T v, T x0, int z, long long g, T vin) -> T {
+        if (p.mode == kCombSum) return ((p.c0 * x0 + p.c1 * x1[z * kst + g]) + p.cin * vin) + p.w * v;
+        if (p.mode == kCombBlend) return x0 + p.w * (v - x0);
+        return v;
+    };
     __syncthreads();
 
     // ---- B: cell centres on [h-1, h+t+1)^D (inverse tensor Simpson)
@@ -703,13 +742,13 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
         return ssm[G::sb_off(l) + (x - (G::H0 - (l == 0))) +
                    G::sbe(l, 0) * ((y - (G::H1 - (l == 1))) + G::sbe(l, 1) * (z - (G::H2 - (l == 2))))];
     };
-    const T gam = (T)I.si_gamma;
+    const T gam = (T)I->si_gamma;
 
     double clamp_mag = 0.0;
     bool bad = false;
 
     // ---- C: point values of the tile (Eq. 2d_af_dc, projection Sec. 5.1.2)
-    box_loop<G::T0, G::T1, G::T2, NT>([&](int i, int j, int k) {
+    box_loop_r<G::T0, G::T1, G::T2, NT>([&](int i, int j, int k, int c) {
         const bool own = ox + i < n0 && oy + j < n1 && oz + k < n2;
         const int x = i + G::H0, y = j + G::H1, z = k + G::H2;
         const long long gi = (ox + i) + (long long)n0 * ((oy + j) + (long long)n1 * (oz + k));
@@ -794,13 +833,13 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
                 v = in[zk * kst + gi];
 #pragma unroll
                 for (int l = 1; l >= 0; l--)
-                    if ((me >> l & 1) && I.bc[l][1] == 1) v = (T)I.bcv[l][1];
+                    if ((me >> l & 1) && I->bc[l][1] == 1) v = (T)I->bcv[l][1];
             }
             if (!isfinite(v)) bad = true;
             if constexpr (LIM) v = clampb(v, P.umin, P.umax);
             // (a stored boundary point combines with its stored input, not the
             // boundary value the stencils see)
-            v = stage_combine(p, v, un[zk * kst + gi], x1 ? x1[zk * kst + gi] : T(0), me ? in[zk * kst + gi] : u0);
+            v = combine_g(v, unp[c][zk], zk, gi, me ? in[zk * kst + gi] : u0);
             if constexpr (LIM) v = clampb(v, P.umin, P.umax);
             out[zk * kst + gi] = v;
         }
@@ -954,7 +993,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
 
     // ---- D3: averages of the tile (Eq. multid_limited_average; with theta = 1
     // and no blending this is the high-order update of Eq. 2d_af_dc)
-    box_loop<G::T0, G::T1, G::T2, NT>([&](int i, int j, int k) {
+    box_loop_r<G::T0, G::T1, G::T2, NT>([&](int i, int j, int k, int c) {
         if (ox + i >= n0 || oy + j >= n1 || oz + k >= n2) return;
         const long long gi = (ox + i) + (long long)n0 * ((oy + j) + (long long)n1 * (oz + k));
         const T u = ub[G::cidx(i + G::H0, j + G::H1, k + G::H2)];
@@ -989,7 +1028,7 @@ __global__ void __launch_bounds__(NT) stage_kernel(StageParams<T> p)
             clamp_mag = fmax(clamp_mag, (double)fabs(c - v));
             v = c;
         }
-        v = stage_combine(p, v, un[gi], x1 ? x1[gi] : T(0), u);
+        v = combine_g(v, unp[c][0], 0, gi, u);
         if constexpr (LIM) {
             T c = clampb(v, P.umin, P.umax);
             clamp_mag = fmax(clamp_mag, (double)fabs(c - v));
