@@ -116,6 +116,58 @@ __device__ __forceinline__ int m3_kind(int h, int j)
     return r;
 }
 
+// One loop over the items of several boxes of a phase, for boxes smaller
+// than the workgroup: box b takes a segment of one index space, each segment
+// starting at a wave boundary, so that a wave works on one box and the
+// boxes are spread over all the waves (a loop per box would give each box's
+// items to the first waves only and leave the last idle).  A segment that is
+// off takes its place in the index space but does nothing.
+template <int W_, int H_, class F>
+struct MSeg {
+    static constexpr int W = W_, N = W_ * H_, PAD = (N + 63) / 64 * 64;
+    bool on;
+    F f;
+};
+template <int W, int H, class F>
+__device__ __forceinline__ MSeg<W, H, F> mseg(bool on, F f)
+{
+    return MSeg<W, H, F>{on, f};
+}
+template <int OFF>
+__device__ __forceinline__ void mseg_run(int)
+{
+}
+template <int OFF, class S, class... R>
+__device__ __forceinline__ void mseg_run(int idx, const S &s, const R &...rest)
+{
+    if (idx < OFF + S::PAD) {
+        const int li = idx - OFF;
+        if (s.on && li < S::N) s.f(li % S::W, li / S::W);
+        return;
+    }
+    mseg_run<OFF + S::PAD>(idx, rest...);
+}
+template <int NT, class S>
+__device__ __forceinline__ void mseg_alone(const S &s)
+{
+    if (!s.on) return;
+    for (int li = (int)threadIdx.x; li < S::N; li += NT) s.f(li % S::W, li / S::W);
+}
+template <int NT, class... S>
+__device__ __forceinline__ void box_merge(const S &...segs)
+{
+    if constexpr (NT >= 256) {
+        constexpr int TOT = (S::PAD + ... + 0);
+#pragma unroll
+        for (int r = 0; r < (TOT + NT - 1) / NT; r++) mseg_run<0>((int)threadIdx.x + r * NT, segs...);
+    } else {
+        // two waves take every box of these phases in one round each anyway,
+        // and the merged loop cost them registers (one wave per SIMD): a loop
+        // per box
+        (mseg_alone<NT>(segs), ...);
+    }
+}
+
 // NT = NH TX TY threads, NH in {1, 2} per column
 template <class T, bool LIM, bool SI, int TX, int TY, int LZ, int NT>
 __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
@@ -332,71 +384,64 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
         __syncthreads();
 
         // ---- 2: centres of plane k+1, raw indicators, low-order z-face k+3/2
-        if (k >= z0 - 2) {
+        // (one merged loop over the five boxes: see box_merge)
+        {
             const T *hm = sH[s6(2 * k + 1)], *hp1 = sH[s6(2 * k + 3)];
             T *hc = sH[s6(2 * k + 2)], *ac = sA[s6(2 * k + 2)];
-            const T *ubk = sUB[s4(k + 1)];
-            box_loop<TX + 2, TY + 2, 1, NT>([&](int x, int y, int) {
-                const int u = x - 1, v = y - 1;
-                const int pc = 2 * u, qc = 2 * v;
-                T acc = T(216) * ubk[G::ub(u, v)];
-#pragma unroll
-                for (int oy = -1; oy <= 1; oy++)
-#pragma unroll
-                    for (int oxx = -1; oxx <= 1; oxx++) {
-                        const int i = G::hp(pc + oxx, qc + oy);
-                        const T wxy = T((oxx == 0 ? 4 : 1) * (oy == 0 ? 4 : 1));
-                        acc -= wxy * (hm[i] + hp1[i]);                        // oz = -1, +1
-                        if (oxx != 0 || oy != 0) acc -= T(4) * wxy * hc[i];  // oz = 0
-                    }
-                const T c = acc * T(0.015625);
-                hc[G::hp(pc, qc)] = c;
-                ac[G::hp(pc, qc)] = P.a(c);
-            });
-        }
-        if (use_si) {
-            if (k >= z0 - 1) {
-                const T *ubk = sUB[s4(k + 1)];
-                box_loop<G::TXW, TY + 1, 1, NT>([&](int x, int y, int) {
-                    const int u = x - 2, v = y;
-                    const T um = ubk[G::ub(u - 1, v)], u0 = ubk[G::ub(u, v)], up = ubk[G::ub(u + 1, v)];
-                    sTX[x + G::TXW * y] = fabs(um - T(2) * u0 + up) / (fabs(um) + T(2) * fabs(u0) + fabs(up) + T(1e-13));
-                });
-                box_loop<TX + 1, TY + 4, 1, NT>([&](int x, int y, int) {
-                    const int u = x, v = y - 2;
-                    const T um = ubk[G::ub(u, v - 1)], u0 = ubk[G::ub(u, v)], up = ubk[G::ub(u, v + 1)];
-                    sTY[x + G::TYW * y] = fabs(um - T(2) * u0 + up) / (fabs(um) + T(2) * fabs(u0) + fabs(up) + T(1e-13));
-                });
-            }
-            if (k >= z0 - 4) {
-                const T *b1 = sUB[s4(k + 1)], *b2 = sUB[s4(k + 2)], *b3 = sUB[s4(k + 3)];
-                T *tz = sTZ[s3(k + 2)];
-                box_loop<TX + 1, TY + 1, 1, NT>([&](int u, int v, int) {
-                    const int i = G::ub(u, v);
-                    const T um = b1[i], u0 = b2[i], up = b3[i];
-                    tz[u + G::EZW * v] = fabs(um - T(2) * u0 + up) / (fabs(um) + T(2) * fabs(u0) + fabs(up) + T(1e-13));
-                });
-            }
-        }
-        if (k >= z0 - 3) {
-            // z-face (k+1)+1/2 between planes k+1 and k+2: LLF flux, and with the
-            // limiter u^{L,+} of the lower cell and u^{L,-} of the upper one
-            const T *b1 = sUB[s4(k + 1)], *b2 = sUB[s4(k + 2)];
+            const T *ub1 = sUB[s4(k + 1)], *ub2 = sUB[s4(k + 2)], *ub3 = sUB[s4(k + 3)];
+            T *tz = sTZ[s3(k + 2)];
             const int sl = s2(k + 1);
-            box_loop<TX, TY, 1, NT>([&](int u, int v, int) {
-                const int i = G::ub(u, v), o = u + TX * v;
-                const T ua = b1[i], ubb = b2[i];
-                const T fa = Ff(2, ua), fb = Ff(2, ubb);
-                const T al = fmax(Fg(2, ua), Fg(2, ubb));
-                const T fL = T(0.5) * (fa + fb) - T(0.5) * al * (ubb - ua);
-                sZL[sl][o] = fL;
-                if constexpr (LIM) {
-                    const T dA = (P.a(ubb) - P.a(ua)) * idx1[2];
-                    const T Km = K * mu[2];
-                    sZP[sl][o] = ua - Km * (fL - fa) + Km * dA;
-                    sZM[sl][o] = ubb - Km * (fb - fL) - Km * dA;
-                }
-            });
+            // the indicator boxes are empty without blending
+            constexpr int SIH = SI ? 1 : 0;
+            box_merge<NT>(
+                mseg<TX + 2, TY + 2>(k >= z0 - 2, [&](int x, int y) {
+                    const int u = x - 1, v = y - 1;
+                    const int pc = 2 * u, qc = 2 * v;
+                    T acc = T(216) * ub1[G::ub(u, v)];
+#pragma unroll
+                    for (int oy = -1; oy <= 1; oy++)
+#pragma unroll
+                        for (int oxx = -1; oxx <= 1; oxx++) {
+                            const int i = G::hp(pc + oxx, qc + oy);
+                            const T wxy = T((oxx == 0 ? 4 : 1) * (oy == 0 ? 4 : 1));
+                            acc -= wxy * (hm[i] + hp1[i]);                        // oz = -1, +1
+                            if (oxx != 0 || oy != 0) acc -= T(4) * wxy * hc[i];  // oz = 0
+                        }
+                    const T c = acc * T(0.015625);
+                    hc[G::hp(pc, qc)] = c;
+                    ac[G::hp(pc, qc)] = P.a(c);
+                }),
+                mseg<G::TXW, (TY + 1) * SIH>(use_si && k >= z0 - 1, [&](int x, int y) {
+                    const int u = x - 2, v = y;
+                    const T um = ub1[G::ub(u - 1, v)], u0 = ub1[G::ub(u, v)], up = ub1[G::ub(u + 1, v)];
+                    sTX[x + G::TXW * y] = fabs(um - T(2) * u0 + up) / (fabs(um) + T(2) * fabs(u0) + fabs(up) + T(1e-13));
+                }),
+                mseg<TX + 1, (TY + 4) * SIH>(use_si && k >= z0 - 1, [&](int x, int y) {
+                    const int u = x, v = y - 2;
+                    const T um = ub1[G::ub(u, v - 1)], u0 = ub1[G::ub(u, v)], up = ub1[G::ub(u, v + 1)];
+                    sTY[x + G::TYW * y] = fabs(um - T(2) * u0 + up) / (fabs(um) + T(2) * fabs(u0) + fabs(up) + T(1e-13));
+                }),
+                mseg<TX + 1, (TY + 1) * SIH>(use_si && k >= z0 - 4, [&](int u, int v) {
+                    const int i = G::ub(u, v);
+                    const T um = ub1[i], u0 = ub2[i], up = ub3[i];
+                    tz[u + G::EZW * v] = fabs(um - T(2) * u0 + up) / (fabs(um) + T(2) * fabs(u0) + fabs(up) + T(1e-13));
+                }),
+                // z-face (k+1)+1/2 between planes k+1 and k+2: LLF flux, and with the
+                // limiter u^{L,+} of the lower cell and u^{L,-} of the upper one
+                mseg<TX, TY>(k >= z0 - 3, [&](int u, int v) {
+                    const int i = G::ub(u, v), o = u + TX * v;
+                    const T ua = ub1[i], ubb = ub2[i];
+                    const T fa = Ff(2, ua), fb = Ff(2, ubb);
+                    const T al = fmax(Fg(2, ua), Fg(2, ubb));
+                    const T fL = T(0.5) * (fa + fb) - T(0.5) * al * (ubb - ua);
+                    sZL[sl][o] = fL;
+                    if constexpr (LIM) {
+                        const T dA = (P.a(ubb) - P.a(ua)) * idx1[2];
+                        const T Km = K * mu[2];
+                        sZP[sl][o] = ua - Km * (fL - fa) + Km * dA;
+                        sZM[sl][o] = ubb - Km * (fb - fL) - Km * dA;
+                    }
+                }));
         }
         __syncthreads();
 
@@ -427,155 +472,156 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
         }
 
         // ---- 4: z-potential of plane k+1, z-flux of face k+1/2, x/y-faces of plane k
-        if (k >= z0 - 2) {
+        // (the two z boxes in one merged loop, see box_merge; merging the x-
+        // and y-faces too took more registers than two waves per SIMD allow)
+        {
             const T *a0 = sA[s6(2 * k + 1)], *a1 = sA[s6(2 * k + 2)], *a2 = sA[s6(2 * k + 3)];
-            const T *ubk = sUB[s4(k + 1)];
+            const T *ubz = sUB[s4(k + 1)];
             const int fl = s2(k), fu = s2(k + 1);  // faces (k+1) -+ 1/2
-            box_loop<TX, TY, 1, NT>([&](int u, int v, int) {
-                const int o = u + TX * v;
-                // (1/216) sum of v_z (x) w (x) w a over the cell's 27 points
-                T sl[3];
-                const T *ap[3] = {a0, a1, a2};
+            const T *h = sH[s6(2 * k + 1)];
+            const int fs = s2(k);
+            const T *ubk = sUB[s4(k)];
+            const T *hm = sH[s6(2 * k - 1)], *h0 = sH[s6(2 * k)], *hq = sH[s6(2 * k + 1)];
+            box_merge<NT>(
+                mseg<TX, TY>(k >= z0 - 2, [&](int u, int v) {
+                    const int o = u + TX * v;
+                    // (1/216) sum of v_z (x) w (x) w a over the cell's 27 points
+                    T sl[3];
+                    const T *ap[3] = {a0, a1, a2};
 #pragma unroll
-                for (int oz = 0; oz < 3; oz++) {
-                    T acc = T(0);
+                    for (int oz = 0; oz < 3; oz++) {
+                        T acc = T(0);
+#pragma unroll
+                        for (int oy = -1; oy <= 1; oy++)
+#pragma unroll
+                            for (int oxx = -1; oxx <= 1; oxx++)
+                                acc += T((oxx == 0 ? 4 : 1) * (oy == 0 ? 4 : 1)) * ap[oz][G::hp(2 * u + oxx, 2 * v + oy)];
+                        sl[oz] = acc;
+                    }
+                    T aH = (T(8) * sl[1] - sl[0] - sl[2]) * T(1.0 / 216.0);
+                    const T aL = P.a(ubz[G::ub(u, v)]);
+                    if (use_si) {
+                        T e = sEZ[s3(k + 1)][u + G::EZW * v];
+                        e *= e;
+                        e *= e;
+                        const T th = e * e;
+                        aH = th * aH + (T(1) - th) * aL;
+                    }
+                    T Pv = aH;
+                    if (lim) {
+                        const T da = aH - aL;
+                        const T gap = gap4<T>(da, sZP[fl][o], sZM[fu][o], sZP[fu][o], sZM[fl][o], P.umin, P.umax);
+                        Pv = aL + limited_part<T>(gap, da, ik3nu[2]);
+                    }
+                    sPZ[s3(k + 1)][o] = Pv;
+                }),
+                mseg<TX, TY>(k >= z0 - 1, [&](int u, int v) {
+                    const int o = u + TX * v;
+                    T fH = T(0);
 #pragma unroll
                     for (int oy = -1; oy <= 1; oy++)
 #pragma unroll
                         for (int oxx = -1; oxx <= 1; oxx++)
-                            acc += T((oxx == 0 ? 4 : 1) * (oy == 0 ? 4 : 1)) * ap[oz][G::hp(2 * u + oxx, 2 * v + oy)];
-                    sl[oz] = acc;
-                }
-                T aH = (T(8) * sl[1] - sl[0] - sl[2]) * T(1.0 / 216.0);
-                const T aL = P.a(ubk[G::ub(u, v)]);
-                if (use_si) {
-                    T e = sEZ[s3(k + 1)][u + G::EZW * v];
-                    e *= e;
-                    e *= e;
-                    const T th = e * e;
-                    aH = th * aH + (T(1) - th) * aL;
-                }
-                T Pv = aH;
-                if (lim) {
-                    const T da = aH - aL;
-                    const T gap = gap4<T>(da, sZP[fl][o], sZM[fu][o], sZP[fu][o], sZM[fl][o], P.umin, P.umax);
-                    Pv = aL + limited_part<T>(gap, da, ik3nu[2]);
-                }
-                sPZ[s3(k + 1)][o] = Pv;
-            });
-        }
-        if (k >= z0 - 1) {
-            const T *h = sH[s6(2 * k + 1)];
-            const int fs = s2(k);
-            box_loop<TX, TY, 1, NT>([&](int u, int v, int) {
-                const int o = u + TX * v;
-                T fH = T(0);
+                            fH += T((oxx == 0 ? 4 : 1) * (oy == 0 ? 4 : 1)) * Ff(2, h[G::hp(2 * u + oxx, 2 * v + oy)]);
+                    fH *= T(1.0 / 36.0);
+                    const T fL = sZL[fs][o];
+                    if (use_si) {
+                        T e = sEZ[s3(k)][u + G::EZW * v] * sEZ[s3(k + 1)][u + G::EZW * v];
+                        e *= e;
+                        const T th = e * e;
+                        fH = th * fH + (T(1) - th) * fL;
+                    }
+                    T F = fH;
+                    if (lim) {
+                        const T df = fH - fL;
+                        const T gap = gap2<T>(df, sZM[fs][o], sZP[fs][o], P.umin, P.umax);
+                        F = fL + limited_part<T>(gap, df, ik3mu[2]);
+                    }
+                    sFZ[fs][o] = F;
+                }));
+            box_merge<NT>(
+                // x-faces: left cell u in [-2, TX], v in [0, TY)
+                mseg<G::FXW, TY>(k >= z0, [&](int x, int v) {
+                    const int u = x - 2, fi = x + G::FXW * v;
+                    const T ua = ubk[G::ub(u, v)], ubb = ubk[G::ub(u + 1, v)];
+                    const T fa = Ff(0, ua), fb = Ff(0, ubb);
+                    const T al = fmax(Fg(0, ua), Fg(0, ubb));
+                    const T fL = T(0.5) * (fa + fb) - T(0.5) * al * (ubb - ua);
+                    T up = T(0), um = T(0);
+                    if constexpr (LIM) {
+                        const T dA = (P.a(ubb) - P.a(ua)) * idx1[0];
+                        const T Km = K * mu[0];
+                        up = ua - Km * (fL - fa) + Km * dA;
+                        um = ubb - Km * (fb - fL) - Km * dA;
+                        sXP[fi] = up;
+                        sXM[fi] = um;
+                    }
+                    if (u < -1 || u > TX - 1) return;
+                    // Simpson average of f_x over the face (points 2u+1, 2v + oy, 2k + oz)
+                    const int pf = 2 * u + 1;
+                    T fH = T(0);
 #pragma unroll
-                for (int oy = -1; oy <= 1; oy++)
+                    for (int oy = -1; oy <= 1; oy++) {
+                        const int i = G::hp(pf, 2 * v + oy);
+                        const T wy = T(oy == 0 ? 4 : 1);
+                        fH += wy * (Ff(0, hm[i]) + T(4) * Ff(0, h0[i]) + Ff(0, hq[i]));
+                    }
+                    fH *= T(1.0 / 36.0);
+                    if (use_si) {
+                        const T *ex = sEX[s2(k)];
+                        T e = ex[(u + 1) + G::EXW * v] * ex[(u + 2) + G::EXW * v];
+                        e *= e;
+                        const T th = e * e;
+                        fH = th * fH + (T(1) - th) * fL;
+                    }
+                    T F = fH;
+                    if (lim) {
+                        const T df = fH - fL;
+                        F = fL + limited_part<T>(gap2<T>(df, um, up, P.umin, P.umax), df, ik3mu[0]);
+                    }
+                    sXF[fi] = F;
+                }));
+            box_merge<NT>(
+                // y-faces: lower cell v in [-2, TY], u in [0, TX)
+                mseg<TX, TY + 3>(k >= z0, [&](int u, int y) {
+                    const int v = y - 2, fi = u + G::FYW * y;
+                    const T ua = ubk[G::ub(u, v)], ubb = ubk[G::ub(u, v + 1)];
+                    const T fa = Ff(1, ua), fb = Ff(1, ubb);
+                    const T al = fmax(Fg(1, ua), Fg(1, ubb));
+                    const T fL = T(0.5) * (fa + fb) - T(0.5) * al * (ubb - ua);
+                    T up = T(0), um = T(0);
+                    if constexpr (LIM) {
+                        const T dA = (P.a(ubb) - P.a(ua)) * idx1[1];
+                        const T Km = K * mu[1];
+                        up = ua - Km * (fL - fa) + Km * dA;
+                        um = ubb - Km * (fb - fL) - Km * dA;
+                        sYP[fi] = up;
+                        sYM[fi] = um;
+                    }
+                    if (v < -1 || v > TY - 1) return;
+                    const int qf = 2 * v + 1;
+                    T fH = T(0);
 #pragma unroll
-                    for (int oxx = -1; oxx <= 1; oxx++)
-                        fH += T((oxx == 0 ? 4 : 1) * (oy == 0 ? 4 : 1)) * Ff(2, h[G::hp(2 * u + oxx, 2 * v + oy)]);
-                fH *= T(1.0 / 36.0);
-                const T fL = sZL[fs][o];
-                if (use_si) {
-                    T e = sEZ[s3(k)][u + G::EZW * v] * sEZ[s3(k + 1)][u + G::EZW * v];
-                    e *= e;
-                    const T th = e * e;
-                    fH = th * fH + (T(1) - th) * fL;
-                }
-                T F = fH;
-                if (lim) {
-                    const T df = fH - fL;
-                    const T gap = gap2<T>(df, sZM[fs][o], sZP[fs][o], P.umin, P.umax);
-                    F = fL + limited_part<T>(gap, df, ik3mu[2]);
-                }
-                sFZ[fs][o] = F;
-            });
-        }
-        if (k >= z0) {
-            const T *ubk = sUB[s4(k)];
-            const T *hm = sH[s6(2 * k - 1)], *h0 = sH[s6(2 * k)], *hq = sH[s6(2 * k + 1)];
-            // x-faces: left cell u in [-2, TX], v in [0, TY)
-            box_loop<G::FXW, TY, 1, NT>([&](int x, int v, int) {
-                const int u = x - 2, fi = x + G::FXW * v;
-                const T ua = ubk[G::ub(u, v)], ubb = ubk[G::ub(u + 1, v)];
-                const T fa = Ff(0, ua), fb = Ff(0, ubb);
-                const T al = fmax(Fg(0, ua), Fg(0, ubb));
-                const T fL = T(0.5) * (fa + fb) - T(0.5) * al * (ubb - ua);
-                T up = T(0), um = T(0);
-                if constexpr (LIM) {
-                    const T dA = (P.a(ubb) - P.a(ua)) * idx1[0];
-                    const T Km = K * mu[0];
-                    up = ua - Km * (fL - fa) + Km * dA;
-                    um = ubb - Km * (fb - fL) - Km * dA;
-                    sXP[fi] = up;
-                    sXM[fi] = um;
-                }
-                if (u < -1 || u > TX - 1) return;
-                // Simpson average of f_x over the face (points 2u+1, 2v + oy, 2k + oz)
-                const int pf = 2 * u + 1;
-                T fH = T(0);
-#pragma unroll
-                for (int oy = -1; oy <= 1; oy++) {
-                    const int i = G::hp(pf, 2 * v + oy);
-                    const T wy = T(oy == 0 ? 4 : 1);
-                    fH += wy * (Ff(0, hm[i]) + T(4) * Ff(0, h0[i]) + Ff(0, hq[i]));
-                }
-                fH *= T(1.0 / 36.0);
-                if (use_si) {
-                    const T *ex = sEX[s2(k)];
-                    T e = ex[(u + 1) + G::EXW * v] * ex[(u + 2) + G::EXW * v];
-                    e *= e;
-                    const T th = e * e;
-                    fH = th * fH + (T(1) - th) * fL;
-                }
-                T F = fH;
-                if (lim) {
-                    const T df = fH - fL;
-                    F = fL + limited_part<T>(gap2<T>(df, um, up, P.umin, P.umax), df, ik3mu[0]);
-                }
-                sXF[fi] = F;
-            });
-            // y-faces: lower cell v in [-2, TY], u in [0, TX)
-            box_loop<TX, TY + 3, 1, NT>([&](int u, int y, int) {
-                const int v = y - 2, fi = u + G::FYW * y;
-                const T ua = ubk[G::ub(u, v)], ubb = ubk[G::ub(u, v + 1)];
-                const T fa = Ff(1, ua), fb = Ff(1, ubb);
-                const T al = fmax(Fg(1, ua), Fg(1, ubb));
-                const T fL = T(0.5) * (fa + fb) - T(0.5) * al * (ubb - ua);
-                T up = T(0), um = T(0);
-                if constexpr (LIM) {
-                    const T dA = (P.a(ubb) - P.a(ua)) * idx1[1];
-                    const T Km = K * mu[1];
-                    up = ua - Km * (fL - fa) + Km * dA;
-                    um = ubb - Km * (fb - fL) - Km * dA;
-                    sYP[fi] = up;
-                    sYM[fi] = um;
-                }
-                if (v < -1 || v > TY - 1) return;
-                const int qf = 2 * v + 1;
-                T fH = T(0);
-#pragma unroll
-                for (int oxx = -1; oxx <= 1; oxx++) {
-                    const int i = G::hp(2 * u + oxx, qf);
-                    const T wx = T(oxx == 0 ? 4 : 1);
-                    fH += wx * (Ff(1, hm[i]) + T(4) * Ff(1, h0[i]) + Ff(1, hq[i]));
-                }
-                fH *= T(1.0 / 36.0);
-                if (use_si) {
-                    const T *ey = sEY[s2(k)];
-                    T e = ey[u + G::EYW * (v + 1)] * ey[u + G::EYW * (v + 2)];
-                    e *= e;
-                    const T th = e * e;
-                    fH = th * fH + (T(1) - th) * fL;
-                }
-                T F = fH;
-                if (lim) {
-                    const T df = fH - fL;
-                    F = fL + limited_part<T>(gap2<T>(df, um, up, P.umin, P.umax), df, ik3mu[1]);
-                }
-                sYF[fi] = F;
-            });
+                    for (int oxx = -1; oxx <= 1; oxx++) {
+                        const int i = G::hp(2 * u + oxx, qf);
+                        const T wx = T(oxx == 0 ? 4 : 1);
+                        fH += wx * (Ff(1, hm[i]) + T(4) * Ff(1, h0[i]) + Ff(1, hq[i]));
+                    }
+                    fH *= T(1.0 / 36.0);
+                    if (use_si) {
+                        const T *ey = sEY[s2(k)];
+                        T e = ey[u + G::EYW * (v + 1)] * ey[u + G::EYW * (v + 2)];
+                        e *= e;
+                        const T th = e * e;
+                        fH = th * fH + (T(1) - th) * fL;
+                    }
+                    T F = fH;
+                    if (lim) {
+                        const T df = fH - fL;
+                        F = fL + limited_part<T>(gap2<T>(df, um, up, P.umin, P.umax), df, ik3mu[1]);
+                    }
+                    sYF[fi] = F;
+                }));
         }
         __syncthreads();
 
