@@ -256,6 +256,9 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
     // blend with X0 = 0 (empty range above) and w = 1, exactly v
     const T wb = p.mode == kCombFE ? T(1) : p.w;
     const bool summing = p.mode == kCombSum;
+    // a forward-Euler stage stores its (clamped) result as it is: the blend
+    // and the second clamp are skipped (a uniform branch)
+    const bool fe = p.mode == kCombFE;
     // (X1 of DoF kind z at global cell gi is read here, by summing stages)
     auto combine = [&](T v, T x0, int z, unsigned gi, T vin) -> T {
         if (summing) return ((p.c0 * x0 + p.c1 * ld(rx1, z, gi)) + p.cin * vin) + p.w * v;
@@ -516,8 +519,10 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
                 }
                 if (!isfinite(v)) bad = true;
                 if constexpr (LIM) v = clampb(v, umin, umaxv);
-                v = combine(v, unv[c][z], z, gi, vin);
-                if constexpr (LIM) v = clampb(v, umin, umaxv);
+                if (!fe) {
+                    v = combine(v, unv[c][z], z, gi, vin);
+                    if constexpr (LIM) v = clampb(v, umin, umaxv);
+                }
                 st(z, gi, v);
             }
         };
@@ -714,11 +719,13 @@ __global__ void __launch_bounds__(NT) stage2o_kernel(StageParams<T> p)
             clamp_mag = fmax(clamp_mag, (T)fabs(cl - v));
             v = cl;
         }
-        v = combine(v, unv[c][0], 0, gi, u);
-        if constexpr (LIM) {
-            const T cl = clampb(v, umin, umaxv);
-            clamp_mag = fmax(clamp_mag, (T)fabs(cl - v));
-            v = cl;
+        if (!fe) {
+            v = combine(v, unv[c][0], 0, gi, u);
+            if constexpr (LIM) {
+                const T cl = clampb(v, umin, umaxv);
+                clamp_mag = fmax(clamp_mag, (T)fabs(cl - v));
+                v = cl;
+            }
         }
         vlo = fmin(vlo, v);
         vhi = fmax(vhi, v);
