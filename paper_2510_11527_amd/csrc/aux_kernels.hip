@@ -383,7 +383,7 @@ hipError_t finalize_launch(int n_inst, const InstDev *inst, const StepCtl *ctl, 
                            int dim, int prec, const unsigned long long *mm, const unsigned long long *wslots,
                            int waves_per_block, long long max_slots, hipStream_t s)
 {
-    if (max_slots > 16384)
+    if (max_slots > 4096)
         hipLaunchKernelGGL(finalize_kernel<1024>, dim3(n_inst), dim3(1024), 0, s, inst, ctl, dtp, st, dim, prec, mm,
                            wslots, waves_per_block);
     else
