@@ -261,6 +261,45 @@ def test_tile_variants_agree(d, fl, n):
     ctx.close()
 
 
+@pytest.mark.parametrize("d,prec", [(1, 64), (3, 32)])
+def test_every_tile_variant_ssprk54_matches_oracle(d, prec):
+    """Three SSP-RK(5,4) steps on every tile variant built for the problem --
+    a forward-Euler stage, blending stages and the summing last stage, whose
+    combinations read U^n prefetched by the kernels and X1 in their summing
+    branch -- against the oracle with its CFL steps prescribed.  3D: 20 cells
+    per axis give every marching tile ragged x and y edges and a walk shorter
+    than the tile's; limiter and blending on."""
+    if d == 1:
+        spec = small_spec(1, 700, FLUXES[0], DIFFS[1], limiter=True, precision=prec)
+        rng = np.random.default_rng(5401)
+        U = state_for(spec, rng)
+    else:
+        spec, U = W.config5(n=20)
+    s, U = prepare(spec, U, prec)
+    P = oracle.problem(s)
+    Uo, t, dts = oracle.run(P, U, nsteps=3, cfl=s["cfl"], integrator="ssprk54")
+    ctx = af.Context(s, integrator="ssprk54")
+    nv = ctx.num_variants()
+    names = [ctx.variant_name(v) for v in range(nv)]
+    ctx.close()
+    ran = 0
+    for v in range(nv):
+        ctx = af.Context(s, integrator="ssprk54")
+        try:
+            ctx.set_variant(v)
+        except af.AFError as e:
+            assert e.status == af.AF_ERR_UNSUPPORTED
+            ctx.close()
+            continue
+        ctx.close()
+        note("ssprk54 every variant d=%d prec=%d %s n=%s" % (d, prec, names[v], s["n"]))
+        V, tg, used, nrm = gpu_run(s, U, dts=dts, integrator="ssprk54", variant=v)
+        check(V, Uo, prec, 5 * len(dts), "ssprk54 variant " + names[v])
+        assert min(x.min() for x in V) >= s["umin"] and max(x.max() for x in V) <= s["umax"]
+        ran += 1
+    assert ran >= 3
+
+
 @pytest.mark.parametrize("case", ["c4", "c5"])
 def test_autotune_selects_a_built_variant_and_leaves_the_solution(case):
     """af_autotune times every built tile variant, keeps one within 3% of
