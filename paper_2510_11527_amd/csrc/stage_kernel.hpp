@@ -460,11 +460,14 @@ __device__ __forceinline__ void atomic_max_wave_t(unsigned long long *dst, T v)
     }
 }
 
-// a(u) is staged per half-grid point (more LDS, fewer evaluations)
+// a(u) is staged per half-grid point (more LDS, fewer evaluations) in 2D
+// and 3D; 1D tiles evaluate it where it is used, which keeps their LDS
+// under 32 KB (five workgroups per CU instead of four; the App. A form
+// reads kappa, not a, anyway)
 template <int D>
 constexpr bool stage_staged_a()
 {
-    return true;
+    return D >= 2;
 }
 
 // elements of the shared face arrays (fluxes, and u^{L,+-} when limiting) or
