@@ -81,7 +81,7 @@ template <class T, bool LIM, bool SI, int TX, int TY>
 constexpr long stage3m_lds_bytes()
 {
     using G = MGeo<TX, TY, SI>;
-    long n = 4L * G::NUB + 12L * G::NHP;
+    long n = 8L * G::NUB + 12L * G::NHP;
     n += 3L * 2 * G::NOWN + 3L * G::NOWN + 2L * G::NOWN;                   // z-faces, P_z, F_z
     n += (long)G::FXN * (LIM ? 3 : 1) + (long)G::FYN * (LIM ? 3 : 1) + G::PXN + G::PYN;
     if (SI) n += 2L * G::EXN + 2L * G::EYN + 3L * G::EZN + 3L * G::EZN + G::TXN + G::TYN;
@@ -178,6 +178,7 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
     constexpr int HZ = G::HZ;
 
     __shared__ T sUB[4][G::NUB];   // averages of planes k .. k+3 (slot: plane & 3)
+    __shared__ T sAU[4][G::NUB];   // a(u) of those averages (evaluated once, at the commit)
     __shared__ T sH[6][G::NHP];    // half planes 2k-2 .. 2k+3 (slot: half plane % 6)
     __shared__ T sA[6][G::NHP];    // a(u) at the same points
     __shared__ T sZL[2][G::NOWN], sZP[2][G::NOWN], sZM[2][G::NOWN];  // z-faces (slot: face index & 1)
@@ -343,11 +344,14 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
             asm volatile("" : "+v"(v));
             unc[j] = v;
         }
-        T *ubk = sUB[s4(k + 3)];
+        T *ubk = sUB[s4(k + 3)], *auk = sAU[s4(k + 3)];
 #pragma unroll
         for (int i = 0; i < NU; i++) {
             const int idx = tid + i * NT;
-            if (idx < G::NUB) ubk[idx] = pu[i];
+            if (idx < G::NUB) {
+                ubk[idx] = pu[i];
+                auk[idx] = P.a(pu[i]);
+            }
         }
         T *he = sH[s6(2 * k + 2)], *ho = sH[s6(2 * k + 3)];
         T *ae = sA[s6(2 * k + 2)], *ao = sA[s6(2 * k + 3)];
@@ -389,6 +393,7 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
             const T *hm = sH[s6(2 * k + 1)], *hp1 = sH[s6(2 * k + 3)];
             T *hc = sH[s6(2 * k + 2)], *ac = sA[s6(2 * k + 2)];
             const T *ub1 = sUB[s4(k + 1)], *ub2 = sUB[s4(k + 2)], *ub3 = sUB[s4(k + 3)];
+            const T *au1 = sAU[s4(k + 1)], *au2 = sAU[s4(k + 2)];
             T *tz = sTZ[s3(k + 2)];
             const int sl = s2(k + 1);
             // the indicator boxes are empty without blending
@@ -414,17 +419,17 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
                 mseg<G::TXW, (TY + 1) * SIH>(use_si && k >= z0 - 1, [&](int x, int y) {
                     const int u = x - 2, v = y;
                     const T um = ub1[G::ub(u - 1, v)], u0 = ub1[G::ub(u, v)], up = ub1[G::ub(u + 1, v)];
-                    sTX[x + G::TXW * y] = fabs(um - T(2) * u0 + up) / (fabs(um) + T(2) * fabs(u0) + fabs(up) + T(1e-13));
+                    sTX[x + G::TXW * y] = fabs(um - T(2) * u0 + up) * fast_rcp(fabs(um) + T(2) * fabs(u0) + fabs(up) + T(1e-13));
                 }),
                 mseg<TX + 1, (TY + 4) * SIH>(use_si && k >= z0 - 1, [&](int x, int y) {
                     const int u = x, v = y - 2;
                     const T um = ub1[G::ub(u, v - 1)], u0 = ub1[G::ub(u, v)], up = ub1[G::ub(u, v + 1)];
-                    sTY[x + G::TYW * y] = fabs(um - T(2) * u0 + up) / (fabs(um) + T(2) * fabs(u0) + fabs(up) + T(1e-13));
+                    sTY[x + G::TYW * y] = fabs(um - T(2) * u0 + up) * fast_rcp(fabs(um) + T(2) * fabs(u0) + fabs(up) + T(1e-13));
                 }),
                 mseg<TX + 1, (TY + 1) * SIH>(use_si && k >= z0 - 4, [&](int u, int v) {
                     const int i = G::ub(u, v);
                     const T um = ub1[i], u0 = ub2[i], up = ub3[i];
-                    tz[u + G::EZW * v] = fabs(um - T(2) * u0 + up) / (fabs(um) + T(2) * fabs(u0) + fabs(up) + T(1e-13));
+                    tz[u + G::EZW * v] = fabs(um - T(2) * u0 + up) * fast_rcp(fabs(um) + T(2) * fabs(u0) + fabs(up) + T(1e-13));
                 }),
                 // z-face (k+1)+1/2 between planes k+1 and k+2: LLF flux, and with the
                 // limiter u^{L,+} of the lower cell and u^{L,-} of the upper one
@@ -436,7 +441,7 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
                     const T fL = T(0.5) * (fa + fb) - T(0.5) * al * (ubb - ua);
                     sZL[sl][o] = fL;
                     if constexpr (LIM) {
-                        const T dA = (P.a(ubb) - P.a(ua)) * idx1[2];
+                        const T dA = (au2[i] - au1[i]) * idx1[2];
                         const T Km = K * mu[2];
                         sZP[sl][o] = ua - Km * (fL - fa) + Km * dA;
                         sZM[sl][o] = ubb - Km * (fb - fL) - Km * dA;
@@ -476,11 +481,11 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
         // and y-faces too took more registers than two waves per SIMD allow)
         {
             const T *a0 = sA[s6(2 * k + 1)], *a1 = sA[s6(2 * k + 2)], *a2 = sA[s6(2 * k + 3)];
-            const T *ubz = sUB[s4(k + 1)];
+            const T *ubz = sUB[s4(k + 1)], *auz = sAU[s4(k + 1)];
             const int fl = s2(k), fu = s2(k + 1);  // faces (k+1) -+ 1/2
             const T *h = sH[s6(2 * k + 1)];
             const int fs = s2(k);
-            const T *ubk = sUB[s4(k)];
+            const T *ubk = sUB[s4(k)], *auk = sAU[s4(k)];
             const T *hm = sH[s6(2 * k - 1)], *h0 = sH[s6(2 * k)], *hq = sH[s6(2 * k + 1)];
             box_merge<NT>(
                 mseg<TX, TY>(k >= z0 - 2, [&](int u, int v) {
@@ -499,7 +504,7 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
                         sl[oz] = acc;
                     }
                     T aH = (T(8) * sl[1] - sl[0] - sl[2]) * T(1.0 / 216.0);
-                    const T aL = P.a(ubz[G::ub(u, v)]);
+                    const T aL = auz[G::ub(u, v)];
                     if (use_si) {
                         T e = sEZ[s3(k + 1)][u + G::EZW * v];
                         e *= e;
@@ -549,7 +554,7 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
                     const T fL = T(0.5) * (fa + fb) - T(0.5) * al * (ubb - ua);
                     T up = T(0), um = T(0);
                     if constexpr (LIM) {
-                        const T dA = (P.a(ubb) - P.a(ua)) * idx1[0];
+                        const T dA = (auk[G::ub(u + 1, v)] - auk[G::ub(u, v)]) * idx1[0];
                         const T Km = K * mu[0];
                         up = ua - Km * (fL - fa) + Km * dA;
                         um = ubb - Km * (fb - fL) - Km * dA;
@@ -591,7 +596,7 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
                     const T fL = T(0.5) * (fa + fb) - T(0.5) * al * (ubb - ua);
                     T up = T(0), um = T(0);
                     if constexpr (LIM) {
-                        const T dA = (P.a(ubb) - P.a(ua)) * idx1[1];
+                        const T dA = (auk[G::ub(u, v + 1)] - auk[G::ub(u, v)]) * idx1[1];
                         const T Km = K * mu[1];
                         up = ua - Km * (fL - fa) + Km * dA;
                         um = ubb - Km * (fb - fL) - Km * dA;
@@ -627,7 +632,7 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
 
         // ---- 5: x- and y-potentials of plane k
         if (k >= z0) {
-            const T *ubk = sUB[s4(k)];
+            const T *auk = sAU[s4(k)];
             const T *am = sA[s6(2 * k - 1)], *a0 = sA[s6(2 * k)], *aq = sA[s6(2 * k + 1)];
             // x: cells u in [-1, TX], v in [0, TY)
             box_loop<G::PXW, TY, 1, NT>([&](int x, int v, int) {
@@ -642,7 +647,7 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
                         aH += w * (am[i] + T(4) * a0[i] + aq[i]);
                     }
                 aH *= T(1.0 / 216.0);
-                const T aL = P.a(ubk[G::ub(u, v)]);
+                const T aL = auk[G::ub(u, v)];
                 if (use_si) {
                     T e = sEX[s2(k)][x + G::EXW * v];
                     e *= e;
@@ -673,7 +678,7 @@ __global__ void __launch_bounds__(NT) stage3m_kernel(StageParams<T> p)
                         aH += w * (am[i] + T(4) * a0[i] + aq[i]);
                     }
                 aH *= T(1.0 / 216.0);
-                const T aL = P.a(ubk[G::ub(u, v)]);
+                const T aL = auk[G::ub(u, v)];
                 if (use_si) {
                     T e = sEY[s2(k)][u + G::EYW * y];
                     e *= e;
