@@ -25,6 +25,7 @@ import pytest
 
 import bench
 import oracle
+from paper_2510_11527_amd import af
 from gpu_common import TOL, abs_bound, check
 
 pytestmark = pytest.mark.gpu
@@ -73,10 +74,27 @@ def sample_cells(spec, U, tile, rng, nrand):
 
 @pytest.mark.parametrize("wl", WORKLOADS)
 def test_full_size_forward_euler_stage_matches_oracle_on_sampled_cells(wl):
+    fe_sampled(wl)
+
+
+@pytest.mark.parametrize("tile", ["3d-march-8x8x32", "3d-march-16x8x256"])
+def test_full_size_3d_stage_on_the_autotuned_tiles(tile):
+    """The 3D workload at full size on the marching tiles the autotuner
+    chooses between (bench.py times whichever it picks), sampled cells
+    against the oracle."""
+    fe_sampled("c5", tile)
+
+
+def fe_sampled(wl, tile_name=None):
     name, items = bench.workload(wl)
     prec = items[0][0]["precision"]
     d = items[0][0]["dim"]
-    ctx = bench.make_ctx(items, integrator="euler")
+    variant = None
+    if tile_name is not None:
+        probe = af.Context(items[0][0])
+        variant = [probe.variant_name(v) for v in range(probe.num_variants())].index(tile_name)
+        probe.close()
+    ctx = bench.make_ctx(items, integrator="euler", variant=variant)
     vname = ctx.variant_name(ctx.variant())
     tile = tile_of(vname, d)
     note("full-size fe %s (%d instances, variant %s)" % (name, len(items), vname))
