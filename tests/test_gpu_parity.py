@@ -508,6 +508,56 @@ def test_batched_instances_match_oracle():
     ctx.close()
 
 
+def _end_time_batch(kind):
+    """Instances of different sizes (so different CFL steps) for one context."""
+    if kind == "2d":  # batched porous-medium / Burgers instances, FP32
+        return W.config4(n_inst=3, sizes=(16, 24, 40))
+    if kind == "3d":  # degenerate 3D with blending, FP32
+        return [W.config5(n=12), W.config5(n=20)]
+    # App. A batch, FP64
+    return W.config_nodc(n_inst=2, n=64) + W.config_nodc(seed=7, n_inst=1, n=160)
+
+
+@pytest.mark.parametrize("kind,tile", [("2d", "2d-own-32x16"), ("2d", "generic-32x8"), ("3d", "3d-march-16x8x32"),
+                                       ("3d", "generic-8x8x8"), ("1d", "generic-512")])
+def test_instances_reaching_the_end_time_at_different_steps(kind, tile):
+    """Stepping to a common end time, the instances of one context with
+    larger CFL steps finish first; from then on the finalize gives them a
+    zero step and every stage must leave them unchanged while the others go
+    on.  Each instance against the oracle replaying its own nonzero steps,
+    the time reached and the number of steps it took."""
+    items = _end_time_batch(kind)
+    specs = [s for s, _ in items]
+    prec = specs[0]["precision"]
+    dt0 = [oracle.dt_cfl(oracle.problem(s), U, s["cfl"]) for s, U in items]
+    T = 3.5 * max(dt0)
+    ctx = af.Context(specs)
+    ctx.set_variant([ctx.variant_name(v) for v in range(ctx.num_variants())].index(tile))
+    for i, (_, U) in enumerate(items):
+        ctx.set_state(i, U)
+    dts = []
+    while len(dts) < 200:
+        d = ctx.step(1, t_end=T)
+        if not np.any(d > 0):
+            break
+        dts.append(d)
+    dts = np.array(dts)
+    taken = (dts > 0).sum(axis=0)
+    note("end time %s %s: steps per instance %s" % (kind, tile, taken.tolist()))
+    # some instance finished at least two steps before the last one
+    assert taken.max() - taken.min() >= 2
+    for i, (s, U) in enumerate(items):
+        V, t = ctx.get_state(i)
+        assert ctx.norms(i)["steps"] == taken[i]
+        assert abs(t - T) <= 1e-12 * T
+        # zero steps only after the instance's last step
+        assert np.all(dts[: taken[i], i] > 0) and np.all(dts[taken[i]:, i] == 0)
+        Uo, to, _ = oracle.run(oracle.problem(s), U, dts=list(dts[: taken[i], i]))
+        assert abs(to - T) <= 1e-12 * T
+        check(V, Uo, prec, 3 * int(taken[i]), "%s instance %d (%d steps)" % (kind, i, taken[i]))
+    ctx.close()
+
+
 def test_conservation_and_bounds_long_run():
     spec, U = W.config2(n=96)
     ctx = af.Context(spec)
