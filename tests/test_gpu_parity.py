@@ -80,6 +80,46 @@ def test_forward_euler_stage_matches_oracle(d, prec, lim, si):
             assert min(v.min() for v in V) >= s["umin"] and max(v.max() for v in V) <= s["umax"]
 
 
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("gamma", [0.25, 6.0])
+def test_si_blending_strength_matches_oracle(d, prec, gamma):
+    """Blending with gamma other than 1 (every other test uses 1, where a
+    kernel that dropped gamma would still agree): one forward-Euler stage
+    with the limiter, on rough random and smooth data, so that the weights
+    exp(-gamma s) take intermediate values; in 3D on the marching and the
+    generic kernel.  On the rough data the oracle's result at this gamma
+    must differ from its result at gamma = 1 by far more than the tolerance
+    (on smooth data s is small and the weights stay near 1 for any gamma)."""
+    rng = np.random.default_rng(1000 * d + prec + int(4 * gamma))
+    n = {1: 41, 2: 19, 3: 9}[d]
+    tiles = ["3d-march-16x8x32", "generic-8x8x4"] if d == 3 else [None]
+    for k in range(2):
+        fl, df = FLUXES[(k + d) % 4] if d < 3 else FLUXES[3 * k % 4], DIFFS[(k + 2 * d) % 5]
+        spec = small_spec(d, n, fl, df, limiter=True, si=True, precision=prec)
+        spec["si_gamma"] = gamma
+        U = state_for(spec, rng, smooth=(k == 1))
+        s, U = prepare(spec, U, prec)
+        P = oracle.problem(s)
+        dt = oracle.dt_cfl(P, U, s["cfl"])
+        Vo, _ = oracle.fe(P, U, dt)
+        Vo1, _ = oracle.fe(oracle.problem(dict(s, si_gamma=1.0)), U, dt)
+        sep = rel_l1(Vo, Vo1)
+        if k == 0:
+            assert sep > 100 * TOL[prec], ("gamma has no effect on this case", sep)
+        for tile in tiles:
+            variant = None
+            if tile is not None:
+                probe = af.Context(s)
+                variant = [probe.variant_name(v) for v in range(probe.num_variants())].index(tile)
+                probe.close()
+            note("si gamma=%g d=%d prec=%d flux=%s diff=%s tile=%s: oracle gamma vs 1 rel_l1 %.2e"
+                 % (gamma, d, prec, fl[0], df[0], tile, sep))
+            V, _, _, _ = gpu_run(s, U, dts=[dt], integrator="euler", variant=variant)
+            check(V, Vo, prec, 1, "si gamma %g" % gamma)
+            assert min(v.min() for v in V) >= s["umin"] and max(v.max() for v in V) <= s["umax"]
+
+
 def _steps_case(name):
     if name == "c2":
         spec, U = W.config2(n=48)
