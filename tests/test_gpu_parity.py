@@ -120,6 +120,49 @@ def test_si_blending_strength_matches_oracle(d, prec, gamma):
             assert min(v.min() for v in V) >= s["umin"] and max(v.max() for v in V) <= s["umax"]
 
 
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("si", [False, True])
+def test_limiter_with_bounds_around_zero(d, prec, si):
+    """MPP bounds [-1, 1] (every other small case uses [0, 1], where a clamp
+    or gap that took 0 for umin would agree): Burgers (f' changes sign
+    inside the bounds) with linear diffusion and a linear flux against the
+    grid with a dead-zone potential whose threshold is negative, on rough
+    data with values at both bounds.  One forward-Euler stage; the unlimited
+    oracle goes below -1, the limited GPU result matches
+    the oracle and stays inside exactly; in 3D on the marching and the
+    generic kernel."""
+    n = {1: 41, 2: 19, 3: 9}[d]
+    tiles = ["3d-march-16x8x32", "generic-8x8x4"] if d == 3 else [None]
+    for k in range(2):
+        fl = [("quad", 0.5, 0.0), ("linear", -0.7, 0.0)][k]
+        df = [("linear", 0.02, 0), ("deadzone", 0.05, -0.25)][k]
+        spec = dict(name="t", dim=d, n=[n + l for l in range(d)], lo=[0.0] * d, hi=[1.0 + 0.1 * l for l in range(d)],
+                    flux=[fl] * d, diff=df, umin=-1.0, umax=1.0, limiter=True, si=si, si_gamma=1.0,
+                    precision=prec, cfl=0.3 / (2 * d))
+        rng = np.random.default_rng(50 * d + k + 5 * si + prec)
+        N = int(np.prod(spec["n"]))
+        U = [rng.uniform(-1, 1, size=N) for _ in range(2 ** d)]
+        U[0] = np.where(rng.uniform(size=N) < 0.6, U[0], rng.choice([-1.0, 1.0], size=N))
+        s, U = prepare(spec, U, prec)
+        assert s["umin"] == -1.0 and s["umax"] == 1.0
+        P = oracle.problem(s)
+        dt = oracle.dt_cfl(P, U, s["cfl"])
+        Vo, _ = oracle.fe(P, U, dt)
+        Vu, _ = oracle.fe(oracle.problem(dict(s, limiter=False)), U, dt)
+        assert min(v.min() for v in Vu) < -1.0 - 1e-3  # the limiter works at the negative bound
+        for tile in tiles:
+            variant = None
+            if tile is not None:
+                probe = af.Context(s)
+                variant = [probe.variant_name(v) for v in range(probe.num_variants())].index(tile)
+                probe.close()
+            note("bounds [-1, 1] d=%d prec=%d si=%d flux=%s diff=%s tile=%s" % (d, prec, si, fl[0], df[0], tile))
+            V, _, _, _ = gpu_run(s, U, dts=[dt], integrator="euler", variant=variant)
+            check(V, Vo, prec, 1, "bounds [-1, 1]")
+            assert min(v.min() for v in V) >= -1.0 and max(v.max() for v in V) <= 1.0
+
+
 def _steps_case(name):
     if name == "c2":
         spec, U = W.config2(n=48)
