@@ -209,6 +209,53 @@ def test_different_flux_per_axis_matches_oracle(d, prec, lim):
             assert min(v.min() for v in V) >= s["umin"] and max(v.max() for v in V) <= s["umax"]
 
 
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("prec", [64, 32])
+def test_instances_of_different_physics_in_one_context(d, prec):
+    """One context holding instances with different flux and potential kinds
+    (Burgers with a power law, Buckley-Leverett with its own potential, a
+    linear flux with a dead zone, a linear flux along the grid with linear
+    diffusion), of different sizes: three SSP-RK3 steps with the GPU's own
+    CFL steps, each instance against the oracle replaying its steps.  Every
+    tile variant that takes the mix."""
+    n0 = {1: 41, 2: 17, 3: 9}[d]
+    phys = [(("quad", 0.5, 0.0), ("power", 0.05, 2.0)), (("bl", 0.0, 0.0), ("bl", 0.01, 0.0)),
+            (("linear", -0.7, 0.0), ("deadzone", 0.05, 0.25)), (("linear", 0.4, 0.0), ("linear", 0.02, 0))]
+    rng = np.random.default_rng(90 * d + prec)
+    items = []
+    for i, (fl, df) in enumerate(phys):
+        spec = small_spec(d, n0 + 3 * i, fl, df, limiter=True, si=(d != 2), precision=prec)
+        U = state_for(spec, rng, smooth=(i % 2 == 1))
+        items.append(prepare(spec, U, prec))
+    specs = [s for s, _ in items]
+    probe = af.Context(specs)
+    names = [probe.variant_name(v) for v in range(probe.num_variants())]
+    probe.close()
+    ran = 0
+    for v, name in enumerate(names):
+        ctx = af.Context(specs)
+        try:
+            ctx.set_variant(v)
+        except af.AFError as e:
+            ctx.close()
+            assert e.status == af.AF_ERR_UNSUPPORTED
+            continue
+        for i, (_, U) in enumerate(items):
+            ctx.set_state(i, U)
+        dts = [ctx.step(1) for _ in range(3)]
+        note("mixed physics d=%d prec=%d tile=%s dt %s" % (d, prec, name, np.round(dts[0], 8).tolist()))
+        for i, (s, U) in enumerate(items):
+            V, _ = ctx.get_state(i)
+            P = oracle.problem(s)
+            assert abs(dts[0][i] - oracle.dt_cfl(P, U, s["cfl"])) <= (1e-15 if prec == 64 else 1e-6) * dts[0][i]
+            Uo, _, _ = oracle.run(P, U, dts=[x[i] for x in dts])
+            check(V, Uo, prec, 9, "mixed physics %s instance %d" % (name, i))
+            assert min(x.min() for x in V) >= s["umin"] and max(x.max() for x in V) <= s["umax"]
+        ctx.close()
+        ran += 1
+    assert ran >= 1
+
+
 def _steps_case(name):
     if name == "c2":
         spec, U = W.config2(n=48)
