@@ -32,11 +32,14 @@ def log(*a):
 
 
 def kernel_source_sha():
-    """Hash of the HIP sources; a traffic figure measured with other sources
-    is stale and not reported."""
+    """Hash of the HIP sources and the build script (its compiler flags); a
+    traffic figure measured with other sources or flags is stale and not
+    reported."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2510_11527_amd", "csrc", "*"))):
-        if f.endswith((".hpp", ".hip", ".h", ".cpp")):
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2510_11527_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "paper_2510_11527_amd", "build.py"))
+    for f in files:
+        if f.endswith((".hpp", ".hip", ".h", ".cpp", ".py")):
             h.update(os.path.basename(f).encode())
             with open(f, "rb") as fh:
                 h.update(fh.read())
