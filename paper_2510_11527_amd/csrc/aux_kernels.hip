@@ -69,9 +69,8 @@ __global__ void __launch_bounds__(kWaveThreads) wavespeed_kernel(const InstDev *
     bool bad = false;
     const int width = wc.i1 - wc.i0;
     const int ncells = width * (wc.r1 - wc.r0);
-    for (int q = (int)threadIdx.x; q < ncells; q += kWaveThreads) {
-        const int r = wc.r0 + q / width, i = wc.i0 + q % width;
-        const int j = r % n1, k = r / n1;
+    // the cell at row r (j, k: its y and z indices), column i
+    auto cell = [&](int r, int i, int j, int k) {
         const long long row = (long long)n0 * r;
         // every load of the cell first
         const double uc = (double)u[row + i];
@@ -107,6 +106,18 @@ __global__ void __launch_bounds__(kWaveThreads) wavespeed_kernel(const InstDev *
             w = face(1, uc, uy, gy, w);
         }
         if constexpr (D >= 3) w = face(2, uc, uz, false, w);
+    };
+    // a chunk within one row (rows longer than a chunk, the usual case on
+    // large grids) takes its row indices once per block, so its loop has no
+    // integer division per cell
+    if (wc.r1 - wc.r0 == 1) {
+        const int j = wc.r0 % n1, k = wc.r0 / n1;
+        for (int q = (int)threadIdx.x; q < width; q += kWaveThreads) cell(wc.r0, wc.i0 + q, j, k);
+    } else {
+        for (int q = (int)threadIdx.x; q < ncells; q += kWaveThreads) {
+            const int r = wc.r0 + q / width;
+            cell(r, wc.i0 + q % width, r % n1, r / n1);
+        }
     }
     // the waves' maxima meet in LDS, then the block's goes to its slot
     constexpr int NW = kWaveThreads / 64;

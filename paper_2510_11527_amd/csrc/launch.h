@@ -42,7 +42,7 @@ hipError_t stage_launch_d3(int prec, bool lim, bool si, unsigned caps, int varia
 // FP64 max over faces of alpha_l/dx_l + kappa_max/dx_l^2 of the averages of
 // U, one slot per chunk (the bits of the chunk's max), plus the divergence
 // check.
-constexpr int kWaveChunk = 512;   // cells per wave-speed block (about)
+constexpr int kWaveChunk = 1024;  // cells per wave-speed block (about)
 constexpr int kWaveThreads = 256;  // threads per wave-speed block (four waves)
 // Cells of wave-speed chunk k of an instance whose rows hold n0 cells
 // (nrows rows): whole rows [r0, r1) when a row holds at most kWaveChunk
