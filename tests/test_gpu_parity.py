@@ -256,6 +256,46 @@ def test_instances_of_different_physics_in_one_context(d, prec):
     assert ran >= 1
 
 
+@pytest.mark.parametrize("d,n", [(1, 3001), (2, 2101)])
+@pytest.mark.parametrize("prec", [64, 32])
+def test_wave_speed_pass_on_rows_longer_than_a_chunk(d, n, prec):
+    """Rows longer than a wave-speed chunk are split into segments, the last
+    one ragged.  Buckley-Leverett fluxes (|f'| not convex: the pass runs
+    every step) on averages in [0, 0.35], where |f'| increases, with the
+    largest averages only in the last cells of a row: the CFL step depends on
+    the ragged segment (without those cells the oracle's step is larger).
+    The step of each of three SSP-RK3 steps against the oracle's for the
+    GPU's state, and the state against the oracle replaying the steps."""
+    fl = ("bl", 0.0, 0.0)
+    spec = small_spec(d, 4, fl, ("bl", 0.01, 0.0), limiter=True, precision=prec)
+    spec["n"] = [n, 4][:d]
+    rng = np.random.default_rng(31 * d + prec)
+    U = [0.3 * u for u in state_for(spec, rng, smooth=True)]
+    U0 = U[0].reshape(spec["n"][::-1])
+    U0[..., -3:] = 0.35  # the tail of every row
+    s, U = prepare(spec, U, prec)
+    P = oracle.problem(s)
+    flat = [u.copy() for u in U]
+    flat[0] = np.asarray(U[0]).reshape(spec["n"][::-1]).copy()
+    flat[0][..., -3:] = 0.3
+    flat[0] = flat[0].reshape(-1)
+    assert oracle.dt_cfl(P, flat, s["cfl"]) > oracle.dt_cfl(P, U, s["cfl"]) * (1 + 1e-6)
+    ctx = af.Context(s)
+    ctx.set_state(0, U)
+    dts = []
+    for k in range(3):
+        Vk, _ = ctx.get_state(0)
+        dto = oracle.dt_cfl(P, Vk, s["cfl"])
+        dtg = ctx.step(1)[0]
+        note("long rows d=%d n=%d prec=%d step %d: dt gpu %.17g oracle %.17g" % (d, n, prec, k, dtg, dto))
+        assert abs(dtg - dto) <= (1e-15 if prec == 64 else 1e-6) * dto
+        dts.append(dtg)
+    V, _ = ctx.get_state(0)
+    ctx.close()
+    Uo, _, _ = oracle.run(P, U, dts=dts)
+    check(V, Uo, prec, 9, "long rows d=%d" % d)
+
+
 def _steps_case(name):
     if name == "c2":
         spec, U = W.config2(n=48)
